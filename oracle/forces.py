@@ -1,0 +1,68 @@
+"""Oracle: force and moment of the oil film on the piston (paper Sec 2.4-III, Eq 2.11).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+The paper integrates "pressure and viscous shear stress" per surface element but gives no
+formulas and no cavitation rule.  Readings taken:
+
+* Cavitation: mode "none" uses p as solved; mode "clamp" uses max(p, p_cav) everywhere
+  below (gradients included).
+* Wall shear on the (stationary) piston surface for a film whose other wall slides at
+  (U, V):  tau_theta = -(h/2) dp/dx + mu U / h,   tau_z = -(h/2) dp/dz + mu V / h,
+  with h at the cell centre.  dp/dx: central difference, periodic; dp/dz: central
+  difference inside, and on the end rows the Dirichlet value at the boundary face,
+  (p_1 - p_in)/(1.5 dz) and (p_out - p_{n-2})/(1.5 dz).
+* Midpoint rule, dA = dx dz, moments about the axis point z_ref = L/2.  With the outward
+  normal (cos, sin, 0) and tangent (-sin, cos, 0) the surface traction is
+  f = (-p cos - tau_theta sin, -p sin + tau_theta cos, tau_z), and
+  (F1, F2, F3, F4) = (Fx, Fy, Mx, My) = (sum f_x dA, sum f_y dA,
+  sum [(z - z_ref)(p sin - tau_theta cos) + tau_z R sin] dA,
+  sum [-(z - z_ref)(p cos + tau_theta sin) - tau_z R cos] dA).
+"""
+
+import numpy as np
+
+from .film import Gap, cell_centers, film, no_texture
+
+
+def effective_pressure(p, mode="none", p_cav=0.0):
+    if mode == "none":
+        return p
+    if mode == "clamp":
+        return np.maximum(p, p_cav)
+    raise ValueError("cavitation mode must be 'none' or 'clamp'")
+
+
+def force_moment(gap: Gap, p, h):
+    """(Fx, Fy, Mx, My) from the cell-centre pressure p and film h, both (n_axial, n_theta)."""
+    nt, nz = gap.n_theta, gap.n_axial
+    p = np.asarray(p).reshape(nz, nt)
+    h = np.asarray(h).reshape(nz, nt)
+    th, z, dth, dz = cell_centers(gap)
+    dx = gap.R * dth
+    dA = dx * dz
+    TH, Z = np.meshgrid(th, z)
+    dpdx = (np.roll(p, -1, axis=1) - np.roll(p, 1, axis=1)) / (2.0 * dx)
+    dpdz = np.zeros_like(p)
+    if nz > 2:
+        dpdz[1:-1, :] = (p[2:, :] - p[:-2, :]) / (2.0 * dz)
+    dpdz[0, :] = (p[1, :] - gap.p_in) / (1.5 * dz)
+    dpdz[-1, :] = (gap.p_out - p[-2, :]) / (1.5 * dz)
+    tau_t = -0.5 * h * dpdx + gap.mu * gap.U / h
+    tau_z = -0.5 * h * dpdz + gap.mu * gap.V / h
+    c, s = np.cos(TH), np.sin(TH)
+    zr = Z - 0.5 * gap.L
+    Fx = np.sum(-p * c - tau_t * s) * dA
+    Fy = np.sum(-p * s + tau_t * c) * dA
+    Mx = np.sum(zr * (p * s - tau_t * c) + tau_z * gap.R * s) * dA
+    My = np.sum(-zr * (p * c + tau_t * s) - tau_z * gap.R * c) * dA
+    return np.array([Fx, Fy, Mx, My])
+
+
+def forces_for_condition(gap: Gap, e, p, texture=no_texture, cavitation="none", p_cav=0.0):
+    """Forces of one solved condition: film at the cell centres, cavitation rule, integrals."""
+    th, z, _, _ = cell_centers(gap)
+    TH, Z = np.meshgrid(th, z)
+    h = film(gap, e, TH, Z, texture)
+    return force_moment(gap, effective_pressure(np.asarray(p).reshape(gap.n_axial, gap.n_theta),
+                                                cavitation, p_cav), h)
