@@ -1,0 +1,198 @@
+"""Benchmark of the joint 9-condition piston-gap solve on one MI355X.
+
+One step = one pass of the whole hot path on the 2048 x 1024 textured workload (20 x 8
+seeded spherical dimples, 9 working conditions, ~18.9 M unknowns): assemble the joint
+system, ASSOR-PCG to ||r_G|| / ||S_G|| <= 1e-10 with the synchronized test, force and
+moment integration, FD Jacobian.  Inputs are resident in HBM when the timed region starts.
+
+Prints ONE JSON line (value = solves/s).  Extra fields: GDOF-iter/s, the roofline of the
+dominant iteration kernel (its average launch time from HIP events recorded on the
+stream it runs on), the plain one-condition-at-a-time solve of the same 9 conditions,
+and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "9-condition ASSOR-PCG solves/s & GDOF-iter/s at 2048×1024; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(n, n_cond, n_op):
+    """Algorithmic HBM bytes of one launch of each iteration kernel: every vector operand is
+    read or written once per condition-DOF; the face conductances (kx, kz: 16 B per
+    operator-DOF) once per distinct operator."""
+    vec = {"k_spmv_dot": 3, "k_update": 6, "k_assor_lower": 2, "k_assor_upper": 3}
+    return {k: 8 * v * n * n_cond + 16 * n * n_op for k, v in vec.items()}
+
+
+def run_cpu_baseline(case, iterations_gpu, n_cond):
+    """Oracle on a bounded sample: condition 0 of the same input, assembly + 20 PCG
+    iterations (Table 1, ASSOR II) + force integral, scaled to n_cond conditions and the
+    GPU's iteration count.  The oracle is plain NumPy/SciPy on one core."""
+    import numpy as np
+    import oracle
+    gap = oracle.Gap(case.R, case.c, case.L, case.mu, case.U, case.V, case.p_in, case.p_out,
+                     case.n_theta, case.n_axial)
+    tex = oracle.dimple_texture(case.R, case.dimple_theta, case.dimple_z, case.dimple_radius,
+                                case.dimple_depth) if case.n_dimples else oracle.no_texture
+    sample_iters = 20
+    t0 = time.perf_counter()
+    A, S = oracle.assemble(gap, case.e, case.edot, tex)
+    t1 = time.perf_counter()
+    M = oracle.assor2_precond(A, case.omega)
+    p, _, _ = oracle.pcg(A, S, M, 1e-300, sample_iters)
+    t2 = time.perf_counter()
+    oracle.forces_for_condition(gap, case.e, p, tex)
+    t3 = time.perf_counter()
+    per_iter = (t2 - t1) / sample_iters
+    solve_s = n_cond * ((t1 - t0) + iterations_gpu * per_iter + (t3 - t2))
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle on condition 0 of the same input: assembly {t1 - t0:.2f} s, "
+                       f"{sample_iters} ASSOR-II PCG iterations {t2 - t1:.2f} s, forces {t3 - t2:.2f} s; "
+                       f"scaled to {n_cond} conditions x {iterations_gpu} iterations"),
+            "sample_seconds": t3 - t0, "seconds_per_solve": solve_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="joint_textured_2048x1024")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2511_06824_amd import gapsolve as G
+    from paper_2511_06824_amd.solver import JointGapSolver
+
+    case = synth.make_case(args.workload, args.seed)
+    n = case.n
+    n_cond, n_op = 9, 5
+    dev = torch.device("cuda:0")
+    solver = JointGapSolver.from_case(case, max_cond=9, device=dev)
+    opts = solver.options(omega=case.omega, eps=case.eps)
+    print(f"bench: {case.label}, {n_cond} conditions, n = {n}, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        _, _, info = solver.step(case.e, case.edot, case.delta, opts)
+        torch.cuda.synchronize()
+        print(f"bench: warmup {w} iterations {info.iterations}", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream(dev)
+    G.gap_kernel_timing(solver.handle, 1)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        solver.assemble(case.e, case.edot, case.delta, 9)
+        ev[s][1].record(stream)
+        _, info = solver.solve(opts)
+        ev[s][2].record(stream)
+        solver.integrate()
+        solver.jacobian_fd()
+        iters.append(info.iterations)
+        print(f"bench: step {s} iterations {info.iterations} rel {info.rel_residual:.2e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    G.gap_kernel_timing(solver.handle, 0)
+
+    elapsed = t1 - t0
+    t_pcg = sum(ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)) / 1e3
+    mean_iters = sum(iters) / len(iters)
+    gdof = n_cond * n * sum(iters) / t_pcg / 1e9
+
+    stats = {}
+    for k, name in enumerate(G.KERNEL_NAMES):
+        cnt, ms = G.gap_kernel_stats(solver.handle, k)
+        if cnt:
+            stats[name] = {"launches": cnt, "avg_us": 1e3 * ms / cnt, "total_ms": ms}
+    nbytes = kernel_bytes(n, n_cond, n_op)
+    dominant = max((k for k in stats if k in nbytes), key=lambda k: stats[k]["total_ms"])
+    achieved = nbytes[dominant] / (stats[dominant]["avg_us"] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "bytes_per_launch": nbytes[dominant], "avg_launch_us": round(stats[dominant]["avg_us"], 2)}
+
+    plain = None
+    if not args.no_plain:
+        plain = run_plain(case, G, JointGapSolver, dev)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = run_cpu_baseline(case, int(round(mean_iters)), n_cond)
+
+    out = {
+        "metric": METRIC, "value": args.steps / elapsed, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_theta": case.n_theta, "n_axial": case.n_axial,
+                   "n_cond": n_cond, "dimples": case.n_dimples, "omega": case.omega, "eps": case.eps,
+                   "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "seed": args.seed},
+        "gdof_iter_per_s": round(gdof, 3), "iterations": mean_iters,
+        "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
+        "roofline": roofline, "plain_baseline": plain, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+
+
+def run_plain(case, G, JointGapSolver, dev):
+    """The same 9 conditions solved one at a time (sequential GPU acceleration): same
+    kernels, eps and omega, a host read of the residual after every iteration, forces per
+    condition, the FD quotient of Eq 2.13-2.14 on the host."""
+    import numpy as np
+    import torch
+    conds = []
+    for k in range(9):
+        e, ed = np.array(case.e, float), np.array(case.edot, float)
+        if 1 <= k <= 4:
+            e[k - 1] += case.delta[k - 1]
+        elif k >= 5:
+            ed[k - 5] += case.delta[k - 1]
+        conds.append((e, ed))
+    s1 = JointGapSolver.from_case(case, max_cond=1, device=dev)
+    opts = s1.options(omega=case.omega, eps=case.eps, check_every=1)
+    s1.assemble(conds[0][0], conds[0][1], None, 1)
+    s1.solve(opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = np.zeros((9, 4))
+    its = 0
+    for k, (ek, edk) in enumerate(conds):
+        s1.assemble(ek, edk, None, 1)
+        _, info = s1.solve(opts)
+        F[k] = s1.integrate().cpu().numpy()[0]
+        its += info.iterations
+    J = (F[1:] - F[0]).T / np.asarray(case.delta)[None, :]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1.close()
+    assert np.all(np.isfinite(J))
+    print(f"bench: plain one-at-a-time solve {t1 - t0:.2f} s, {its} iterations", file=sys.stderr, flush=True)
+    return {"solves_per_s": 1.0 / (t1 - t0), "seconds_per_solve": t1 - t0, "iterations_total": its,
+            "method": "9 single-condition solves, same kernels, host residual read every iteration"}
+
+
+if __name__ == "__main__":
+    main()

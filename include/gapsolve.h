@@ -1,0 +1,200 @@
+/*
+ * gapsolve.h -- C ABI of the MI355X (gfx950) joint piston-gap Reynolds solver.
+ *
+ * Paper: "A GPU-boosted high-performance multi-working condition joint analysis framework
+ * for predicting dynamics of textured axial piston pump" (arXiv 2511.06824).
+ *
+ * The library computes, on one GPU and in FP64 throughout, the hot path of the paper's
+ * framework (Sec 3.2, steps I-IV):
+ *   I.   assemble the 5-point finite-volume system A_k p_k = S_k of every working condition
+ *        k = 0..8 (Eq 2.1, 2.4-2.7, 2.17-2.19) from the film thickness of Eq 2.3;
+ *   II.  solve the block-diagonal joint system A_G p_G = S_G (Eq 3.7-3.8) by the adjusted
+ *        PCG of Table 1 with the ASSOR preconditioner (Eq 3.3-3.6) and the synchronized
+ *        global stopping test of Eq 3.9;
+ *   III. integrate pressure and viscous-shear force and moment per condition (Sec 2.4-III);
+ *   IV.  form the double Jacobian of Eq 2.13-2.14 by forward differences.
+ *
+ * Conventions shared by every entry point
+ *   - Units are SI.  All floating point is IEEE double.
+ *   - Grid: n_theta cells around the circumference (periodic, fastest index) by n_axial
+ *     cells along the gap; cell (i, j) has centre theta_i = (i + 1/2) 2 pi / n_theta,
+ *     z_j = (j + 1/2) L / n_axial.  A field of one condition is n = n_theta * n_axial
+ *     doubles, element i + j * n_theta.  Fields of several conditions are stored
+ *     condition-major: element i + j * n_theta + k * n (Eq 3.8).
+ *   - Condition k (Eq 2.17-2.19): k = 0 is (e, edot); k = 1..4 adds delta[k-1] to e_k;
+ *     k = 5..8 adds delta[k-1] to edot_{k-4}.
+ *   - Device pointers are HIP device allocations owned by the caller (for instance the
+ *     storage of a torch tensor); the library never frees them.  Host pointers are
+ *     read during the call only.  A handle owns its internal device buffers until
+ *     destroy_gap_grid.
+ *   - stream is a hipStream_t passed as void* (NULL: the legacy default stream).  Calls
+ *     are ordered on that stream; solve_joint_pcg synchronizes it (it reads the device
+ *     convergence flag), the other calls return before the device work completes.
+ *   - A handle is not thread-safe; use one handle per host thread and stream.
+ *   - No exception crosses the ABI.  Each call returns a gap_status; on failure
+ *     gap_last_error() describes it.  Arguments are validated before any device work,
+ *     so invalid input never reaches a kernel.
+ */
+#ifndef GAPSOLVE_H
+#define GAPSOLVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gap_grid_s *gap_grid_t;
+
+typedef enum {
+    GAP_OK = 0,
+    GAP_EINVAL = -1,      /* an argument is out of range or NULL where it may not be */
+    GAP_ECONTACT = -2,    /* some condition has |e| >= clearance at a gap end: h <= 0 */
+    GAP_ENOCONV = -3,     /* max_iter reached; the last iterate is written, info filled */
+    GAP_ENONFINITE = -4,  /* a NaN/Inf appeared in a reduction; the solve was stopped */
+    GAP_ENOMEM = -5,      /* a device or pinned-host allocation failed */
+    GAP_EDEVICE = -6,     /* a HIP runtime call failed */
+    GAP_ESTATE = -7       /* call out of order (e.g. solve before assemble) */
+} gap_status;
+
+enum { GAP_PRECOND_JACOBI = 0, GAP_PRECOND_ASSOR1 = 1, GAP_PRECOND_ASSOR2 = 2 };
+enum { GAP_SCALARS_GLOBAL = 0, GAP_SCALARS_PER_COND = 1 };
+enum { GAP_CAVITATION_NONE = 0, GAP_CAVITATION_CLAMP = 1 };
+#define GAP_MAX_COND 9
+
+/* Gap geometry, fluid and boundary data (Eq 2.3; Table 8 lists the paper's pump).
+ *   R          piston radius R_k (> 0)
+ *   clearance  radial clearance c, bore radius R_c = R + c (> 0)
+ *   length     gap length L_F (> 0)
+ *   mu         dynamic viscosity (> 0)
+ *   U, V       sliding speed of the bore wall relative to the piston, circumferential and
+ *              axial (any sign)
+ *   p_in       Dirichlet pressure at z = 0 (south boundary, Sec 2.1)
+ *   p_out      Dirichlet pressure at z = L (north boundary)
+ *   n_theta    cells around the circumference, 3 <= n_theta <= 4096
+ *   n_axial    cells along the gap, 2 <= n_axial <= 65536                                */
+typedef struct {
+    double R, clearance, length, mu, U, V, p_in, p_out;
+    int32_t n_theta, n_axial;
+} gap_geom;
+
+/* Spherical-cap dimples on the piston (the texture depth h_Text of Eq 2.3).  Host
+ * arrays of `count` entries: centre angle (rad), centre axial position (m), footprint
+ * radius a (> 0) and depth d (0 < d < a).  A cap adds sqrt(rho^2 - r^2) - (rho - d) with
+ * rho = (a^2 + d^2) / (2 d) at in-surface distance r < a (arc length R dtheta, wrapped,
+ * and dz); overlapping caps combine by max.  count = 0 or a NULL gap_dimples: smooth. */
+typedef struct {
+    int32_t count;
+    const double *theta, *z, *radius, *depth;
+} gap_dimples;
+
+/* PCG options (Table 1, Sec 3.1, 3.3).
+ *   omega        relaxation factor of ASSOR, 0 < omega < 2 (paper: 1.8 smooth, 1.6 textured)
+ *   eps          stopping tolerance on ||r_G|| / ||S_G|| (Eq 3.9), > 0
+ *   max_iter     iteration cap, >= 1
+ *   precond      GAP_PRECOND_ASSOR2 (Eq 3.4, the paper's "ASSOR"), _ASSOR1 (Eq 3.2) or
+ *                _JACOBI (Eq 2.8)
+ *   neumann      Neumann order of the ASSOR II inverse; 1 is Eq 3.4 (only 1 is supported)
+ *   scalars      GAP_SCALARS_GLOBAL: one alpha/beta for the joint system (CG on A_G);
+ *                GAP_SCALARS_PER_COND: one recurrence per condition, still one
+ *                synchronized stopping test on the joint residual
+ *   warm_start   nonzero: p holds the initial guess p_0; zero: p_0 = 0 (Table 1 step 1)
+ *   check_every  iterations between host reads of the device convergence flag (0: 32)  */
+typedef struct {
+    double omega, eps;
+    int32_t max_iter, precond, neumann, scalars, warm_start, check_every;
+} gap_solver_opts;
+
+/* Result of a solve.  iterations counts completed Table 1 iterations (SpMV + update);
+ * rel_residual is the recurrence ||r_G|| / ||S_G|| at exit; rel_residual_cond[k] the
+ * same per condition; status repeats the return code. */
+typedef struct {
+    int32_t iterations, status, n_cond, reserved;
+    double rel_residual;
+    double rel_residual_cond[GAP_MAX_COND];
+} gap_solve_info;
+
+/* Fill *opts with the defaults: omega 1.6, eps 1e-10, max_iter 100000, ASSOR II,
+ * neumann 1, GLOBAL scalars, cold start, check_every 32.  Returns GAP_EINVAL if NULL. */
+gap_status gap_default_opts(gap_solver_opts *opts);
+
+/* Create a handle for one gap (Eq 2.3 geometry, Sec 2.1 grid) that can hold up to
+ * max_cond (1 or 9) working conditions.  Allocates every device buffer the path needs
+ * (stencils, sources, Krylov vectors, reduction scratch), evaluates the dimple depths at
+ * cell centres and faces once, and leaves the handle in the "created" state.  *out
+ * receives the handle, or NULL on failure.  Errors: GAP_EINVAL (NULL, sizes, non-positive
+ * geometry, bad dimple), GAP_ENOMEM, GAP_EDEVICE. */
+gap_status create_gap_grid(const gap_geom *geom, const gap_dimples *dimples, int32_t max_cond,
+                           gap_grid_t *out);
+
+/* Release a handle and all its device memory (waits for its pending work).  NULL is a
+ * no-op. */
+gap_status destroy_gap_grid(gap_grid_t grid);
+
+/* Step I (Sec 3.2; Eq 2.3-2.7, 2.17-2.19): assemble the n_cond (1 or 9, <= max_cond)
+ * systems for base state e[4] (m), edot[4] (m/s) and FD steps delta[8] (e1..e4,
+ * edot1..edot4; may be NULL when n_cond = 1).  Rates enter only the source, so
+ * conditions 5..8 share the operator of condition 0 and 5 operators are built.
+ * Boundary treatment (step a3): Dirichlet ends folded into the diagonal and source at
+ * half a cell, periodic circumferential wrap.  Errors: GAP_EINVAL, GAP_ECONTACT (some
+ * condition has |e| >= clearance at z = 0 or z = L), GAP_EDEVICE. */
+gap_status assemble_joint_system(gap_grid_t grid, const double e[4], const double edot[4],
+                                 const double delta[8], int32_t n_cond, void *stream);
+
+/* Step II (Table 1; Eq 3.4-3.6, 3.7, 3.9): solve the assembled joint system.  p is a
+ * device array of n_cond * n doubles, condition-major; it receives the solution (and
+ * holds the initial guess when opts->warm_start).  info (host, may be NULL) receives the
+ * iteration count and residuals.  Synchronizes `stream`.  Errors: GAP_EINVAL,
+ * GAP_ESTATE (nothing assembled), GAP_ENOCONV, GAP_ENONFINITE, GAP_EDEVICE. */
+gap_status solve_joint_pcg(gap_grid_t grid, const gap_solver_opts *opts, double *p,
+                           gap_solve_info *info, void *stream);
+
+/* Step III (Sec 2.4-III) with the cavitation treatment of step a3: for every assembled
+ * condition, integrate (Fx, Fy, Mx, My) of pressure and wall shear over the piston
+ * surface (midpoint rule, moments about z = L/2).  cavitation = GAP_CAVITATION_NONE uses
+ * p as solved; GAP_CAVITATION_CLAMP uses max(p, p_cav).  p: device, n_cond * n doubles.
+ * F: device, n_cond * 4 doubles, row k = (Fx, Fy, Mx, My) of condition k.
+ * Errors: GAP_EINVAL, GAP_ESTATE, GAP_EDEVICE. */
+gap_status integrate_force_moment(gap_grid_t grid, const double *p, int32_t cavitation,
+                                  double p_cav, double *F, void *stream);
+
+/* Step IV (Eq 2.13-2.14): forward-difference double Jacobian from the forces of the 9
+ * conditions.  F: device, 9 * 4 doubles from integrate_force_moment.  J: device, 32
+ * doubles, row-major 4 x 8, J[i*8 + k] = (F[(k+1)*4 + i] - F[i]) / delta[k], rows
+ * (Fx, Fy, Mx, My), columns (e1..e4, edot1..edot4), delta as given to the last assemble.
+ * Errors: GAP_EINVAL, GAP_ESTATE (fewer than 9 conditions assembled), GAP_EDEVICE. */
+gap_status jacobian_fd(gap_grid_t grid, const double *F, double *J, void *stream);
+
+/* Copy the assembled system of condition k to caller device buffers (inspection and
+ * testing): kx (n doubles, east-face conductances h^3/(12 mu) dz/dx), kz
+ * ((n_axial + 1) * n_theta doubles, axial-face conductances h^3/(12 mu) dx/dz, doubled on
+ * the two Dirichlet faces), S (n doubles).  Any of the three may be NULL.  The matrix is
+ * A_PP = kx(i) + kx(i-1) + kz(j) + kz(j+1), off-diagonals minus the shared face value.
+ * Errors: GAP_EINVAL, GAP_ESTATE, GAP_EDEVICE. */
+gap_status gap_read_system(gap_grid_t grid, int32_t k, double *kx, double *kz, double *S,
+                           void *stream);
+
+/* Measurement support.  While enabled, solve_joint_pcg brackets every launch of the
+ * iteration kernels with HIP events on the caller's stream and accumulates the elapsed
+ * device time per kernel kind; gap_kernel_stats reads the counts and totals.  Enabling
+ * (or re-enabling) resets the counters; disabling keeps them readable.
+ * Errors: GAP_EINVAL (NULL grid, unknown kernel), GAP_EDEVICE. */
+enum {
+    GAP_KERNEL_SPMV_DOT = 0,    /* u = z + beta u; v = A u; u^T v          (Table 1 steps 9, 3) */
+    GAP_KERNEL_UPDATE = 1,      /* p += alpha u; r -= alpha A u; D^-1 r    (steps 4-5)        */
+    GAP_KERNEL_ASSOR_LOWER = 2, /* (I - w D^-1 L) D^-1 r                   (Eq 3.5)           */
+    GAP_KERNEL_ASSOR_UPPER = 3, /* z = w(2-w)(I - w D^-1 L^T) v; r^T z     (Eq 3.6, step 8)   */
+    GAP_KERNEL_FINALIZE = 4,    /* scalar reductions, alpha/beta, stopping test (Eq 3.9)     */
+    GAP_KERNEL_COUNT = 5
+};
+gap_status gap_kernel_timing(gap_grid_t grid, int32_t enable);
+gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char *gap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAPSOLVE_H */

@@ -107,14 +107,17 @@ def dimple_texture(R, theta_c, z_c, radius, depth):
 
     def tex(theta, z):
         theta, z = np.broadcast_arrays(np.asarray(theta, dtype=float), np.asarray(z, dtype=float))
+        shape = theta.shape
+        theta, z = theta.ravel(), z.ravel()
         out = np.zeros(theta.shape)
         for tc, zc, a, d in zip(theta_c, z_c, radius, depth):
-            dth = np.mod(theta - tc + np.pi, 2.0 * np.pi) - np.pi
-            r2 = (R * dth) ** 2 + (z - zc) ** 2
+            near = np.nonzero(np.abs(z - zc) < a)[0]      # only points in the cap's axial band
+            dth = np.mod(theta[near] - tc + np.pi, 2.0 * np.pi) - np.pi
+            r2 = (R * dth) ** 2 + (z[near] - zc) ** 2
             rho = (a * a + d * d) / (2.0 * d)
             inside = r2 < a * a
             cap = np.where(inside, np.sqrt(np.maximum(rho * rho - r2, 0.0)) - (rho - d), 0.0)
-            out = np.maximum(out, cap)
-        return out
+            out[near] = np.maximum(out[near], cap)
+        return out.reshape(shape)
 
     return tex

@@ -1,0 +1,474 @@
+// HIP kernels of the joint piston-gap solve (gfx950, FP64, no MFMA: bandwidth-bound sparse work).
+//
+// Work decomposition shared by the solve kernels: the rows of every condition are cut into
+// `per_cond` chunks of `rows` consecutive rows; block b works on chunk b (condition
+// b / per_cond).  Every chunk writes one partial sum per reduced quantity to a fixed slot,
+// and a one-block finalize kernel adds the slots of each condition in a fixed order, so
+// all reductions are deterministic and independent of scheduling.
+#pragma once
+
+#include "gap_device.hpp"
+
+struct ChunkMap {
+    int per_cond;   // chunks per condition
+    int rows;       // rows per chunk (the last chunk of a condition may hold fewer)
+    int total;      // per_cond * n_cond
+};
+
+__device__ __forceinline__ void chunk_rows(const ChunkMap& cm, int nz, int b, int& c, int& j0, int& j1)
+{
+    c = b / cm.per_cond;
+    j0 = (b - c * cm.per_cond) * cm.rows;
+    j1 = min(j0 + cm.rows, nz);
+}
+
+// ---------------------------------------------------------------------------------------
+// Texture: spherical caps scattered over their footprint boxes, overlaps combined by max.
+// Depths are >= 0, so their IEEE bit patterns order like unsigned integers.
+// plane 0: cell centres, plane 1: east faces, plane 2: axial faces (nz + 1 rows).
+__global__ void k_texture(GeomDev g, int count, const double* __restrict__ th_c,
+                          const double* __restrict__ z_c, const double* __restrict__ rad,
+                          const double* __restrict__ dep, double* tex_c, double* tex_e, double* tex_f)
+{
+    const int k = blockIdx.x;
+    const int plane = blockIdx.y;
+    if (k >= count) return;
+    const double tc = th_c[k], zc = z_c[k], a = rad[k], d = dep[k];
+    const double rho = (a * a + d * d) / (2.0 * d);
+    const double half_ang = a / g.R;
+    const int span_i = (int)ceil(half_ang / g.dth) + 2;
+    int ncol = 2 * span_i + 1;
+    if (ncol > g.nt) ncol = g.nt;
+    const int ic0 = (int)floor(tc / g.dth) - span_i;
+    const int nrows = (plane == 2) ? g.nz + 1 : g.nz;
+    int jlo = (int)floor((zc - a) / g.dz) - 2;
+    int jhi = (int)ceil((zc + a) / g.dz) + 2;
+    if (jlo < 0) jlo = 0;
+    if (jhi > nrows - 1) jhi = nrows - 1;
+    if (jhi < jlo) return;
+    double* dst = plane == 0 ? tex_c : (plane == 1 ? tex_e : tex_f);
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    const long long cells = (long long)ncol * (jhi - jlo + 1);
+    for (long long q = threadIdx.x; q < cells; q += blockDim.x) {
+        const int jr = jlo + (int)(q / ncol);
+        int i = (ic0 + (int)(q % ncol)) % g.nt;
+        if (i < 0) i += g.nt;
+        const double th = (plane == 1) ? (i + 1.0) * g.dth : (i + 0.5) * g.dth;
+        const double z = (plane == 2) ? jr * g.dz : (jr + 0.5) * g.dz;
+        double dt = th - tc + 0.5 * two_pi;
+        dt = dt - two_pi * floor(dt / two_pi) - 0.5 * two_pi;
+        const double ds = g.R * dt, dzz = z - zc;
+        const double r2 = ds * ds + dzz * dzz;
+        if (r2 < a * a) {
+            const double v = sqrt(fmax(rho * rho - r2, 0.0)) - (rho - d);
+            if (v > 0.0)
+                atomicMax((unsigned long long*)&dst[(size_t)jr * g.nt + i],
+                          (unsigned long long)__double_as_longlong(v));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Assembly (step I): one thread per (cell, condition).  Writes the source of every
+// condition and, for conditions that own an operator, its face conductances.
+__global__ void k_assemble(GeomDev g, CondDev cd, TablesDev tb, double* __restrict__ kx,
+                           double* __restrict__ kz, double* __restrict__ S)
+{
+    const int c = blockIdx.y;
+    const int n = g.nt * g.nz;
+    const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gidx >= n) return;
+    const int j = gidx / g.nt, i = gidx - j * g.nt;
+    const int iw = i ? i - 1 : g.nt - 1;
+    const double* e = cd.e[c];
+    const double zj = (j + 0.5) * g.dz;
+    const double h_e = film_h(g, e, tb.cos_e[i], tb.sin_e[i], zj, tb.tex_e[gidx]);
+    const double h_w = film_h(g, e, tb.cos_e[iw], tb.sin_e[iw], zj, tb.tex_e[j * g.nt + iw]);
+    const double h_s = film_h(g, e, tb.cos_c[i], tb.sin_c[i], j * g.dz, tb.tex_f[j * g.nt + i]);
+    const double h_n = film_h(g, e, tb.cos_c[i], tb.sin_c[i], (j + 1) * g.dz, tb.tex_f[(j + 1) * g.nt + i]);
+    const double hdot = film_rate(g, e, cd.ed[c], tb.cos_c[i], tb.sin_c[i], zj);
+    const double kfz = g.dx / g.dz / (12.0 * g.mu);
+    double s = -(0.5 * g.U) * (h_e - h_w) * g.dz - (0.5 * g.V) * (h_n - h_s) * g.dx - hdot * g.dx * g.dz;
+    if (j == 0) s += 2.0 * (h_s * h_s * h_s) * kfz * g.p_in;
+    if (j == g.nz - 1) s += 2.0 * (h_n * h_n * h_n) * kfz * g.p_out;
+    S[(size_t)c * n + gidx] = s;
+    if (c < cd.n_op) {
+        const double kfx = g.dz / g.dx / (12.0 * g.mu);
+        kx[(size_t)c * n + gidx] = (h_e * h_e * h_e) * kfx;
+        double* kzo = kz + (size_t)c * (n + g.nt);
+        kzo[gidx] = (j == 0 ? 2.0 : 1.0) * (h_s * h_s * h_s) * kfz;
+        if (j == g.nz - 1) kzo[n + i] = 2.0 * (h_n * h_n * h_n) * kfz;
+    }
+}
+
+// Diagonal A_PP = kx(i) + kx(i-1) + kz(j) + kz(j+1) (Dirichlet faces included).
+__device__ __forceinline__ double diag_at(const double* kx, const double* kz, int i, int j, int nt)
+{
+    const int iw = i ? i - 1 : nt - 1;
+    return ((kx[j * nt + i] + kx[j * nt + iw]) + kz[j * nt + i]) + kz[(j + 1) * nt + i];
+}
+
+// (A x)(i, j) with x given by a functor of (i, j).
+template <class X>
+__device__ __forceinline__ double apply_A(const double* kx, const double* kz, int i, int j, int nt,
+                                          int nz, X x)
+{
+    const int iw = i ? i - 1 : nt - 1;
+    const int ie = (i + 1 < nt) ? i + 1 : 0;
+    const double kE = kx[j * nt + i], kW = kx[j * nt + iw];
+    const double kS = kz[j * nt + i], kN = kz[(j + 1) * nt + i];
+    double a = (((kE + kW) + kS) + kN) * x(i, j) - kE * x(ie, j) - kW * x(iw, j);
+    if (j > 0) a -= kS * x(i, j - 1);
+    if (j < nz - 1) a -= kN * x(i, j + 1);
+    return a;
+}
+
+// Diagonal preconditioners: Jacobi (Eq 2.8) and ASSOR I (Eq 3.2), stored as M^{-1}_ii per
+// operator.  ASSOR I: w(2-w) / (D_ii + w^2 sum_k L_ik^2 / D_kk), L the strict lower
+// triangle in the natural order (west, south, and the east wrap of the last column).
+__global__ void k_diag_precond(GeomDev g, int kind, double omega, const double* __restrict__ kx_all,
+                               const double* __restrict__ kz_all, double* __restrict__ minv, int n_op)
+{
+    const int o = blockIdx.y;
+    const int n = g.nt * g.nz;
+    const int gidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gidx >= n || o >= n_op) return;
+    const double* kx = kx_all + (size_t)o * n;
+    const double* kz = kz_all + (size_t)o * (n + g.nt);
+    const int nt = g.nt, j = gidx / nt, i = gidx - j * nt;
+    const double D = diag_at(kx, kz, i, j, nt);
+    double val;
+    if (kind == 0) {
+        val = 1.0 / D;
+    } else {
+        double s = 0.0;
+        if (i > 0) { const double l = kx[j * nt + i - 1]; s += l * l / diag_at(kx, kz, i - 1, j, nt); }
+        if (i == nt - 1) { const double l = kx[j * nt + i]; s += l * l / diag_at(kx, kz, 0, j, nt); }
+        if (j > 0) { const double l = kz[j * nt + i]; s += l * l / diag_at(kx, kz, i, j - 1, nt); }
+        val = omega * (2.0 - omega) / (D + omega * omega * s);
+    }
+    minv[(size_t)o * n + gidx] = val;
+}
+
+// ---------------------------------------------------------------------------------------
+// PCG (Table 1).  Vector arguments point at condition 0; condition c is at offset c * n.
+struct PcgArgs {
+    const double* kx;   // [n_op][n]
+    const double* kz;   // [n_op][n + nt]
+    const double* minv; // [n_op][n] diagonal preconditioner (Jacobi / ASSOR I), or null
+    const double* S;    // [n_cond][n]
+    double* p;          // [n_cond][n] solution (caller memory)
+    double* r;          // [n_cond][n] residual
+    double* u_in;       // search direction of the previous iteration
+    double* u_out;      // search direction of this iteration
+    double* z;          // preconditioned residual
+    double* y;          // ASSOR scratch: D^{-1} r
+    double* w;          // ASSOR scratch: (I - w D^{-1} L) D^{-1} r
+    double* partial;    // [n_q][chunks]
+    ScalarsDev* sc;
+    double omega;
+    int precond;        // 0 Jacobi, 1 ASSOR I, 2 ASSOR II
+};
+
+// Initial residual r0 = S - A p0 (p0 = 0 unless warm), u = 0, and the first half of the
+// preconditioner (y = D^{-1} r0) or the diagonal one (z = M^{-1} r0).
+// partials: 0 ||S||^2, 1 ||r||^2, 2 r.z (diagonal preconditioners only).
+__global__ void k_init(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a, int warm)
+{
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt, nz = g.nz;
+    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
+    const int o = cd.op[c];
+    const double* kx = a.kx + (size_t)o * n;
+    const double* kz = a.kz + (size_t)o * (n + nt);
+    const double* p = a.p + off;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = j0; j < j1; ++j) {
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const int gi = j * nt + i;
+            const double s = a.S[off + gi];
+            double r = s;
+            if (warm) r = s - apply_A(kx, kz, i, j, nt, nz, [&](int ii, int jj) { return p[jj * nt + ii]; });
+            else a.p[off + gi] = 0.0;
+            a.r[off + gi] = r;
+            a.u_in[off + gi] = 0.0;
+            acc[0] += s * s;
+            acc[1] += r * r;
+            if (a.precond == 2) {
+                a.y[off + gi] = r / diag_at(kx, kz, i, j, nt);
+            } else {
+                const double zz = a.minv[(size_t)o * n + gi] * r;
+                a.z[off + gi] = zz;
+                acc[2] += r * zz;
+            }
+        }
+    }
+    block_sum<3>(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) a.partial[q * cm.total + blockIdx.x] = acc[q];
+}
+
+// Table 1 steps 9 and 3: u = z + beta u_prev, then v = A u and the partial u^T v.
+__global__ void k_spmv_dot(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a)
+{
+    if (a.sc->done) return;
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt, nz = g.nz;
+    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
+    const int o = cd.op[c];
+    const double* kx = a.kx + (size_t)o * n;
+    const double* kz = a.kz + (size_t)o * (n + nt);
+    const double beta = a.sc->beta[c];
+    const double* zc = a.z + off;
+    const double* ui = a.u_in + off;
+    auto u = [&](int ii, int jj) { const int q = jj * nt + ii; return zc[q] + beta * ui[q]; };
+    double acc[1] = {0.0};
+    for (int j = j0; j < j1; ++j) {
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const double uc = u(i, j);
+            const double v = apply_A(kx, kz, i, j, nt, nz, u);
+            a.u_out[off + j * nt + i] = uc;
+            acc[0] += uc * v;
+        }
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = acc[0];
+}
+
+// Table 1 steps 4-5 (and 7 for the diagonal preconditioners): p += alpha u,
+// r -= alpha A u (A u recomputed from u), then y = D^{-1} r (ASSOR II) or z = M^{-1} r.
+// partials: 0 ||r||^2, 1 r.z (diagonal preconditioners).
+__global__ void k_update(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a)
+{
+    if (a.sc->done) return;
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt, nz = g.nz;
+    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
+    const int o = cd.op[c];
+    const double* kx = a.kx + (size_t)o * n;
+    const double* kz = a.kz + (size_t)o * (n + nt);
+    const double alpha = a.sc->alpha[c];
+    const double* uc = a.u_out + off;
+    auto u = [&](int ii, int jj) { return uc[jj * nt + ii]; };
+    double acc[2] = {0.0, 0.0};
+    for (int j = j0; j < j1; ++j) {
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const int gi = j * nt + i;
+            const double v = apply_A(kx, kz, i, j, nt, nz, u);
+            a.p[off + gi] += alpha * uc[gi];
+            const double r = a.r[off + gi] - alpha * v;
+            a.r[off + gi] = r;
+            acc[0] += r * r;
+            if (a.precond == 2) {
+                a.y[off + gi] = r / diag_at(kx, kz, i, j, nt);
+            } else {
+                const double zz = a.minv[(size_t)o * n + gi] * r;
+                a.z[off + gi] = zz;
+                acc[1] += r * zz;
+            }
+        }
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        a.partial[blockIdx.x] = acc[0];
+        a.partial[cm.total + blockIdx.x] = acc[1];
+    }
+}
+
+// ASSOR II first step (Eq 3.5): w = (I - omega D^{-1} L) y with y = D^{-1} r.
+// L couples (i, j) to (i-1, j) for i > 0, to (0, j) for i = n_theta-1, and to (i, j-1).
+__global__ void k_assor_lower(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a, int check_done)
+{
+    if (check_done && a.sc->done) return;
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt;
+    const size_t n = (size_t)nt * g.nz, off = (size_t)c * n;
+    const int o = cd.op[c];
+    const double* kx = a.kx + (size_t)o * n;
+    const double* kz = a.kz + (size_t)o * (n + nt);
+    const double* y = a.y + off;
+    const double om = a.omega;
+    for (int j = j0; j < j1; ++j) {
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const int gi = j * nt + i;
+            double s = 0.0;
+            if (i > 0) s += kx[gi - 1] * y[gi - 1];
+            if (i == nt - 1) s += kx[gi] * y[j * nt];
+            if (j > 0) s += kz[gi] * y[gi - nt];
+            a.w[off + gi] = y[gi] + om / diag_at(kx, kz, i, j, nt) * s;
+        }
+    }
+}
+
+// ASSOR II second step (Eq 3.6): z = w (2 - w)(I - omega D^{-1} L^T) w; partial r.z into
+// slot rz_slot.
+// L^T couples (i, j) to (i+1, j) for i < n_theta-1, to (n_theta-1, j) for i = 0, and to
+// (i, j+1).
+__global__ void k_assor_upper(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a, int check_done, int rz_slot)
+{
+    if (check_done && a.sc->done) return;
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt, nz = g.nz;
+    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
+    const int o = cd.op[c];
+    const double* kx = a.kx + (size_t)o * n;
+    const double* kz = a.kz + (size_t)o * (n + nt);
+    const double* w = a.w + off;
+    const double om = a.omega;
+    const double scale = om * (2.0 - om);
+    double acc[1] = {0.0};
+    for (int j = j0; j < j1; ++j) {
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const int gi = j * nt + i;
+            double s = 0.0;
+            if (i < nt - 1) s += kx[gi] * w[gi + 1];
+            if (i == 0) s += kx[j * nt + nt - 1] * w[j * nt + nt - 1];
+            if (j < nz - 1) s += kz[gi + nt] * w[gi + nt];
+            const double zz = scale * (w[gi] + om / diag_at(kx, kz, i, j, nt) * s);
+            a.z[off + gi] = zz;
+            acc[0] += a.r[off + gi] * zz;
+        }
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) a.partial[rz_slot * cm.total + blockIdx.x] = acc[0];
+}
+
+// ---------------------------------------------------------------------------------------
+// Finalize kernels: one block adds the chunk partials of every condition in a fixed order
+// and updates the device scalars.
+__device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& cm, int c)
+{
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < cm.per_cond; b += blockDim.x) v[0] += part[c * cm.per_cond + b];
+    block_sum<1>(v);
+    return v[0];   // valid in thread 0
+}
+
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
+
+__global__ void k_finalize(ChunkMap cm, int n_cond, const double* __restrict__ part, ScalarsDev* sc,
+                           int mode, int per_cond_scalars, double eps, int max_iter)
+{
+    if (mode != FIN_INIT && sc->done) return;
+    __shared__ double q0[GAP_MAXC], q1[GAP_MAXC], q2[GAP_MAXC];
+    for (int c = 0; c < n_cond; ++c) {
+        const double a0 = cond_sum(part, cm, c);
+        const double a1 = (mode != FIN_ALPHA) ? cond_sum(part + cm.total, cm, c) : 0.0;
+        const double a2 = (mode == FIN_INIT) ? cond_sum(part + 2 * cm.total, cm, c) : 0.0;
+        if (threadIdx.x == 0) { q0[c] = a0; q1[c] = a1; q2[c] = a2; }
+    }
+    if (threadIdx.x != 0) return;
+    bool bad = false;
+    if (mode == FIN_ALPHA) {
+        double num = 0.0, den = 0.0;
+        for (int c = 0; c < n_cond; ++c) { num += sc->d[c]; den += q0[c]; }
+        for (int c = 0; c < n_cond; ++c) {
+            const double al = per_cond_scalars ? sc->d[c] / q0[c] : num / den;
+            sc->alpha[c] = al;
+            bad |= !finite_d(al);
+        }
+        if (bad) { sc->status = -4; sc->done = 1; }
+        return;
+    }
+    // FIN_INIT: q0 = ||S||^2, q1 = ||r||^2, q2 = r.z ;  FIN_BETA: q0 = ||r||^2, q1 = r.z
+    const double* rr = (mode == FIN_INIT) ? q1 : q0;
+    const double* rz = (mode == FIN_INIT) ? q2 : q1;
+    if (mode == FIN_INIT) {
+        for (int c = 0; c < n_cond; ++c) { sc->ss[c] = q0[c]; sc->beta[c] = 0.0; sc->alpha[c] = 0.0; }
+        sc->iter = 0;
+        sc->status = 0;
+        sc->done = 0;
+    } else {
+        double num = 0.0, den = 0.0;
+        for (int c = 0; c < n_cond; ++c) { num += rz[c]; den += sc->d[c]; }
+        for (int c = 0; c < n_cond; ++c) {
+            const double be = per_cond_scalars ? rz[c] / sc->d[c] : num / den;
+            sc->beta[c] = be;
+            bad |= !finite_d(be);
+        }
+        sc->iter += 1;
+    }
+    double rs = 0.0, ss = 0.0;
+    for (int c = 0; c < n_cond; ++c) {
+        sc->d[c] = rz[c];
+        sc->rr[c] = rr[c];
+        rs += rr[c];
+        ss += sc->ss[c];
+        const double sref = sc->ss[c] > 0.0 ? sc->ss[c] : 1.0;
+        sc->rel_cond[c] = sqrt(rr[c] / sref);
+    }
+    const double rel = sqrt(rs / (ss > 0.0 ? ss : 1.0));
+    sc->rel = rel;
+    bad |= !finite_d(rel);
+    if (bad) { sc->status = -4; sc->done = 1; }
+    else if (rel <= eps) { sc->done = 1; }
+    else if (sc->iter >= max_iter) { sc->status = -3; sc->done = 1; }
+}
+
+// ---------------------------------------------------------------------------------------
+// Force and moment integration (step III) with the cavitation rule; partials 0..3 are
+// Fx, Fy, Mx, My per chunk before the factor dA.
+__device__ __forceinline__ double peff(double p, int cav, double pc) { return (cav && p < pc) ? pc : p; }
+
+__global__ void k_forces(GeomDev g, CondDev cd, ChunkMap cm, TablesDev tb, const double* __restrict__ p_all,
+                         int cav, double p_cav, double* __restrict__ partial)
+{
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt, nz = g.nz;
+    const size_t n = (size_t)nt * nz;
+    const double* p = p_all + (size_t)c * n;
+    const double* e = cd.e[c];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = j0; j < j1; ++j) {
+        const double zj = (j + 0.5) * g.dz;
+        const double zr = zj - 0.5 * g.L;
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const int gi = j * nt + i;
+            const int iw = i ? i - 1 : nt - 1;
+            const int ie = (i + 1 < nt) ? i + 1 : 0;
+            const double pc = peff(p[gi], cav, p_cav);
+            const double dpdx = (peff(p[j * nt + ie], cav, p_cav) - peff(p[j * nt + iw], cav, p_cav)) / (2.0 * g.dx);
+            double dpdz;
+            if (j == 0) dpdz = (peff(p[gi + nt], cav, p_cav) - g.p_in) / (1.5 * g.dz);
+            else if (j == nz - 1) dpdz = (g.p_out - peff(p[gi - nt], cav, p_cav)) / (1.5 * g.dz);
+            else dpdz = (peff(p[gi + nt], cav, p_cav) - peff(p[gi - nt], cav, p_cav)) / (2.0 * g.dz);
+            const double cs = tb.cos_c[i], sn = tb.sin_c[i];
+            const double h = film_h(g, e, cs, sn, zj, tb.tex_c[gi]);
+            const double tt = -0.5 * h * dpdx + g.mu * g.U / h;
+            const double tz = -0.5 * h * dpdz + g.mu * g.V / h;
+            acc[0] += -pc * cs - tt * sn;
+            acc[1] += -pc * sn + tt * cs;
+            acc[2] += zr * (pc * sn - tt * cs) + tz * g.R * sn;
+            acc[3] += -zr * (pc * cs + tt * sn) - tz * g.R * cs;
+        }
+    }
+    block_sum<4>(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) partial[q * cm.total + blockIdx.x] = acc[q];
+}
+
+__global__ void k_forces_finalize(ChunkMap cm, int n_cond, double dA, const double* __restrict__ part,
+                                  double* __restrict__ F)
+{
+    for (int c = 0; c < n_cond; ++c)
+        for (int q = 0; q < 4; ++q) {
+            const double s = cond_sum(part + q * cm.total, cm, c);
+            if (threadIdx.x == 0) F[c * 4 + q] = s * dA;
+        }
+}
+
+// Eq 2.13-2.14: J[i][k] = (F_{k+1,i} - F_{0,i}) / delta_k.
+struct Delta8 { double d[8]; };
+__global__ void k_jacobian_fd(const double* __restrict__ F, Delta8 dl, double* __restrict__ J)
+{
+    const int t = threadIdx.x;
+    if (t >= 32) return;
+    const int i = t / 8, k = t % 8;
+    J[t] = (F[(k + 1) * 4 + i] - F[i]) / dl.d[k];
+}

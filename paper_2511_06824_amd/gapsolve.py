@@ -1,0 +1,207 @@
+"""ctypes binding of the gapsolve C ABI (include/gapsolve.h), same names as the C entry points.
+
+Argument marshalling only: every step of the solve runs in the HIP library.  Device
+buffers are passed as integer addresses (for instance ``tensor.data_ptr()`` of a torch
+CUDA tensor) and streams as the integer value of a hipStream_t (``None`` or 0: the
+default stream).  Every non-OK status raises ``GapError`` carrying the library's message.
+If the library has not been built, importing this module succeeds but the first call
+raises ``GapLibraryMissing``: there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libgapsolve.so")
+
+GAP_OK = 0
+GAP_EINVAL = -1
+GAP_ECONTACT = -2
+GAP_ENOCONV = -3
+GAP_ENONFINITE = -4
+GAP_ENOMEM = -5
+GAP_EDEVICE = -6
+GAP_ESTATE = -7
+STATUS_NAMES = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ECONTACT", -3: "GAP_ENOCONV",
+                -4: "GAP_ENONFINITE", -5: "GAP_ENOMEM", -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
+
+GAP_PRECOND_JACOBI, GAP_PRECOND_ASSOR1, GAP_PRECOND_ASSOR2 = 0, 1, 2
+GAP_SCALARS_GLOBAL, GAP_SCALARS_PER_COND = 0, 1
+GAP_CAVITATION_NONE, GAP_CAVITATION_CLAMP = 0, 1
+GAP_MAX_COND = 9
+GAP_KERNEL_SPMV_DOT, GAP_KERNEL_UPDATE, GAP_KERNEL_ASSOR_LOWER, GAP_KERNEL_ASSOR_UPPER, GAP_KERNEL_FINALIZE = range(5)
+GAP_KERNEL_COUNT = 5
+KERNEL_NAMES = ["k_spmv_dot", "k_update", "k_assor_lower", "k_assor_upper", "k_finalize"]
+
+
+class gap_geom(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double), ("clearance", ctypes.c_double), ("length", ctypes.c_double),
+                ("mu", ctypes.c_double), ("U", ctypes.c_double), ("V", ctypes.c_double),
+                ("p_in", ctypes.c_double), ("p_out", ctypes.c_double),
+                ("n_theta", ctypes.c_int32), ("n_axial", ctypes.c_int32)]
+
+
+class gap_dimples(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("theta", ctypes.POINTER(ctypes.c_double)),
+                ("z", ctypes.POINTER(ctypes.c_double)), ("radius", ctypes.POINTER(ctypes.c_double)),
+                ("depth", ctypes.POINTER(ctypes.c_double))]
+
+
+class gap_solver_opts(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("neumann", ctypes.c_int32), ("scalars", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class gap_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("n_cond", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("rel_residual_cond", ctypes.c_double * GAP_MAX_COND)]
+
+
+class GapLibraryMissing(RuntimeError):
+    pass
+
+
+class GapError(RuntimeError):
+    def __init__(self, status, message, info=None):
+        self.status = status
+        self.info = info
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D8 = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "gap_default_opts": [ctypes.POINTER(gap_solver_opts)],
+    "create_gap_grid": [ctypes.POINTER(gap_geom), ctypes.POINTER(gap_dimples), ctypes.c_int32,
+                        ctypes.POINTER(_P)],
+    "destroy_gap_grid": [_P],
+    "assemble_joint_system": [_P, _D8, _D8, _D8, ctypes.c_int32, _P],
+    "solve_joint_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(gap_solve_info), _P],
+    "integrate_force_moment": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
+    "jacobian_fd": [_P, _P, _P, _P],
+    "gap_read_system": [_P, ctypes.c_int32, _P, _P, _P, _P],
+    "gap_kernel_timing": [_P, ctypes.c_int32],
+    "gap_kernel_stats": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+}
+
+
+def library_path():
+    return LIB_PATH
+
+
+def load():
+    """Load the HIP library (once).  Raises GapLibraryMissing if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GapLibraryMissing(
+                f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGNATURES.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        lib.gap_last_error.argtypes = []
+        lib.gap_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def gap_last_error():
+    return load().gap_last_error().decode()
+
+
+def _check(status, info=None):
+    if status != GAP_OK:
+        raise GapError(status, gap_last_error(), info)
+
+
+def _darr(values, count):
+    if values is None:
+        return None
+    vals = [float(v) for v in values]
+    if len(vals) != count:
+        raise ValueError(f"expected {count} values, got {len(vals)}")
+    return (ctypes.c_double * count)(*vals)
+
+
+def _stream(stream):
+    return ctypes.c_void_p(int(stream) if stream else 0)
+
+
+def gap_default_opts():
+    o = gap_solver_opts()
+    _check(load().gap_default_opts(ctypes.byref(o)))
+    return o
+
+
+def make_geom(R, clearance, length, mu, U, V, p_in, p_out, n_theta, n_axial):
+    return gap_geom(float(R), float(clearance), float(length), float(mu), float(U), float(V),
+                    float(p_in), float(p_out), int(n_theta), int(n_axial))
+
+
+def make_dimples(theta, z, radius, depth):
+    """gap_dimples over host copies; the returned object keeps its arrays alive."""
+    count = len(theta)
+    d = gap_dimples()
+    d.count = count
+    d._keep = [(ctypes.c_double * max(count, 1))(*[float(v) for v in arr]) for arr in (theta, z, radius, depth)]
+    d.theta, d.z, d.radius, d.depth = [ctypes.cast(a, _D8) for a in d._keep]
+    return d
+
+
+def create_gap_grid(geom, dimples, max_cond):
+    h = ctypes.c_void_p()
+    _check(load().create_gap_grid(ctypes.byref(geom), ctypes.byref(dimples) if dimples is not None else None,
+                                  int(max_cond), ctypes.byref(h)))
+    return h
+
+
+def destroy_gap_grid(handle):
+    _check(load().destroy_gap_grid(handle))
+
+
+def assemble_joint_system(handle, e, edot, delta, n_cond, stream=None):
+    _check(load().assemble_joint_system(handle, _darr(e, 4), _darr(edot, 4), _darr(delta, 8), int(n_cond),
+                                        _stream(stream)))
+
+
+def solve_joint_pcg(handle, opts, p_ptr, stream=None, raise_on_error=True):
+    """Returns (status, gap_solve_info); raises GapError on failure unless told not to."""
+    info = gap_solve_info()
+    st = load().solve_joint_pcg(handle, ctypes.byref(opts), ctypes.c_void_p(int(p_ptr)), ctypes.byref(info),
+                                _stream(stream))
+    if raise_on_error:
+        _check(st, info)
+    return st, info
+
+
+def integrate_force_moment(handle, p_ptr, cavitation, p_cav, F_ptr, stream=None):
+    _check(load().integrate_force_moment(handle, ctypes.c_void_p(int(p_ptr)), int(cavitation), float(p_cav),
+                                         ctypes.c_void_p(int(F_ptr)), _stream(stream)))
+
+
+def jacobian_fd(handle, F_ptr, J_ptr, stream=None):
+    _check(load().jacobian_fd(handle, ctypes.c_void_p(int(F_ptr)), ctypes.c_void_p(int(J_ptr)), _stream(stream)))
+
+
+def gap_read_system(handle, k, kx_ptr, kz_ptr, S_ptr, stream=None):
+    _check(load().gap_read_system(handle, int(k), ctypes.c_void_p(int(kx_ptr or 0)),
+                                  ctypes.c_void_p(int(kz_ptr or 0)), ctypes.c_void_p(int(S_ptr or 0)),
+                                  _stream(stream)))
+
+
+def gap_kernel_timing(handle, enable):
+    _check(load().gap_kernel_timing(handle, int(enable)))
+
+
+def gap_kernel_stats(handle, kernel):
+    """(launches, total device milliseconds) of one iteration kernel kind."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(load().gap_kernel_stats(handle, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

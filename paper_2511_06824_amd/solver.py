@@ -1,0 +1,104 @@
+"""Torch-facing wrapper of the gapsolve C ABI: device buffers and streams come from torch,
+every step of the path runs in the HIP library (``gapsolve``)."""
+
+import torch
+
+from . import gapsolve as G
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class JointGapSolver:
+    """One gap geometry (+ dimples) on one GPU, holding up to `max_cond` conditions.
+
+    Owns the library handle and the caller-side buffers: p (n_cond x n), F (n_cond x 4),
+    J (4 x 8), all float64 on `device`."""
+
+    def __init__(self, R, clearance, length, mu, U, V, p_in, p_out, n_theta, n_axial,
+                 dimples=None, max_cond=9, device="cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("JointGapSolver needs a HIP GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self.n_theta, self.n_axial = int(n_theta), int(n_axial)
+        self.n = self.n_theta * self.n_axial
+        self.max_cond = int(max_cond)
+        self.geom = G.make_geom(R, clearance, length, mu, U, V, p_in, p_out, n_theta, n_axial)
+        dm = None
+        if dimples is not None and len(dimples[0]) > 0:
+            dm = G.make_dimples(*dimples)
+        with torch.cuda.device(self.device):
+            self.handle = G.create_gap_grid(self.geom, dm, self.max_cond)
+        self.p = torch.zeros(self.max_cond * self.n, dtype=torch.float64, device=self.device)
+        self.F = torch.zeros(self.max_cond * 4, dtype=torch.float64, device=self.device)
+        self.J = torch.zeros(32, dtype=torch.float64, device=self.device)
+        self.n_cond = 0
+
+    @classmethod
+    def from_case(cls, case, max_cond=9, device="cuda:0"):
+        dimples = None
+        if case.n_dimples:
+            dimples = (case.dimple_theta, case.dimple_z, case.dimple_radius, case.dimple_depth)
+        return cls(case.R, case.c, case.L, case.mu, case.U, case.V, case.p_in, case.p_out,
+                   case.n_theta, case.n_axial, dimples=dimples, max_cond=max_cond, device=device)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            G.destroy_gap_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the four steps -------------------------------------------------------------
+    def assemble(self, e, edot, delta=None, n_cond=9):
+        G.assemble_joint_system(self.handle, e, edot, delta, n_cond, _stream(self.device))
+        self.n_cond = int(n_cond)
+
+    @staticmethod
+    def options(omega=1.6, eps=1e-10, max_iter=100000, precond=G.GAP_PRECOND_ASSOR2, scalars=G.GAP_SCALARS_GLOBAL,
+                warm_start=False, check_every=0, neumann=1):
+        o = G.gap_default_opts()
+        o.omega, o.eps, o.max_iter = float(omega), float(eps), int(max_iter)
+        o.precond, o.scalars, o.neumann = int(precond), int(scalars), int(neumann)
+        o.warm_start, o.check_every = int(bool(warm_start)), int(check_every)
+        return o
+
+    def solve(self, opts=None, raise_on_error=True, **kw):
+        """Returns (p view of shape (n_cond, n_axial, n_theta), gap_solve_info)."""
+        opts = opts if opts is not None else self.options(**kw)
+        st, info = G.solve_joint_pcg(self.handle, opts, self.p.data_ptr(), _stream(self.device), raise_on_error)
+        return self.pressure(), info
+
+    def pressure(self):
+        return self.p[: self.n_cond * self.n].view(self.n_cond, self.n_axial, self.n_theta)
+
+    def integrate(self, cavitation=G.GAP_CAVITATION_NONE, p_cav=0.0, p=None):
+        src = self.p if p is None else p
+        G.integrate_force_moment(self.handle, src.data_ptr(), cavitation, p_cav, self.F.data_ptr(),
+                                 _stream(self.device))
+        return self.F[: self.n_cond * 4].view(self.n_cond, 4)
+
+    def jacobian_fd(self):
+        G.jacobian_fd(self.handle, self.F.data_ptr(), self.J.data_ptr(), _stream(self.device))
+        return self.J.view(4, 8)
+
+    def read_system(self, k):
+        kx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        kz = torch.empty(self.n + self.n_theta, dtype=torch.float64, device=self.device)
+        S = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        G.gap_read_system(self.handle, k, kx.data_ptr(), kz.data_ptr(), S.data_ptr(), _stream(self.device))
+        return (kx.view(self.n_axial, self.n_theta), kz.view(self.n_axial + 1, self.n_theta),
+                S.view(self.n_axial, self.n_theta))
+
+    def step(self, e, edot, delta, opts, cavitation=G.GAP_CAVITATION_NONE, p_cav=0.0):
+        """One pass of the hot path: assemble 9 conditions, joint PCG, forces, FD Jacobian."""
+        self.assemble(e, edot, delta, 9)
+        _, info = self.solve(opts)
+        F = self.integrate(cavitation, p_cav)
+        J = self.jacobian_fd()
+        return F, J, info
