@@ -71,7 +71,7 @@ enum { GAP_CAVITATION_NONE = 0, GAP_CAVITATION_CLAMP = 1 };
  *              axial (any sign)
  *   p_in       Dirichlet pressure at z = 0 (south boundary, Sec 2.1)
  *   p_out      Dirichlet pressure at z = L (north boundary)
- *   n_theta    cells around the circumference, 3 <= n_theta <= 4096
+ *   n_theta    cells around the circumference, 3 <= n_theta <= 2048 (one workgroup holds a ring)
  *   n_axial    cells along the gap, 2 <= n_axial <= 65536                                */
 typedef struct {
     double R, clearance, length, mu, U, V, p_in, p_out;
@@ -99,10 +99,13 @@ typedef struct {
  *                GAP_SCALARS_PER_COND: one recurrence per condition, still one
  *                synchronized stopping test on the joint residual
  *   warm_start   nonzero: p holds the initial guess p_0; zero: p_0 = 0 (Table 1 step 1)
- *   check_every  iterations between host reads of the device convergence flag (0: 32)  */
+ *   check_every  iterations between host reads of the device convergence flag (0: 32);
+ *                launches after convergence return at once, so the count is exact
+ *   graph        nonzero: each block of check_every iterations is captured once into a
+ *                hipGraph and replayed; zero: plain launches                           */
 typedef struct {
     double omega, eps;
-    int32_t max_iter, precond, neumann, scalars, warm_start, check_every;
+    int32_t max_iter, precond, neumann, scalars, warm_start, check_every, graph, reserved;
 } gap_solver_opts;
 
 /* Result of a solve.  iterations counts completed Table 1 iterations (SpMV + update);
@@ -115,7 +118,8 @@ typedef struct {
 } gap_solve_info;
 
 /* Fill *opts with the defaults: omega 1.6, eps 1e-10, max_iter 100000, ASSOR II,
- * neumann 1, GLOBAL scalars, cold start, check_every 32.  Returns GAP_EINVAL if NULL. */
+ * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1.  Returns GAP_EINVAL if
+ * NULL. */
 gap_status gap_default_opts(gap_solver_opts *opts);
 
 /* Create a handle for one gap (Eq 2.3 geometry, Sec 2.1 grid) that can hold up to
@@ -177,15 +181,14 @@ gap_status gap_read_system(gap_grid_t grid, int32_t k, double *kx, double *kz, d
 /* Measurement support.  While enabled, solve_joint_pcg brackets every launch of the
  * iteration kernels with HIP events on the caller's stream and accumulates the elapsed
  * device time per kernel kind; gap_kernel_stats reads the counts and totals.  Enabling
- * (or re-enabling) resets the counters; disabling keeps them readable.
+ * (or re-enabling) resets the counters; disabling keeps them readable.  While enabled the
+ * iteration blocks are launched without graph capture (opts->graph is ignored), since
+ * events recorded by graph nodes cannot be timed; the results are bitwise the same.
  * Errors: GAP_EINVAL (NULL grid, unknown kernel), GAP_EDEVICE. */
 enum {
-    GAP_KERNEL_SPMV_DOT = 0,    /* u = z + beta u; v = A u; u^T v          (Table 1 steps 9, 3) */
-    GAP_KERNEL_UPDATE = 1,      /* p += alpha u; r -= alpha A u; D^-1 r    (steps 4-5)        */
-    GAP_KERNEL_ASSOR_LOWER = 2, /* (I - w D^-1 L) D^-1 r                   (Eq 3.5)           */
-    GAP_KERNEL_ASSOR_UPPER = 3, /* z = w(2-w)(I - w D^-1 L^T) v; r^T z     (Eq 3.6, step 8)   */
-    GAP_KERNEL_FINALIZE = 4,    /* scalar reductions, alpha/beta, stopping test (Eq 3.9)     */
-    GAP_KERNEL_COUNT = 5
+    GAP_KERNEL_PCG_A = 0,  /* u = z + beta u; u^T A u; beta and the stopping test (Table 1 steps 9, 3, 6) */
+    GAP_KERNEL_PCG_B = 1,  /* alpha; p, r update; z = M^-1 r (ASSOR II sweeps); r^T z, r^T r (steps 4-8) */
+    GAP_KERNEL_COUNT = 2
 };
 gap_status gap_kernel_timing(gap_grid_t grid, int32_t enable);
 gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, double *total_ms);

@@ -23,21 +23,6 @@ struct CondDev {
     int n_cond, n_op;
 };
 
-// Per-solve scalars living in device memory (one record per joint system).
-struct ScalarsDev {
-    double d[GAP_MAXC];      // r^T z of the current iterate, per condition
-    double rr[GAP_MAXC];     // ||r||^2 per condition
-    double ss[GAP_MAXC];     // ||S||^2 per condition
-    double alpha[GAP_MAXC];  // step length used by the update kernel
-    double beta[GAP_MAXC];   // direction update used by the SpMV kernel
-    double rel;              // ||r_G|| / ||S_G||
-    double rel_cond[GAP_MAXC];
-    int iter;                // completed iterations
-    int done;                // nonzero: every kernel of the loop returns at once
-    int status;              // 0 running/converged, -3 no convergence, -4 non-finite
-    int pad;
-};
-
 // Read-only tables and texture samples of one grid.
 struct TablesDev {
     const double *cos_c, *sin_c;   // at theta_i = (i + 1/2) dtheta       [nt]

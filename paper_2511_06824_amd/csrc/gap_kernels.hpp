@@ -151,266 +151,6 @@ __global__ void k_diag_precond(GeomDev g, int kind, double omega, const double* 
 }
 
 // ---------------------------------------------------------------------------------------
-// PCG (Table 1).  Vector arguments point at condition 0; condition c is at offset c * n.
-struct PcgArgs {
-    const double* kx;   // [n_op][n]
-    const double* kz;   // [n_op][n + nt]
-    const double* minv; // [n_op][n] diagonal preconditioner (Jacobi / ASSOR I), or null
-    const double* S;    // [n_cond][n]
-    double* p;          // [n_cond][n] solution (caller memory)
-    double* r;          // [n_cond][n] residual
-    double* u_in;       // search direction of the previous iteration
-    double* u_out;      // search direction of this iteration
-    double* z;          // preconditioned residual
-    double* y;          // ASSOR scratch: D^{-1} r
-    double* w;          // ASSOR scratch: (I - w D^{-1} L) D^{-1} r
-    double* partial;    // [n_q][chunks]
-    ScalarsDev* sc;
-    double omega;
-    int precond;        // 0 Jacobi, 1 ASSOR I, 2 ASSOR II
-};
-
-// Initial residual r0 = S - A p0 (p0 = 0 unless warm), u = 0, and the first half of the
-// preconditioner (y = D^{-1} r0) or the diagonal one (z = M^{-1} r0).
-// partials: 0 ||S||^2, 1 ||r||^2, 2 r.z (diagonal preconditioners only).
-__global__ void k_init(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a, int warm)
-{
-    int c, j0, j1;
-    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
-    const int nt = g.nt, nz = g.nz;
-    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
-    const int o = cd.op[c];
-    const double* kx = a.kx + (size_t)o * n;
-    const double* kz = a.kz + (size_t)o * (n + nt);
-    const double* p = a.p + off;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int j = j0; j < j1; ++j) {
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            const int gi = j * nt + i;
-            const double s = a.S[off + gi];
-            double r = s;
-            if (warm) r = s - apply_A(kx, kz, i, j, nt, nz, [&](int ii, int jj) { return p[jj * nt + ii]; });
-            else a.p[off + gi] = 0.0;
-            a.r[off + gi] = r;
-            a.u_in[off + gi] = 0.0;
-            acc[0] += s * s;
-            acc[1] += r * r;
-            if (a.precond == 2) {
-                a.y[off + gi] = r / diag_at(kx, kz, i, j, nt);
-            } else {
-                const double zz = a.minv[(size_t)o * n + gi] * r;
-                a.z[off + gi] = zz;
-                acc[2] += r * zz;
-            }
-        }
-    }
-    block_sum<3>(acc);
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 3; ++q) a.partial[q * cm.total + blockIdx.x] = acc[q];
-}
-
-// Table 1 steps 9 and 3: u = z + beta u_prev, then v = A u and the partial u^T v.
-__global__ void k_spmv_dot(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a)
-{
-    if (a.sc->done) return;
-    int c, j0, j1;
-    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
-    const int nt = g.nt, nz = g.nz;
-    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
-    const int o = cd.op[c];
-    const double* kx = a.kx + (size_t)o * n;
-    const double* kz = a.kz + (size_t)o * (n + nt);
-    const double beta = a.sc->beta[c];
-    const double* zc = a.z + off;
-    const double* ui = a.u_in + off;
-    auto u = [&](int ii, int jj) { const int q = jj * nt + ii; return zc[q] + beta * ui[q]; };
-    double acc[1] = {0.0};
-    for (int j = j0; j < j1; ++j) {
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            const double uc = u(i, j);
-            const double v = apply_A(kx, kz, i, j, nt, nz, u);
-            a.u_out[off + j * nt + i] = uc;
-            acc[0] += uc * v;
-        }
-    }
-    block_sum<1>(acc);
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = acc[0];
-}
-
-// Table 1 steps 4-5 (and 7 for the diagonal preconditioners): p += alpha u,
-// r -= alpha A u (A u recomputed from u), then y = D^{-1} r (ASSOR II) or z = M^{-1} r.
-// partials: 0 ||r||^2, 1 r.z (diagonal preconditioners).
-__global__ void k_update(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a)
-{
-    if (a.sc->done) return;
-    int c, j0, j1;
-    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
-    const int nt = g.nt, nz = g.nz;
-    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
-    const int o = cd.op[c];
-    const double* kx = a.kx + (size_t)o * n;
-    const double* kz = a.kz + (size_t)o * (n + nt);
-    const double alpha = a.sc->alpha[c];
-    const double* uc = a.u_out + off;
-    auto u = [&](int ii, int jj) { return uc[jj * nt + ii]; };
-    double acc[2] = {0.0, 0.0};
-    for (int j = j0; j < j1; ++j) {
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            const int gi = j * nt + i;
-            const double v = apply_A(kx, kz, i, j, nt, nz, u);
-            a.p[off + gi] += alpha * uc[gi];
-            const double r = a.r[off + gi] - alpha * v;
-            a.r[off + gi] = r;
-            acc[0] += r * r;
-            if (a.precond == 2) {
-                a.y[off + gi] = r / diag_at(kx, kz, i, j, nt);
-            } else {
-                const double zz = a.minv[(size_t)o * n + gi] * r;
-                a.z[off + gi] = zz;
-                acc[1] += r * zz;
-            }
-        }
-    }
-    block_sum<2>(acc);
-    if (threadIdx.x == 0) {
-        a.partial[blockIdx.x] = acc[0];
-        a.partial[cm.total + blockIdx.x] = acc[1];
-    }
-}
-
-// ASSOR II first step (Eq 3.5): w = (I - omega D^{-1} L) y with y = D^{-1} r.
-// L couples (i, j) to (i-1, j) for i > 0, to (0, j) for i = n_theta-1, and to (i, j-1).
-__global__ void k_assor_lower(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a, int check_done)
-{
-    if (check_done && a.sc->done) return;
-    int c, j0, j1;
-    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
-    const int nt = g.nt;
-    const size_t n = (size_t)nt * g.nz, off = (size_t)c * n;
-    const int o = cd.op[c];
-    const double* kx = a.kx + (size_t)o * n;
-    const double* kz = a.kz + (size_t)o * (n + nt);
-    const double* y = a.y + off;
-    const double om = a.omega;
-    for (int j = j0; j < j1; ++j) {
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            const int gi = j * nt + i;
-            double s = 0.0;
-            if (i > 0) s += kx[gi - 1] * y[gi - 1];
-            if (i == nt - 1) s += kx[gi] * y[j * nt];
-            if (j > 0) s += kz[gi] * y[gi - nt];
-            a.w[off + gi] = y[gi] + om / diag_at(kx, kz, i, j, nt) * s;
-        }
-    }
-}
-
-// ASSOR II second step (Eq 3.6): z = w (2 - w)(I - omega D^{-1} L^T) w; partial r.z into
-// slot rz_slot.
-// L^T couples (i, j) to (i+1, j) for i < n_theta-1, to (n_theta-1, j) for i = 0, and to
-// (i, j+1).
-__global__ void k_assor_upper(GeomDev g, CondDev cd, ChunkMap cm, PcgArgs a, int check_done, int rz_slot)
-{
-    if (check_done && a.sc->done) return;
-    int c, j0, j1;
-    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
-    const int nt = g.nt, nz = g.nz;
-    const size_t n = (size_t)nt * nz, off = (size_t)c * n;
-    const int o = cd.op[c];
-    const double* kx = a.kx + (size_t)o * n;
-    const double* kz = a.kz + (size_t)o * (n + nt);
-    const double* w = a.w + off;
-    const double om = a.omega;
-    const double scale = om * (2.0 - om);
-    double acc[1] = {0.0};
-    for (int j = j0; j < j1; ++j) {
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            const int gi = j * nt + i;
-            double s = 0.0;
-            if (i < nt - 1) s += kx[gi] * w[gi + 1];
-            if (i == 0) s += kx[j * nt + nt - 1] * w[j * nt + nt - 1];
-            if (j < nz - 1) s += kz[gi + nt] * w[gi + nt];
-            const double zz = scale * (w[gi] + om / diag_at(kx, kz, i, j, nt) * s);
-            a.z[off + gi] = zz;
-            acc[0] += a.r[off + gi] * zz;
-        }
-    }
-    block_sum<1>(acc);
-    if (threadIdx.x == 0) a.partial[rz_slot * cm.total + blockIdx.x] = acc[0];
-}
-
-// ---------------------------------------------------------------------------------------
-// Finalize kernels: one block adds the chunk partials of every condition in a fixed order
-// and updates the device scalars.
-__device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& cm, int c)
-{
-    double v[1] = {0.0};
-    for (int b = threadIdx.x; b < cm.per_cond; b += blockDim.x) v[0] += part[c * cm.per_cond + b];
-    block_sum<1>(v);
-    return v[0];   // valid in thread 0
-}
-
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
-
-__global__ void k_finalize(ChunkMap cm, int n_cond, const double* __restrict__ part, ScalarsDev* sc,
-                           int mode, int per_cond_scalars, double eps, int max_iter)
-{
-    if (mode != FIN_INIT && sc->done) return;
-    __shared__ double q0[GAP_MAXC], q1[GAP_MAXC], q2[GAP_MAXC];
-    for (int c = 0; c < n_cond; ++c) {
-        const double a0 = cond_sum(part, cm, c);
-        const double a1 = (mode != FIN_ALPHA) ? cond_sum(part + cm.total, cm, c) : 0.0;
-        const double a2 = (mode == FIN_INIT) ? cond_sum(part + 2 * cm.total, cm, c) : 0.0;
-        if (threadIdx.x == 0) { q0[c] = a0; q1[c] = a1; q2[c] = a2; }
-    }
-    if (threadIdx.x != 0) return;
-    bool bad = false;
-    if (mode == FIN_ALPHA) {
-        double num = 0.0, den = 0.0;
-        for (int c = 0; c < n_cond; ++c) { num += sc->d[c]; den += q0[c]; }
-        for (int c = 0; c < n_cond; ++c) {
-            const double al = per_cond_scalars ? sc->d[c] / q0[c] : num / den;
-            sc->alpha[c] = al;
-            bad |= !finite_d(al);
-        }
-        if (bad) { sc->status = -4; sc->done = 1; }
-        return;
-    }
-    // FIN_INIT: q0 = ||S||^2, q1 = ||r||^2, q2 = r.z ;  FIN_BETA: q0 = ||r||^2, q1 = r.z
-    const double* rr = (mode == FIN_INIT) ? q1 : q0;
-    const double* rz = (mode == FIN_INIT) ? q2 : q1;
-    if (mode == FIN_INIT) {
-        for (int c = 0; c < n_cond; ++c) { sc->ss[c] = q0[c]; sc->beta[c] = 0.0; sc->alpha[c] = 0.0; }
-        sc->iter = 0;
-        sc->status = 0;
-        sc->done = 0;
-    } else {
-        double num = 0.0, den = 0.0;
-        for (int c = 0; c < n_cond; ++c) { num += rz[c]; den += sc->d[c]; }
-        for (int c = 0; c < n_cond; ++c) {
-            const double be = per_cond_scalars ? rz[c] / sc->d[c] : num / den;
-            sc->beta[c] = be;
-            bad |= !finite_d(be);
-        }
-        sc->iter += 1;
-    }
-    double rs = 0.0, ss = 0.0;
-    for (int c = 0; c < n_cond; ++c) {
-        sc->d[c] = rz[c];
-        sc->rr[c] = rr[c];
-        rs += rr[c];
-        ss += sc->ss[c];
-        const double sref = sc->ss[c] > 0.0 ? sc->ss[c] : 1.0;
-        sc->rel_cond[c] = sqrt(rr[c] / sref);
-    }
-    const double rel = sqrt(rs / (ss > 0.0 ? ss : 1.0));
-    sc->rel = rel;
-    bad |= !finite_d(rel);
-    if (bad) { sc->status = -4; sc->done = 1; }
-    else if (rel <= eps) { sc->done = 1; }
-    else if (sc->iter >= max_iter) { sc->status = -3; sc->done = 1; }
-}
-
-// ---------------------------------------------------------------------------------------
 // Force and moment integration (step III) with the cavitation rule; partials 0..3 are
 // Fx, Fy, Mx, My per chunk before the factor dA.
 __device__ __forceinline__ double peff(double p, int cav, double pc) { return (cav && p < pc) ? pc : p; }
@@ -451,6 +191,14 @@ __global__ void k_forces(GeomDev g, CondDev cd, ChunkMap cm, TablesDev tb, const
     block_sum<4>(acc);
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) partial[q * cm.total + blockIdx.x] = acc[q];
+}
+
+__device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& cm, int c)
+{
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < cm.per_cond; b += blockDim.x) v[0] += part[c * cm.per_cond + b];
+    block_sum<1>(v);
+    return v[0];   // valid in thread 0
 }
 
 __global__ void k_forces_finalize(ChunkMap cm, int n_cond, double dA, const double* __restrict__ part,

@@ -1,0 +1,504 @@
+// Fused PCG iteration kernels (Table 1 with ASSOR II, Eq 3.4-3.6) for gfx950, FP64.
+//
+// Two kernels per iteration:
+//   A(j): beta from the previous r.z sums; stopping test (Eq 3.9); u_j = z_j + beta u_{j-1};
+//         partial u_j^T A u_j.
+//   B(j): alpha = d_j / (u_j^T A u_j); p += alpha u_j; r_{j+1} = r_j - alpha A u_j (A u_j
+//         recomputed from u_j); z_{j+1} = M^{-1} r_{j+1}; partials r.z and r.r.
+//   B in "init" mode computes r_0 = S - A p_0 and z_0 instead.
+//
+// Work decomposition: a workgroup owns the whole ring of one condition (all n_theta
+// columns; thread t handles columns t, t + NT, ..., t + (Q-1) NT) and marches over a chunk
+// of consecutive rows.  Ring neighbours come from LDS, axial neighbours from registers of
+// the previous/next row, so the periodic wrap and the ASSOR split of the wrap entries
+// (east wrap of the last column in L, west wrap of the first column in L^T) stay inside one
+// workgroup.  The chunk of rows [j0, j1) reads one or two halo rows on each side.
+//
+// Scalars: every workgroup reduces the per-chunk partial sums it needs at its start, in a
+// fixed order, so all workgroups of a launch derive identical alpha / beta / stopping
+// decisions without atomics or an extra launch; workgroup 0 publishes the host-visible
+// record.  Iteration indices live in device memory (iter_a read by A and written by B,
+// iter_b read by B and written by A), so the launches take identical arguments every
+// iteration and can be replayed from a captured graph.
+#pragma once
+
+#include "gap_device.hpp"
+
+struct PcgScalars {
+    int iter_a;                 // iteration index the next A launch runs (written by B, init)
+    int iter_b;                 // iteration index the next B launch runs (written by A)
+    int done;                   // nonzero: every launch returns at once
+    int status;                 // 0, -3 (no convergence), -4 (non-finite)
+    int iterations;             // completed iterations (written by A)
+    int pad;
+    double rel;                 // ||r_G|| / ||S_G|| of the last completed iteration
+    double rel_cond[GAP_MAXC];  // per condition
+};
+
+struct PcgDev {
+    // operator (face conductances) and diagonal preconditioner, per distinct operator
+    const double* kx;           // [n_op][n]
+    const double* kz;           // [n_op][n + nt]
+    const double* minv;         // [n_op][n]  (Jacobi / ASSOR I), or null
+    // vectors, condition-major
+    const double* S;            // [n_cond][n]
+    double* p;                  // [n_cond][n]  caller memory
+    double* r[2];               // residual, ping-pong by iteration parity
+    double* u[2];               // search direction, ping-pong by iteration parity
+    double* z;                  // preconditioned residual
+    // partial sums, one slot per chunk: slot = c * chunks + k
+    double* part_rz[2];         // r.z, parity of the iteration that consumes it as d_j
+    double* part_rr;            // ||r||^2
+    double* part_ss;            // ||S||^2 (init)
+    double* part_uau;           // u^T A u
+    PcgScalars* sc;
+    int op[GAP_MAXC];
+    int nt, nz, n_cond;
+    int chunks_a, rows_a;       // row chunks per condition of the A launch
+    int chunks_b, rows_b;       // row chunks per condition of the B launches
+    double omega, eps;
+    int max_iter, per_cond, warm, precond;   // precond: 0 Jacobi, 1 ASSOR I, 2 ASSOR II
+};
+
+// Block -> (condition, chunk): consecutive blocks take the conditions of one chunk row, so
+// the conditions that share an operator read its face conductances at about the same time
+// (the repeats are served by the caches).  slot = c * chunks + k indexes the partial sums.
+__device__ __forceinline__ void pcg_chunk(int b, int n_cond, int chunks, int rows, int nz, int& c, int& j0,
+                                          int& j1, int& slot)
+{
+    const int k = b / n_cond;
+    c = b - k * n_cond;
+    j0 = k * rows;
+    j1 = min(j0 + rows, nz);
+    slot = c * chunks + k;
+}
+
+// Per-condition sums of up to 4 partial arrays, in a fixed order: wave w handles
+// conditions w, w + NW, ...; lanes stride over the chunk slots, then a fixed shuffle tree.
+// Results land in out[q][c] (shared memory), valid after the trailing barrier.
+template <int NT, int NQ>
+__device__ __forceinline__ void cond_sums(int n_cond, const int (&chunks)[NQ], const double* const (&src)[NQ],
+                                          double (*out)[GAP_MAXC])
+{
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c = w; c < n_cond; c += NW) {
+        double v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            v[q] = 0.0;
+            for (int k = lane; k < chunks[q]; k += 64) v[q] += src[q][c * chunks[q] + k];
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) out[q][c] = v[q];
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of NV values over the workgroup (fixed order), result valid in thread 0.
+template <int NT, int NV>
+__device__ __forceinline__ void wg_sum(double (&v)[NV])
+{
+    constexpr int NW = NT / 64;
+    __shared__ double part[NV][NW];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) part[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = part[k][0];
+            for (int i = 1; i < NW; ++i) s += part[k][i];
+            v[k] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// A(j): u = z + beta u_prev, partial u^T A u.
+template <int NT, int Q>
+__global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
+{
+    if (a.sc->done) return;
+    int c, j0, j1, slot;
+    pcg_chunk(blockIdx.x, a.n_cond, a.chunks_a, a.rows_a, a.nz, c, j0, j1, slot);
+    const int j = a.sc->iter_a;
+    const int nt = a.nt, nz = a.nz;
+    const size_t n = (size_t)nt * nz;
+
+    // ---- scalars: beta_{j-1} = d_j / d_{j-1}, stopping test on ||r_j|| -----------------
+    __shared__ double sums[4][GAP_MAXC];
+    {
+        const double* src[4] = {a.part_rz[j & 1], a.part_rz[(j + 1) & 1], a.part_rr, a.part_ss};
+        const int cnt[4] = {a.chunks_b, a.chunks_b, a.chunks_b, a.chunks_b};
+        cond_sums<NT, 4>(a.n_cond, cnt, src, sums);
+    }
+    double dn = 0.0, dp = 0.0, rr = 0.0, ss = 0.0;
+    for (int k = 0; k < a.n_cond; ++k) {
+        dn += sums[0][k];
+        dp += sums[1][k];
+        rr += sums[2][k];
+        ss += sums[3][k];
+    }
+    const double rel = sqrt(rr / (ss > 0.0 ? ss : 1.0));
+    double beta = 0.0;
+    if (j > 0) beta = a.per_cond ? sums[0][c] / sums[1][c] : dn / dp;
+    bool bad = !finite_d(rel) || !finite_d(beta);
+    if (a.per_cond && j > 0)
+        for (int k = 0; k < a.n_cond; ++k) bad |= !finite_d(sums[0][k] / sums[1][k]);
+    const bool stop = bad || rel <= a.eps || j >= a.max_iter;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        PcgScalars* s = a.sc;
+        s->iterations = j;
+        s->rel = rel;
+        for (int k = 0; k < a.n_cond; ++k) {
+            const double sk = sums[3][k] > 0.0 ? sums[3][k] : 1.0;
+            s->rel_cond[k] = sqrt(sums[2][k] / sk);
+        }
+        s->iter_b = j;
+        s->status = bad ? -4 : (rel <= a.eps ? 0 : (j >= a.max_iter ? -3 : 0));
+        if (stop) s->done = 1;
+    }
+    if (stop) return;
+
+    // ---- march over the rows of the chunk ----------------------------------------------
+    extern __shared__ double lds[];
+    double* su = lds;             // [2][nt]  u of the current row, by row parity
+    double* skx = lds + 2 * nt;   // [2][nt]  kx of the current row
+    const int op = a.op[c];
+    const double* kx = a.kx + (size_t)op * n;
+    const double* kz = a.kz + (size_t)op * (n + nt);
+    const double* zc = a.z + (size_t)c * n;
+    const double* ui = a.u[(j + 1) & 1] + (size_t)c * n;
+    double* uo = a.u[j & 1] + (size_t)c * n;
+    const bool first = (j == 0);
+    const int t = threadIdx.x;
+
+    // registers: u of rows s-1, s, s+1; face conductances of faces s, s+1; kx of row s;
+    // and the loads of the next row step, issued one step ahead
+    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q];
+    double nz_[Q], nu_[Q], nkx[Q], nkz[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = t + q * NT;
+        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = 0.0;
+        nz_[q] = nu_[q] = nkx[q] = nkz[q] = 0.0;
+        if (i < nt) {
+            if (j0 > 0) {
+                const size_t g = (size_t)(j0 - 1) * nt + i;
+                um[q] = first ? zc[g] : zc[g] + beta * ui[g];
+            }
+            size_t g = (size_t)j0 * nt + i;
+            uc[q] = first ? zc[g] : zc[g] + beta * ui[g];
+            kzS[q] = kz[g];
+            kxc[q] = kx[g];
+            g += nt;
+            kzN[q] = kz[g];
+            if (j0 + 1 < nz) {
+                up[q] = first ? zc[g] : zc[g] + beta * ui[g];
+            }
+        }
+    }
+    double acc = 0.0;
+    for (int s = j0; s < j1; ++s) {
+        const int buf = s & 1;
+        // issue the loads of the next row step (row s + 2 of u, row s + 1 of kx, face s + 2)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            if (i < nt && s + 1 < j1) {
+                const size_t g1 = (size_t)(s + 1) * nt + i;
+                nkx[q] = kx[g1];
+                nkz[q] = kz[g1 + nt];
+                if (s + 2 < nz) {
+                    nz_[q] = zc[g1 + nt];
+                    if (!first) nu_[q] = ui[g1 + nt];
+                }
+            }
+            if (i < nt) {
+                su[buf * nt + i] = uc[q];
+                skx[buf * nt + i] = kxc[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            if (i < nt) {
+                const int iw = i ? i - 1 : nt - 1;
+                const int ie = (i + 1 < nt) ? i + 1 : 0;
+                const double kW = skx[buf * nt + iw];
+                const double D = ((kxc[q] + kW) + kzS[q]) + kzN[q];
+                double v = D * uc[q] - kxc[q] * su[buf * nt + ie] - kW * su[buf * nt + iw];
+                if (s > 0) v -= kzS[q] * um[q];
+                if (s < nz - 1) v -= kzN[q] * up[q];
+                acc += uc[q] * v;
+                uo[(size_t)s * nt + i] = uc[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            um[q] = uc[q];
+            uc[q] = up[q];
+            kzS[q] = kzN[q];
+            kzN[q] = nkz[q];
+            kxc[q] = nkx[q];
+            up[q] = (s + 2 < nz) ? (first ? nz_[q] : nz_[q] + beta * nu_[q]) : 0.0;
+        }
+    }
+    double v1[1] = {acc};
+    wg_sum<NT, 1>(v1);
+    if (threadIdx.x == 0) a.part_uau[slot] = v1[0];
+}
+
+// ---------------------------------------------------------------------------------------
+// B(j) (INIT = false) or the initial residual (INIT = true).
+template <int NT, int Q, bool INIT>
+__global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev a)
+{
+    if (!INIT && a.sc->done) return;
+    int c, j0, j1, slot;
+    pcg_chunk(blockIdx.x, a.n_cond, a.chunks_b, a.rows_b, a.nz, c, j0, j1, slot);
+    const int j = INIT ? -1 : a.sc->iter_b;
+    const int nt = a.nt, nz = a.nz;
+    const size_t n = (size_t)nt * nz;
+
+    // ---- scalars: alpha_j = d_j / (u_j^T A u_j) ------------------------------------------
+    double alpha = 1.0;
+    if (!INIT) {
+        __shared__ double sums[2][GAP_MAXC];
+        const double* src[2] = {a.part_rz[j & 1], a.part_uau};
+        const int cnt[2] = {a.chunks_b, a.chunks_a};
+        cond_sums<NT, 2>(a.n_cond, cnt, src, sums);
+        double num = 0.0, den = 0.0;
+        bool bad = false;
+        for (int k = 0; k < a.n_cond; ++k) {
+            num += sums[0][k];
+            den += sums[1][k];
+            if (a.per_cond) bad |= !finite_d(sums[0][k] / sums[1][k]);
+        }
+        alpha = a.per_cond ? sums[0][c] / sums[1][c] : num / den;
+        bad |= !finite_d(alpha);
+        if (bad) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                a.sc->status = -4;
+                a.sc->done = 1;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->iter_a = j + 1;
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->iter_a = 0;
+        a.sc->iter_b = 0;
+        a.sc->done = 0;
+        a.sc->status = 0;
+        a.sc->iterations = 0;
+    }
+
+    const bool spmv = !INIT || a.warm;
+    const bool assor = (a.precond == 2);
+    const int op = a.op[c];
+    const double* kx = a.kx + (size_t)op * n;
+    const double* kz = a.kz + (size_t)op * (n + nt);
+    const double* mv = assor ? nullptr : a.minv + (size_t)op * n;
+    const double* uu = (INIT ? a.p : a.u[j & 1]) + (size_t)c * n;
+    const double* rin = (INIT ? a.S : a.r[j & 1]) + (size_t)c * n;
+    double* rout = a.r[(j + 1) & 1] + (size_t)c * n;
+    double* pp = a.p + (size_t)c * n;
+    double* zz = a.z + (size_t)c * n;
+    const double om = a.omega;
+    const double scale = om * (2.0 - om);
+
+    extern __shared__ double lds[];
+    double* su = lds;             // u row s
+    double* skx = lds + nt;       // kx row s
+    double* sy = lds + 2 * nt;    // y = D^-1 r' row s
+    double* sv = lds + 3 * nt;    // [2][nt]: (I - w D^-1 L) y, rows by parity
+
+    // rows visited: the chunk plus, for the ASSOR sweeps, one halo row on each side
+    const int s_begin = assor ? max(j0 - 1, 0) : j0;
+    const int s_last = assor ? min(j1, nz - 1) : j1 - 1;
+    const bool updates_p = !INIT || !a.warm;   // B writes p += alpha u; cold init writes p = 0
+
+    const int t = threadIdx.x;
+    // state of rows s-1, s, s+1 and of the row below (for the lagged Eq 3.6 sweep)
+    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], rc[Q], pc[Q];
+    double yprev[Q], vprev[Q], dinvprev[Q], kxprev[Q], rpprev[Q];
+    // loads of the next row step, issued one step ahead
+    double nu[Q], nkx[Q], nkz[Q], nr[Q], np[Q];
+    double kxwrap_prev = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = t + q * NT;
+        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = rc[q] = pc[q] = 0.0;
+        yprev[q] = vprev[q] = dinvprev[q] = kxprev[q] = rpprev[q] = 0.0;
+        nu[q] = nkx[q] = nkz[q] = nr[q] = np[q] = 0.0;
+        if (i < nt) {
+            const size_t g = (size_t)s_begin * nt + i;
+            if (spmv) {
+                if (s_begin > 0) um[q] = uu[g - nt];
+                uc[q] = uu[g];
+                if (s_begin + 1 < nz) up[q] = uu[g + nt];
+            }
+            kzS[q] = kz[g];
+            kzN[q] = kz[g + nt];
+            kxc[q] = kx[g];
+            rc[q] = rin[g];
+            if (!INIT && s_begin >= j0) pc[q] = pp[g];
+        }
+    }
+    double acc_rz = 0.0, acc_rr = 0.0, acc_ss = 0.0;
+
+    for (int s = s_begin; s <= s_last; ++s) {
+        const bool own = (s >= j0 && s < j1);
+        // issue the loads of row s + 1 (u of row s + 2, face s + 2)
+        if (s + 1 <= s_last) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int i = t + q * NT;
+                if (i < nt) {
+                    const size_t g1 = (size_t)(s + 1) * nt + i;
+                    nu[q] = (spmv && s + 2 < nz) ? uu[g1 + nt] : 0.0;
+                    nkx[q] = kx[g1];
+                    nkz[q] = kz[g1 + nt];
+                    nr[q] = rin[g1];
+                    np[q] = (!INIT && s + 1 >= j0 && s + 1 < j1) ? pp[g1] : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            if (i < nt) {
+                su[i] = uc[q];
+                skx[i] = kxc[q];
+            }
+        }
+        __syncthreads();
+        const double kxwrap = skx[nt - 1];
+        double rp[Q], dinv[Q], y[Q], kWq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            rp[q] = dinv[q] = y[q] = kWq[q] = 0.0;
+            if (i < nt) {
+                const size_t g = (size_t)s * nt + i;
+                const int iw = i ? i - 1 : nt - 1;
+                const int ie = (i + 1 < nt) ? i + 1 : 0;
+                const double kW = skx[iw];
+                kWq[q] = kW;   // skx may be rewritten by the next row before the sweep below
+                const double D = ((kxc[q] + kW) + kzS[q]) + kzN[q];
+                const double r0 = rc[q];
+                double r1 = r0;
+                if (spmv) {
+                    double v = D * uc[q] - kxc[q] * su[ie] - kW * su[iw];
+                    if (s > 0) v -= kzS[q] * um[q];
+                    if (s < nz - 1) v -= kzN[q] * up[q];
+                    r1 = r0 - alpha * v;
+                }
+                rp[q] = r1;
+                dinv[q] = 1.0 / D;
+                if (own) {
+                    rout[g] = r1;
+                    acc_rr += r1 * r1;
+                    if (INIT) acc_ss += r0 * r0;
+                    if (updates_p) pp[g] = INIT ? 0.0 : pc[q] + alpha * uc[q];
+                    if (!assor) {
+                        const double zv = mv[g] * r1;
+                        zz[g] = zv;
+                        acc_rz += r1 * zv;
+                    }
+                }
+                if (assor) {
+                    y[q] = r1 * dinv[q];
+                    sy[i] = y[q];
+                }
+            }
+        }
+        if (assor) {
+            __syncthreads();
+            double* svc = sv + (s & 1) * nt;
+            const double* svp = sv + ((s + 1) & 1) * nt;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int i = t + q * NT;
+                if (i < nt) {
+                    // Eq 3.5: v = y + w D^-1 (couplings to west, south and the east wrap)
+                    double lo = 0.0;
+                    if (i > 0) lo += kWq[q] * sy[i - 1];
+                    if (i == nt - 1) lo += kxc[q] * sy[0];
+                    if (s > 0) lo += kzS[q] * yprev[q];
+                    const double v = y[q] + om * dinv[q] * lo;
+                    svc[i] = v;
+                    // Eq 3.6 for the row below: z = w(2-w)(v + w D^-1 (east, north, west wrap))
+                    if (s - 1 >= j0 && s - 1 < j1) {
+                        double hi = kzS[q] * v;
+                        if (i < nt - 1) hi += kxprev[q] * svp[i + 1];
+                        if (i == 0) hi += kxwrap_prev * svp[nt - 1];
+                        const double zv = scale * (vprev[q] + om * dinvprev[q] * hi);
+                        zz[(size_t)(s - 1) * nt + i] = zv;
+                        acc_rz += rpprev[q] * zv;
+                    }
+                    yprev[q] = y[q];
+                    vprev[q] = v;
+                }
+            }
+        } else {
+            __syncthreads();   // the LDS rows are rewritten by the next row step
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            um[q] = uc[q];
+            uc[q] = up[q];
+            up[q] = nu[q];
+            kzS[q] = kzN[q];
+            kzN[q] = nkz[q];
+            dinvprev[q] = dinv[q];
+            kxprev[q] = kxc[q];
+            kxc[q] = nkx[q];
+            rpprev[q] = rp[q];
+            rc[q] = nr[q];
+            pc[q] = np[q];
+        }
+        kxwrap_prev = kxwrap;
+    }
+    // last row of the ring: no northern neighbour
+    if (assor && j1 == nz) {
+        __syncthreads();
+        const double* svp = sv + ((nz - 1) & 1) * nt;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            if (i < nt) {
+                double hi = 0.0;
+                if (i < nt - 1) hi += kxprev[q] * svp[i + 1];
+                if (i == 0) hi += kxwrap_prev * svp[nt - 1];
+                const double zv = scale * (vprev[q] + om * dinvprev[q] * hi);
+                zz[(size_t)(nz - 1) * nt + i] = zv;
+                acc_rz += rpprev[q] * zv;
+            }
+        }
+    }
+    double v3[3] = {acc_rz, acc_rr, acc_ss};
+    wg_sum<NT, 3>(v3);
+    if (threadIdx.x == 0) {
+        a.part_rz[(j + 1) & 1][slot] = v3[0];
+        a.part_rr[slot] = v3[1];
+        if (INIT) a.part_ss[slot] = v3[2];
+    }
+}

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "gap_kernels.hpp"
+#include "gap_pcg.hpp"
 
 namespace {
 
@@ -44,7 +45,7 @@ gap_status fail(gap_status s, const char* fmt, ...)
 bool is_finite(double x) { return std::isfinite(x); }
 
 constexpr int kTargetChunks = 2048;
-constexpr int kMaxThetaCells = 4096;
+constexpr int kMaxThetaCells = 2048;
 constexpr int kMaxAxialCells = 65536;
 
 ChunkMap make_chunks(int nz, int n_cond)
@@ -56,6 +57,94 @@ ChunkMap make_chunks(int nz, int n_cond)
     cm.per_cond = (nz + cm.rows - 1) / cm.rows;
     cm.total = cm.per_cond * n_cond;
     return cm;
+}
+
+// Threads per workgroup and ring columns per thread for a ring of nt cells.
+void pcg_shape(int nt, int& NT, int& Q)
+{
+    if (nt <= 64) { NT = 64; Q = 1; }
+    else if (nt <= 128) { NT = 128; Q = 1; }
+    else if (nt <= 256) { NT = 256; Q = 1; }
+    else if (nt <= 512) { NT = 512; Q = 1; }
+    else if (nt <= 1024) { NT = 512; Q = 2; }
+    else { NT = 512; Q = 4; }      // n_theta <= 2048 (validated at create)
+}
+
+// Dynamic LDS of the A kernel (u and kx rows, double-buffered) and of the B kernels
+// (u, kx, y rows and two rows of the first ASSOR sweep).
+size_t pcg_lds_bytes(int which, int nt) { return (size_t)(which == 0 ? 4 : 5) * nt * sizeof(double); }
+
+// Row chunks per condition: as many workgroups as the device holds at once (occupancy x CUs),
+// so that one launch runs in a single round.
+void pcg_chunks(int nz, int n_cond, int slots, int& chunks, int& rows)
+{
+    int per = slots / n_cond;
+    if (per < 1) per = 1;
+    if (per > nz) per = nz;
+    rows = (nz + per - 1) / per;
+    chunks = (nz + rows - 1) / rows;
+}
+
+template <int NT, int Q>
+const void* pcg_fn(int which)
+{
+    return which == 0 ? (const void*)k_pcg_a<NT, Q>
+         : which == 1 ? (const void*)k_pcg_b<NT, Q, false> : (const void*)k_pcg_b<NT, Q, true>;
+}
+
+template <int NT, int Q>
+hipError_t pcg_prepare_t(int which, int nt, int* occupancy)
+{
+    const void* fn = pcg_fn<NT, Q>(which);
+    const size_t lds = pcg_lds_bytes(which, nt);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds);
+    if (e != hipSuccess) return e;
+    *occupancy = nb > 0 ? nb : 1;
+    return hipSuccess;
+}
+
+template <int NT, int Q>
+hipError_t launch_pcg_t(int which, const PcgDev& a, hipStream_t st)
+{
+    const size_t lds = pcg_lds_bytes(which, a.nt);
+    const int blocks = a.n_cond * (which == 0 ? a.chunks_a : a.chunks_b);
+    if (which == 0) hipLaunchKernelGGL((k_pcg_a<NT, Q>), dim3(blocks), dim3(NT), lds, st, a);
+    else if (which == 1) hipLaunchKernelGGL((k_pcg_b<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL((k_pcg_b<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
+
+// Set the LDS attribute of a kernel and read how many of its workgroups fit on one CU.
+hipError_t pcg_prepare(int which, int nt, int* occupancy)
+{
+    int NT_, Q_;
+    pcg_shape(nt, NT_, Q_);
+    switch (NT_ * 16 + Q_) {
+    case 64 * 16 + 1: return pcg_prepare_t<64, 1>(which, nt, occupancy);
+    case 128 * 16 + 1: return pcg_prepare_t<128, 1>(which, nt, occupancy);
+    case 256 * 16 + 1: return pcg_prepare_t<256, 1>(which, nt, occupancy);
+    case 512 * 16 + 1: return pcg_prepare_t<512, 1>(which, nt, occupancy);
+    case 512 * 16 + 2: return pcg_prepare_t<512, 2>(which, nt, occupancy);
+    default: return pcg_prepare_t<512, 4>(which, nt, occupancy);
+    }
+}
+
+// which: 0 = A(j), 1 = B(j), 2 = initial residual.
+hipError_t launch_pcg(int which, const PcgDev& a, hipStream_t st)
+{
+    int NT_, Q_;
+    pcg_shape(a.nt, NT_, Q_);
+    switch (NT_ * 16 + Q_) {
+    case 64 * 16 + 1: return launch_pcg_t<64, 1>(which, a, st);
+    case 128 * 16 + 1: return launch_pcg_t<128, 1>(which, a, st);
+    case 256 * 16 + 1: return launch_pcg_t<256, 1>(which, a, st);
+    case 512 * 16 + 1: return launch_pcg_t<512, 1>(which, a, st);
+    case 512 * 16 + 2: return launch_pcg_t<512, 2>(which, a, st);
+    default: return launch_pcg_t<512, 4>(which, a, st);
+    }
 }
 
 }  // namespace
@@ -75,10 +164,15 @@ struct gap_grid_s {
     double *trig = nullptr;                                  // cos_c, sin_c, cos_e, sin_e
     double *tex = nullptr;                                   // centres, east faces, axial faces
     double *kx = nullptr, *kz = nullptr, *minv = nullptr;
-    double *S = nullptr, *r = nullptr, *u0 = nullptr, *u1 = nullptr, *z = nullptr, *y = nullptr, *w = nullptr;
-    double *partial = nullptr;
-    ScalarsDev *sc = nullptr;
-    ScalarsDev *sc_host = nullptr;                           // pinned
+    double *S = nullptr, *r0 = nullptr, *r1 = nullptr, *u0 = nullptr, *u1 = nullptr, *z = nullptr;
+    double *partial = nullptr;                               // force-integration partials
+    double *pcg_part = nullptr;                              // PCG partials: 5 arrays of max_cond * max_pcg_chunks
+    size_t pcg_part_stride = 0;
+    PcgScalars *sc = nullptr;
+    PcgScalars *sc_host = nullptr;                           // pinned
+    int cus = 256;                                           // compute units of the device
+    int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
+    int lds_max = 65536;                                     // bytes of LDS one workgroup may use
     int minv_kind = -1;
     double minv_omega = 0.0;
     // kernel timing (measurement support)
@@ -88,6 +182,11 @@ struct gap_grid_s {
     int ev_used = 0;
     long long launches[GAP_KERNEL_COUNT] = {0};
     double total_ms[GAP_KERNEL_COUNT] = {0};
+    // captured iteration block (graph replay)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PcgDev exec_args{};
+    int exec_block = 0;
 
     TablesDev tables() const
     {
@@ -107,9 +206,12 @@ namespace {
 
 void release(gap_grid_t g)
 {
-    double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r, g->u0, g->u1, g->z, g->y, g->w, g->partial};
+    double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->partial,
+                      g->pcg_part};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
     if (g->sc) (void)hipFree(g->sc);
     if (g->sc_host) (void)hipHostFree(g->sc_host);
@@ -200,6 +302,8 @@ gap_status gap_default_opts(gap_solver_opts* o)
     o->scalars = GAP_SCALARS_GLOBAL;
     o->warm_start = 0;
     o->check_every = 32;
+    o->graph = 1;
+    o->reserved = 0;
     return GAP_OK;
 }
 
@@ -264,21 +368,48 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     ALLOC(g->tex, 2 * n + (g->nz + 1) * nt);
     ALLOC(g->kx, g->max_op * n);
     ALLOC(g->kz, g->max_op * (n + nt));
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || g->cus < 1)
+            g->cus = 256;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            g->lds_max = lds;
+        int NT, Q;
+        pcg_shape(g->nt, NT, Q);
+        const size_t need = pcg_lds_bytes(1, NT * Q) + 2048;
+        if (need > (size_t)g->lds_max) {
+            release(g);
+            return fail(GAP_EINVAL, "n_theta = %d needs %zu bytes of LDS per workgroup, the device allows %d",
+                        geom->n_theta, need, g->lds_max);
+        }
+    }
+    // PCG partial sums: at most one slot per row of every condition
+    const size_t max_pcg = (size_t)max_cond * g->nz;
+    g->pcg_part_stride = max_pcg;
+    for (int which = 0; which < 3; ++which) {
+        hipError_t pe = pcg_prepare(which, g->nt, &g->occ[which]);
+        if (pe != hipSuccess) {
+            release(g);
+            return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(pe));
+        }
+    }
     ALLOC(g->S, max_cond * n);
-    ALLOC(g->r, max_cond * n);
+    ALLOC(g->r0, max_cond * n);
+    ALLOC(g->r1, max_cond * n);
     ALLOC(g->u0, max_cond * n);
     ALLOC(g->u1, max_cond * n);
     ALLOC(g->z, max_cond * n);
-    ALLOC(g->y, max_cond * n);
-    ALLOC(g->w, max_cond * n);
     ALLOC(g->partial, 4 * max_chunks);
+    ALLOC(g->pcg_part, 5 * max_pcg);
 #undef ALLOC
-    if (hipMalloc((void**)&g->sc, sizeof(ScalarsDev)) != hipSuccess) {
+    if (hipMalloc((void**)&g->sc, sizeof(PcgScalars)) != hipSuccess) {
         g->sc = nullptr;
         release(g);
         return fail(GAP_ENOMEM, "hipMalloc of the scalar block failed");
     }
-    if (hipHostMalloc((void**)&g->sc_host, sizeof(ScalarsDev), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&g->sc_host, sizeof(PcgScalars), hipHostMallocDefault) != hipSuccess) {
         g->sc_host = nullptr;
         release(g);
         return fail(GAP_ENOMEM, "hipHostMalloc of the scalar block failed");
@@ -294,7 +425,8 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     }
     hipError_t e = hipMemcpy(g->trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(g->tex, 0, (2 * n + (g->nz + 1) * nt) * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->sc, 0, sizeof(ScalarsDev));
+    if (e == hipSuccess) e = hipMemset(g->sc, 0, sizeof(PcgScalars));
+    if (e == hipSuccess) e = hipMemset(g->pcg_part, 0, 5 * g->pcg_part_stride * sizeof(double));
     if (e != hipSuccess) {
         release(g);
         return fail(GAP_EDEVICE, "initialising tables: %s", hipGetErrorString(e));
@@ -394,7 +526,6 @@ gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, ga
     const int check_every = o->check_every ? o->check_every : 32;
     hipStream_t st = (hipStream_t)stream;
     const GeomDev& gd = g->gd;
-    const ChunkMap cm = g->cm;
 
     if (o->precond != GAP_PRECOND_ASSOR2 && (g->minv_kind != o->precond || g->minv_omega != o->omega)) {
         if (!g->minv) {
@@ -408,93 +539,116 @@ gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, ga
         g->minv_omega = o->omega;
     }
 
-    PcgArgs a;
+    PcgDev a{};
     a.kx = g->kx;
     a.kz = g->kz;
     a.minv = g->minv;
     a.S = g->S;
     a.p = p;
-    a.r = g->r;
-    a.u_in = g->u0;
-    a.u_out = g->u1;
+    a.r[0] = g->r0;
+    a.r[1] = g->r1;
+    a.u[0] = g->u0;
+    a.u[1] = g->u1;
     a.z = g->z;
-    a.y = g->y;
-    a.w = g->w;
-    a.partial = g->partial;
+    const size_t ps = g->pcg_part_stride;
+    a.part_rz[0] = g->pcg_part;
+    a.part_rz[1] = g->pcg_part + ps;
+    a.part_rr = g->pcg_part + 2 * ps;
+    a.part_ss = g->pcg_part + 3 * ps;
+    a.part_uau = g->pcg_part + 4 * ps;
     a.sc = g->sc;
+    for (int c = 0; c < GAP_MAXC; ++c) a.op[c] = g->cd.op[c];
+    a.nt = g->nt;
+    a.nz = g->nz;
+    a.n_cond = g->n_cond;
+    pcg_chunks(g->nz, g->n_cond, g->occ[0] * g->cus, a.chunks_a, a.rows_a);
+    pcg_chunks(g->nz, g->n_cond, std::min(g->occ[1], g->occ[2]) * g->cus, a.chunks_b, a.rows_b);
     a.omega = o->omega;
+    a.eps = o->eps;
+    a.max_iter = o->max_iter;
+    a.per_cond = o->scalars == GAP_SCALARS_PER_COND;
+    a.warm = o->warm_start ? 1 : 0;
     a.precond = o->precond;
-    const dim3 grid(cm.total), block(GAP_BLOCK);
-    const int per_cond = o->scalars == GAP_SCALARS_PER_COND;
 
-    hipLaunchKernelGGL(k_init, grid, block, 0, st, gd, g->cd, cm, a, o->warm_start ? 1 : 0);
-    HIPLAUNCHCHK("k_init");
-    if (o->precond == GAP_PRECOND_ASSOR2) {
-        hipLaunchKernelGGL(k_assor_lower, grid, block, 0, st, gd, g->cd, cm, a, 0);
-        hipLaunchKernelGGL(k_assor_upper, grid, block, 0, st, gd, g->cd, cm, a, 0, 2);
-        HIPLAUNCHCHK("ASSOR (init)");
+    hipError_t le = launch_pcg(2, a, st);
+    if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
+
+    // One block = check_every iterations (A, B launch pairs); after each block the host reads
+    // the device record.  Launches after convergence return at once.
+    auto enqueue_block = [&](hipStream_t s) -> hipError_t {
+        for (int it = 0; it < check_every; ++it) {
+            timing_mark(g, GAP_KERNEL_PCG_A, true, s);
+            hipError_t e1 = launch_pcg(0, a, s);
+            timing_mark(g, GAP_KERNEL_PCG_A, false, s);
+            if (e1 != hipSuccess) return e1;
+            timing_mark(g, GAP_KERNEL_PCG_B, true, s);
+            e1 = launch_pcg(1, a, s);
+            timing_mark(g, GAP_KERNEL_PCG_B, false, s);
+            if (e1 != hipSuccess) return e1;
+        }
+        return hipSuccess;
+    };
+    // Event pairs around each launch need plain launches: events recorded by graph nodes
+    // cannot be read back with hipEventElapsedTime.
+    const bool use_graph = o->graph != 0 && !g->timing;
+    if (use_graph) {
+        const bool same = g->exec && g->exec_block == check_every && std::memcmp(&g->exec_args, &a, sizeof a) == 0;
+        if (!same) {
+            if (g->exec) {
+                (void)hipGraphExecDestroy(g->exec);
+                g->exec = nullptr;
+            }
+            if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = enqueue_block(g->cap_stream);
+            hipError_t ee = hipStreamEndCapture(g->cap_stream, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(GAP_EDEVICE, "capturing the PCG block: %s",
+                            hipGetErrorString(ce != hipSuccess ? ce : ee));
+            }
+            hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                g->exec = nullptr;
+                return fail(GAP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            }
+            g->exec_args = a;
+            g->exec_block = check_every;
+        }
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), block, 0, st, cm, g->n_cond, (const double*)g->partial, g->sc, (int)FIN_INIT,
-                       per_cond, o->eps, o->max_iter);
-    HIPLAUNCHCHK("k_finalize (init)");
-
     const long max_blocks = o->max_iter / check_every + 2;
     for (long blk = 0; blk < max_blocks; ++blk) {
-        HIPCHK(hipMemcpyAsync(g->sc_host, g->sc, sizeof(ScalarsDev), hipMemcpyDeviceToHost, st));
+        if (use_graph) {
+            HIPCHK(hipGraphLaunch(g->exec, st));
+        } else {
+            if (g->timing) {
+                gap_status ts = timing_reserve(g, 2 * check_every);
+                if (ts != GAP_OK) return ts;
+            }
+            le = enqueue_block(st);
+            if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a PCG iteration: %s", hipGetErrorString(le));
+        }
+        HIPCHK(hipMemcpyAsync(g->sc_host, g->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (g->timing) {
             gap_status ts = timing_collect(g);
             if (ts != GAP_OK) return ts;
         }
         if (g->sc_host->done) break;
-        if (g->timing) {
-            gap_status ts = timing_reserve(g, 6 * check_every);
-            if (ts != GAP_OK) return ts;
-        }
-        for (int it = 0; it < check_every; ++it) {
-            timing_mark(g, GAP_KERNEL_SPMV_DOT, true, st);
-            hipLaunchKernelGGL(k_spmv_dot, grid, block, 0, st, gd, g->cd, cm, a);
-            timing_mark(g, GAP_KERNEL_SPMV_DOT, false, st);
-            timing_mark(g, GAP_KERNEL_FINALIZE, true, st);
-            hipLaunchKernelGGL(k_finalize, dim3(1), block, 0, st, cm, g->n_cond, (const double*)g->partial, g->sc,
-                               (int)FIN_ALPHA, per_cond, o->eps, o->max_iter);
-            timing_mark(g, GAP_KERNEL_FINALIZE, false, st);
-            timing_mark(g, GAP_KERNEL_UPDATE, true, st);
-            hipLaunchKernelGGL(k_update, grid, block, 0, st, gd, g->cd, cm, a);
-            timing_mark(g, GAP_KERNEL_UPDATE, false, st);
-            if (o->precond == GAP_PRECOND_ASSOR2) {
-                timing_mark(g, GAP_KERNEL_ASSOR_LOWER, true, st);
-                hipLaunchKernelGGL(k_assor_lower, grid, block, 0, st, gd, g->cd, cm, a, 1);
-                timing_mark(g, GAP_KERNEL_ASSOR_LOWER, false, st);
-                timing_mark(g, GAP_KERNEL_ASSOR_UPPER, true, st);
-                hipLaunchKernelGGL(k_assor_upper, grid, block, 0, st, gd, g->cd, cm, a, 1, 1);
-                timing_mark(g, GAP_KERNEL_ASSOR_UPPER, false, st);
-            }
-            timing_mark(g, GAP_KERNEL_FINALIZE, true, st);
-            hipLaunchKernelGGL(k_finalize, dim3(1), block, 0, st, cm, g->n_cond, (const double*)g->partial, g->sc,
-                               (int)FIN_BETA, per_cond, o->eps, o->max_iter);
-            timing_mark(g, GAP_KERNEL_FINALIZE, false, st);
-            HIPLAUNCHCHK("PCG iteration");
-            std::swap(a.u_in, a.u_out);
-        }
     }
-    HIPCHK(hipMemcpyAsync(g->sc_host, g->sc, sizeof(ScalarsDev), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (g->timing) {
-        gap_status ts = timing_collect(g);
-        if (ts != GAP_OK) return ts;
-    }
-    const ScalarsDev& h = *g->sc_host;
+    const PcgScalars& h = *g->sc_host;
     if (info) {
         std::memset(info, 0, sizeof *info);
-        info->iterations = h.iter;
+        info->iterations = h.iterations;
         info->n_cond = g->n_cond;
         info->rel_residual = h.rel;
         for (int c = 0; c < g->n_cond; ++c) info->rel_residual_cond[c] = h.rel_cond[c];
     }
     gap_status result = GAP_OK;
-    if (h.status == -4) result = fail(GAP_ENONFINITE, "non-finite value in the PCG reductions at iteration %d", h.iter);
-    else if (h.status == -3 || !h.done) result = fail(GAP_ENOCONV, "no convergence after %d iterations (rel %.3e)", h.iter, h.rel);
+    if (h.status == -4) result = fail(GAP_ENONFINITE, "non-finite value in the PCG reductions at iteration %d", h.iterations);
+    else if (h.status == -3 || !h.done) result = fail(GAP_ENOCONV, "no convergence after %d iterations (rel %.3e)", h.iterations, h.rel);
     if (info) info->status = result;
     return result;
 }

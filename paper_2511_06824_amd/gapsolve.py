@@ -29,9 +29,9 @@ GAP_PRECOND_JACOBI, GAP_PRECOND_ASSOR1, GAP_PRECOND_ASSOR2 = 0, 1, 2
 GAP_SCALARS_GLOBAL, GAP_SCALARS_PER_COND = 0, 1
 GAP_CAVITATION_NONE, GAP_CAVITATION_CLAMP = 0, 1
 GAP_MAX_COND = 9
-GAP_KERNEL_SPMV_DOT, GAP_KERNEL_UPDATE, GAP_KERNEL_ASSOR_LOWER, GAP_KERNEL_ASSOR_UPPER, GAP_KERNEL_FINALIZE = range(5)
-GAP_KERNEL_COUNT = 5
-KERNEL_NAMES = ["k_spmv_dot", "k_update", "k_assor_lower", "k_assor_upper", "k_finalize"]
+GAP_KERNEL_PCG_A, GAP_KERNEL_PCG_B = 0, 1
+GAP_KERNEL_COUNT = 2
+KERNEL_NAMES = ["k_pcg_a", "k_pcg_b"]
 
 
 class gap_geom(ctypes.Structure):
@@ -50,7 +50,8 @@ class gap_dimples(ctypes.Structure):
 class gap_solver_opts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("neumann", ctypes.c_int32), ("scalars", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class gap_solve_info(ctypes.Structure):

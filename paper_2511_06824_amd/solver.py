@@ -61,11 +61,11 @@ class JointGapSolver:
 
     @staticmethod
     def options(omega=1.6, eps=1e-10, max_iter=100000, precond=G.GAP_PRECOND_ASSOR2, scalars=G.GAP_SCALARS_GLOBAL,
-                warm_start=False, check_every=0, neumann=1):
+                warm_start=False, check_every=0, neumann=1, graph=True):
         o = G.gap_default_opts()
         o.omega, o.eps, o.max_iter = float(omega), float(eps), int(max_iter)
         o.precond, o.scalars, o.neumann = int(precond), int(scalars), int(neumann)
-        o.warm_start, o.check_every = int(bool(warm_start)), int(check_every)
+        o.warm_start, o.check_every, o.graph = int(bool(warm_start)), int(check_every), int(bool(graph))
         return o
 
     def solve(self, opts=None, raise_on_error=True, **kw):
