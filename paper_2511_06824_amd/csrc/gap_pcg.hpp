@@ -56,21 +56,28 @@ struct PcgDev {
     int nt, nz, n_cond;
     int chunks_a, rows_a;       // row chunks per condition of the A launch
     int chunks_b, rows_b;       // row chunks per condition of the B launches
+    const int* work_a;          // block -> (chunk << 4 | condition), -1 = idle (A launch)
+    const int* work_b;          // same for the B launches
+    int blocks_a, blocks_b;
     double omega, eps;
     int max_iter, per_cond, warm, precond;   // precond: 0 Jacobi, 1 ASSOR I, 2 ASSOR II
 };
 
-// Block -> (condition, chunk): consecutive blocks take the conditions of one chunk row, so
-// the conditions that share an operator read its face conductances at about the same time
-// (the repeats are served by the caches).  slot = c * chunks + k indexes the partial sums.
-__device__ __forceinline__ void pcg_chunk(int b, int n_cond, int chunks, int rows, int nz, int& c, int& j0,
+// Block -> (condition, chunk) from a schedule table built on the host (see gapsolve.hip:
+// workgroups reach the XCDs round-robin, and the table places the conditions that share an
+// operator on one XCD so that their face-conductance reads meet in its L2).
+// slot = c * chunks + k indexes the partial sums.  Returns false for idle padding blocks.
+__device__ __forceinline__ bool pcg_chunk(const int* work, int b, int chunks, int rows, int nz, int& c, int& j0,
                                           int& j1, int& slot)
 {
-    const int k = b / n_cond;
-    c = b - k * n_cond;
+    const int w = work[b];
+    if (w < 0) return false;
+    const int k = w >> 4;
+    c = w & 15;
     j0 = k * rows;
     j1 = min(j0 + rows, nz);
     slot = c * chunks + k;
+    return true;
 }
 
 // Per-condition sums of up to 4 partial arrays, in a fixed order: wave w handles
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
 {
     if (a.sc->done) return;
     int c, j0, j1, slot;
-    pcg_chunk(blockIdx.x, a.n_cond, a.chunks_a, a.rows_a, a.nz, c, j0, j1, slot);
+    if (!pcg_chunk(a.work_a, blockIdx.x, a.chunks_a, a.rows_a, a.nz, c, j0, j1, slot)) return;
     const int j = a.sc->iter_a;
     const int nt = a.nt, nz = a.nz;
     const size_t n = (size_t)nt * nz;
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev a)
 {
     if (!INIT && a.sc->done) return;
     int c, j0, j1, slot;
-    pcg_chunk(blockIdx.x, a.n_cond, a.chunks_b, a.rows_b, a.nz, c, j0, j1, slot);
+    if (!pcg_chunk(a.work_b, blockIdx.x, a.chunks_b, a.rows_b, a.nz, c, j0, j1, slot)) return;
     const int j = INIT ? -1 : a.sc->iter_b;
     const int nt = a.nt, nz = a.nz;
     const size_t n = (size_t)nt * nz;

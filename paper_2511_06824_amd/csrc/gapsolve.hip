@@ -85,6 +85,40 @@ void pcg_chunks(int nz, int n_cond, int slots, int& chunks, int& rows)
     chunks = (nz + rows - 1) / rows;
 }
 
+// Schedule of one PCG launch.  Workgroup b is dispatched to XCD b % 8; the conditions of
+// one chunk row that share an operator form a group that is kept on one XCD (their reads of
+// the operator then meet in that XCD's L2), groups are spread so that every XCD gets the
+// same number of workgroups (largest groups first, to the least loaded XCD), and idle
+// entries (-1) pad the XCD lists to equal length.  Entry = chunk << 4 | condition.
+std::vector<int> pcg_schedule(int chunks, int n_cond, const int* op)
+{
+    constexpr int X = 8;
+    std::vector<std::vector<int>> lists(X);
+    std::vector<int> load(X, 0);
+    std::vector<std::vector<int>> groups;
+    for (int k = 0; k < chunks; ++k) {
+        std::vector<std::vector<int>> by_op(GAP_MAXC);
+        for (int c = 0; c < n_cond; ++c) by_op[op[c]].push_back((k << 4) | c);
+        for (auto& gcl : by_op)
+            if (!gcl.empty()) groups.push_back(gcl);
+    }
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const std::vector<int>& x, const std::vector<int>& y) { return x.size() > y.size(); });
+    for (const auto& gcl : groups) {
+        int best = 0;
+        for (int x = 1; x < X; ++x)
+            if (load[x] < load[best]) best = x;
+        for (int w : gcl) lists[best].push_back(w);
+        load[best] += (int)gcl.size();
+    }
+    size_t len = 0;
+    for (auto& l : lists) len = std::max(len, l.size());
+    std::vector<int> table(X * len, -1);
+    for (int x = 0; x < X; ++x)
+        for (size_t m = 0; m < lists[x].size(); ++m) table[m * X + x] = lists[x][m];
+    return table;
+}
+
 template <int NT, int Q>
 const void* pcg_fn(int which)
 {
@@ -110,7 +144,7 @@ template <int NT, int Q>
 hipError_t launch_pcg_t(int which, const PcgDev& a, hipStream_t st)
 {
     const size_t lds = pcg_lds_bytes(which, a.nt);
-    const int blocks = a.n_cond * (which == 0 ? a.chunks_a : a.chunks_b);
+    const int blocks = which == 0 ? a.blocks_a : a.blocks_b;
     if (which == 0) hipLaunchKernelGGL((k_pcg_a<NT, Q>), dim3(blocks), dim3(NT), lds, st, a);
     else if (which == 1) hipLaunchKernelGGL((k_pcg_b<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, a);
     else hipLaunchKernelGGL((k_pcg_b<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, a);
@@ -170,6 +204,10 @@ struct gap_grid_s {
     size_t pcg_part_stride = 0;
     PcgScalars *sc = nullptr;
     PcgScalars *sc_host = nullptr;                           // pinned
+    int *sched = nullptr;                                    // PCG schedule tables (device)
+    size_t sched_cap = 0;
+    std::vector<int> sched_key;                              // (n_cond, chunks_a, chunks_b, ops) of the tables
+    int sched_blocks_a = 0, sched_blocks_b = 0;
     int cus = 256;                                           // compute units of the device
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
     int lds_max = 65536;                                     // bytes of LDS one workgroup may use
@@ -213,6 +251,7 @@ void release(gap_grid_t g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+    if (g->sched) (void)hipFree(g->sched);
     if (g->sc) (void)hipFree(g->sc);
     if (g->sc_host) (void)hipHostFree(g->sc_host);
     delete g;
@@ -563,6 +602,39 @@ gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, ga
     a.n_cond = g->n_cond;
     pcg_chunks(g->nz, g->n_cond, g->occ[0] * g->cus, a.chunks_a, a.rows_a);
     pcg_chunks(g->nz, g->n_cond, std::min(g->occ[1], g->occ[2]) * g->cus, a.chunks_b, a.rows_b);
+    {
+        std::vector<int> key = {g->n_cond, a.chunks_a, a.chunks_b};
+        for (int c = 0; c < g->n_cond; ++c) key.push_back(a.op[c]);
+        if (key != g->sched_key) {
+            const std::vector<int> ta = pcg_schedule(a.chunks_a, g->n_cond, a.op);
+            const std::vector<int> tb = pcg_schedule(a.chunks_b, g->n_cond, a.op);
+            const size_t need = ta.size() + tb.size();
+            if (need > g->sched_cap) {
+                if (g->sched) HIPCHK(hipFree(g->sched));
+                g->sched = nullptr;
+                g->sched_cap = 0;
+                if (hipMalloc((void**)&g->sched, need * sizeof(int)) != hipSuccess) {
+                    g->sched = nullptr;
+                    return fail(GAP_ENOMEM, "hipMalloc of the PCG schedule failed");
+                }
+                g->sched_cap = need;
+                if (g->exec) {                 // a captured graph may point at the old table
+                    (void)hipGraphExecDestroy(g->exec);
+                    g->exec = nullptr;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(g->sched, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(g->sched + ta.size(), tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            g->sched_key = key;
+            g->sched_blocks_a = (int)ta.size();
+            g->sched_blocks_b = (int)tb.size();
+        }
+    }
+    a.work_a = g->sched;
+    a.work_b = g->sched + g->sched_blocks_a;
+    a.blocks_a = g->sched_blocks_a;
+    a.blocks_b = g->sched_blocks_b;
     a.omega = o->omega;
     a.eps = o->eps;
     a.max_iter = o->max_iter;
