@@ -59,6 +59,7 @@ typedef enum {
 
 enum { GAP_PRECOND_JACOBI = 0, GAP_PRECOND_ASSOR1 = 1, GAP_PRECOND_ASSOR2 = 2 };
 enum { GAP_SCALARS_GLOBAL = 0, GAP_SCALARS_PER_COND = 1 };
+enum { GAP_STRATEGY_SYNC = 0, GAP_STRATEGY_ASYNC = 1 };
 enum { GAP_CAVITATION_NONE = 0, GAP_CAVITATION_CLAMP = 1 };
 #define GAP_MAX_COND 9
 
@@ -96,8 +97,12 @@ typedef struct {
  *                _JACOBI (Eq 2.8)
  *   neumann      Neumann order of the ASSOR II inverse; 1 is Eq 3.4 (only 1 is supported)
  *   scalars      GAP_SCALARS_GLOBAL: one alpha/beta for the joint system (CG on A_G);
- *                GAP_SCALARS_PER_COND: one recurrence per condition, still one
- *                synchronized stopping test on the joint residual
+ *                GAP_SCALARS_PER_COND: one recurrence per condition
+ *   strategy     GAP_STRATEGY_SYNC: stop when ||r_G|| / ||S_G|| <= eps (Eq 3.9);
+ *                GAP_STRATEGY_ASYNC: stop each condition when ||r_k|| / ||S_k|| <= eps
+ *                (Eq 3.10); a converged condition is frozen on the device (its workgroups
+ *                return at once), the joint scalars run over the remaining ones, and the
+ *                solve ends when all have converged.  No host round trip is involved.
  *   warm_start   nonzero: p holds the initial guess p_0; zero: p_0 = 0 (Table 1 step 1)
  *   check_every  iterations between host reads of the device convergence flag (0: 32);
  *                launches after convergence return at once, so the count is exact
@@ -105,7 +110,7 @@ typedef struct {
  *                hipGraph and replayed; zero: plain launches                           */
 typedef struct {
     double omega, eps;
-    int32_t max_iter, precond, neumann, scalars, warm_start, check_every, graph, reserved;
+    int32_t max_iter, precond, neumann, scalars, warm_start, check_every, graph, strategy;
 } gap_solver_opts;
 
 /* Result of a solve.  iterations counts completed Table 1 iterations (SpMV + update);
@@ -118,8 +123,8 @@ typedef struct {
 } gap_solve_info;
 
 /* Fill *opts with the defaults: omega 1.6, eps 1e-10, max_iter 100000, ASSOR II,
- * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1.  Returns GAP_EINVAL if
- * NULL. */
+ * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1, SYNC strategy.  Returns
+ * GAP_EINVAL if NULL. */
 gap_status gap_default_opts(gap_solver_opts *opts);
 
 /* Create a handle for one gap (Eq 2.3 geometry, Sec 2.1 grid) that can hold up to
@@ -168,6 +173,29 @@ gap_status integrate_force_moment(gap_grid_t grid, const double *p, int32_t cavi
  * (Fx, Fy, Mx, My), columns (e1..e4, edot1..edot4), delta as given to the last assemble.
  * Errors: GAP_EINVAL, GAP_ESTATE (fewer than 9 conditions assembled), GAP_EDEVICE. */
 gap_status jacobian_fd(gap_grid_t grid, const double *F, double *J, void *stream);
+
+/* Step IV by the adjoint method: the exact derivative of steps I-III of condition 0 with
+ * respect to (e1..e4, edot1..edot4), instead of the forward differences of Eq 2.13-2.14.
+ * With A(e) p = S(e, edot) and F_i = f_i(p, e):
+ *   dF_i/dx_k = df_i/dx_k + lambda_i^T (dS/dx_k - dA/dx_k p0),   A lambda_i = df_i/dp,
+ * where A is the symmetric operator of condition 0, so the adjoint solves reuse it.
+ *   p0     device, n doubles: the solved pressure of condition 0 of the last assembly (the
+ *          first n values of the p returned by solve_joint_pcg)
+ *   w      host, 4 weights, or NULL.  NULL: J (device, 32 doubles) receives the full 4 x 8
+ *          matrix, laid out as in jacobian_fd, from 4 adjoint solves (needs a handle created
+ *          for 9 conditions).  Non-NULL: J (device, 8 doubles) receives the vector-Jacobian
+ *          product w^T J from one adjoint solve.
+ *   opts   omega, eps, precond, max_iter, check_every and graph of the adjoint solves; each
+ *          adjoint field runs its own recurrence and meets eps on its own (per-condition
+ *          scalars, asynchronized test).
+ *   cavitation, p_cav as in integrate_force_moment; in CLAMP mode d max(p, p_cav)/dp is taken
+ *          as 1 where p > p_cav and 0 elsewhere.
+ *   info   host, may be NULL: iterations and residuals of the adjoint solve.
+ * The assembled system and the caller's p are left untouched (the handle's Krylov buffers
+ * are reused).  Synchronizes stream.  Errors: GAP_EINVAL, GAP_ESTATE, GAP_ENOCONV,
+ * GAP_ENONFINITE, GAP_EDEVICE. */
+gap_status jacobian_adjoint(gap_grid_t grid, const gap_solver_opts *opts, const double *p0, int32_t cavitation,
+                            double p_cav, const double *w, double *J, gap_solve_info *info, void *stream);
 
 /* Copy the assembled system of condition k to caller device buffers (inspection and
  * testing): kx (n doubles, east-face conductances h^3/(12 mu) dz/dx), kz

@@ -103,3 +103,65 @@ def pcg(A, S, precond, eps, max_iter, p0=None):
         d = d_new
         u = z + beta * u
     return p, it, hist
+
+
+def pcg_blocks(blocks, rhs, preconds, eps, max_iter, scalars="global", strategy="sync"):
+    """Table 1 on the joint system of Eq 3.7 kept as a list of blocks, with the variants of
+    Sec 3.3: scalars "global" (one alpha, beta over all blocks: CG on A_G) or "per_cond"
+    (one recurrence per block); strategy "sync" (stop when ||r_G|| / ||S_G|| <= eps, Eq 3.9)
+    or "async" (a block stops when ||r_k|| / ||S_k|| <= eps, Eq 3.10, and is frozen; the
+    global scalars then run over the remaining blocks).
+    Returns (list of p_k, iterations, history of ||r_G|| / ||S_G||)."""
+    K = len(blocks)
+    A = [sp.csr_matrix(b) for b in blocks]
+    S = [np.asarray(s, dtype=float) for s in rhs]
+    p = [np.zeros_like(s) for s in S]
+    r = [s.copy() for s in S]
+    s_norm2 = [s @ s for s in S]
+    z = [preconds[k](r[k]) for k in range(K)]
+    u = [zk.copy() for zk in z]
+    d = [r[k] @ z[k] for k in range(K)]
+
+    def rel_all():
+        return np.sqrt(sum(rk @ rk for rk in r) / sum(s_norm2))
+
+    def rel_k(k):
+        return np.sqrt((r[k] @ r[k]) / s_norm2[k])
+
+    def active_set():
+        if strategy == "sync":
+            return list(range(K))
+        return [k for k in range(K) if rel_k(k) > eps]
+
+    hist = [rel_all()]
+    it = 0
+    act = active_set()
+    done = (rel_all() <= eps) if strategy == "sync" else not act
+    while not done and it < max_iter:
+        v = {k: A[k] @ u[k] for k in act}
+        uv = {k: u[k] @ v[k] for k in act}
+        if scalars == "global":
+            alpha = {k: sum(d[m] for m in act) / sum(uv[m] for m in act) for k in act}
+        else:
+            alpha = {k: d[k] / uv[k] for k in act}
+        for k in act:
+            p[k] = p[k] + alpha[k] * u[k]
+            r[k] = r[k] - alpha[k] * v[k]
+        it += 1
+        hist.append(rel_all())
+        new_act = active_set()
+        done = (hist[-1] <= eps) if strategy == "sync" else not new_act
+        if done:
+            break
+        for k in new_act:
+            z[k] = preconds[k](r[k])
+        d_new = {k: r[k] @ z[k] for k in new_act}
+        if scalars == "global":
+            beta = {k: sum(d_new[m] for m in new_act) / sum(d[m] for m in new_act) for k in new_act}
+        else:
+            beta = {k: d_new[k] / d[k] for k in new_act}
+        for k in new_act:
+            d[k] = d_new[k]
+            u[k] = z[k] + beta[k] * u[k]
+        act = new_act
+    return p, it, hist

@@ -26,7 +26,7 @@ __device__ __forceinline__ void chunk_rows(const ChunkMap& cm, int nz, int b, in
 // Texture: spherical caps scattered over their footprint boxes, overlaps combined by max.
 // Depths are >= 0, so their IEEE bit patterns order like unsigned integers.
 // plane 0: cell centres, plane 1: east faces, plane 2: axial faces (nz + 1 rows).
-__global__ void k_texture(GeomDev g, int count, const double* __restrict__ th_c,
+__global__ __launch_bounds__(GAP_BLOCK) void k_texture(GeomDev g, int count, const double* __restrict__ th_c,
                           const double* __restrict__ z_c, const double* __restrict__ rad,
                           const double* __restrict__ dep, double* tex_c, double* tex_e, double* tex_f)
 {
@@ -71,7 +71,7 @@ __global__ void k_texture(GeomDev g, int count, const double* __restrict__ th_c,
 // ---------------------------------------------------------------------------------------
 // Assembly (step I): one thread per (cell, condition).  Writes the source of every
 // condition and, for conditions that own an operator, its face conductances.
-__global__ void k_assemble(GeomDev g, CondDev cd, TablesDev tb, double* __restrict__ kx,
+__global__ __launch_bounds__(GAP_BLOCK) void k_assemble(GeomDev g, CondDev cd, TablesDev tb, double* __restrict__ kx,
                            double* __restrict__ kz, double* __restrict__ S)
 {
     const int c = blockIdx.y;
@@ -126,7 +126,7 @@ __device__ __forceinline__ double apply_A(const double* kx, const double* kz, in
 // Diagonal preconditioners: Jacobi (Eq 2.8) and ASSOR I (Eq 3.2), stored as M^{-1}_ii per
 // operator.  ASSOR I: w(2-w) / (D_ii + w^2 sum_k L_ik^2 / D_kk), L the strict lower
 // triangle in the natural order (west, south, and the east wrap of the last column).
-__global__ void k_diag_precond(GeomDev g, int kind, double omega, const double* __restrict__ kx_all,
+__global__ __launch_bounds__(GAP_BLOCK) void k_diag_precond(GeomDev g, int kind, double omega, const double* __restrict__ kx_all,
                                const double* __restrict__ kz_all, double* __restrict__ minv, int n_op)
 {
     const int o = blockIdx.y;
@@ -155,7 +155,7 @@ __global__ void k_diag_precond(GeomDev g, int kind, double omega, const double* 
 // Fx, Fy, Mx, My per chunk before the factor dA.
 __device__ __forceinline__ double peff(double p, int cav, double pc) { return (cav && p < pc) ? pc : p; }
 
-__global__ void k_forces(GeomDev g, CondDev cd, ChunkMap cm, TablesDev tb, const double* __restrict__ p_all,
+__global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, ChunkMap cm, TablesDev tb, const double* __restrict__ p_all,
                          int cav, double p_cav, double* __restrict__ partial)
 {
     int c, j0, j1;
@@ -201,7 +201,7 @@ __device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& c
     return v[0];   // valid in thread 0
 }
 
-__global__ void k_forces_finalize(ChunkMap cm, int n_cond, double dA, const double* __restrict__ part,
+__global__ __launch_bounds__(GAP_BLOCK) void k_forces_finalize(ChunkMap cm, int n_cond, double dA, const double* __restrict__ part,
                                   double* __restrict__ F)
 {
     for (int c = 0; c < n_cond; ++c)

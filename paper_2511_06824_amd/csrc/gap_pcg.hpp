@@ -30,7 +30,7 @@ struct PcgScalars {
     int done;                   // nonzero: every launch returns at once
     int status;                 // 0, -3 (no convergence), -4 (non-finite)
     int iterations;             // completed iterations (written by A)
-    int pad;
+    int active_b;               // conditions still iterating, bit c (written by A, read by B)
     double rel;                 // ||r_G|| / ||S_G|| of the last completed iteration
     double rel_cond[GAP_MAXC];  // per condition
 };
@@ -61,6 +61,7 @@ struct PcgDev {
     int blocks_a, blocks_b;
     double omega, eps;
     int max_iter, per_cond, warm, precond;   // precond: 0 Jacobi, 1 ASSOR I, 2 ASSOR II
+    int async;                  // 1: each condition stops at its own test (Eq 3.10) and is frozen
 };
 
 // Block -> (condition, chunk) from a schedule table built on the host (see gapsolve.hip:
@@ -155,20 +156,32 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
         const int cnt[4] = {a.chunks_b, a.chunks_b, a.chunks_b, a.chunks_b};
         cond_sums<NT, 4>(a.n_cond, cnt, src, sums);
     }
+    // Active conditions: all (synchronized test, Eq 3.9) or those whose own relative residual
+    // is above eps (asynchronized test, Eq 3.10; a converged condition is frozen, so its
+    // residual and the decision stay fixed).  Scalars of the joint recurrence run over the
+    // active conditions.
+    unsigned active = 0;
     double dn = 0.0, dp = 0.0, rr = 0.0, ss = 0.0;
     for (int k = 0; k < a.n_cond; ++k) {
-        dn += sums[0][k];
-        dp += sums[1][k];
+        const double sk = sums[3][k] > 0.0 ? sums[3][k] : 1.0;
+        const bool act = !a.async || sqrt(sums[2][k] / sk) > a.eps;
+        if (act) {
+            active |= 1u << k;
+            dn += sums[0][k];
+            dp += sums[1][k];
+        }
         rr += sums[2][k];
         ss += sums[3][k];
     }
     const double rel = sqrt(rr / (ss > 0.0 ? ss : 1.0));
     double beta = 0.0;
     if (j > 0) beta = a.per_cond ? sums[0][c] / sums[1][c] : dn / dp;
-    bool bad = !finite_d(rel) || !finite_d(beta);
-    if (a.per_cond && j > 0)
-        for (int k = 0; k < a.n_cond; ++k) bad |= !finite_d(sums[0][k] / sums[1][k]);
-    const bool stop = bad || rel <= a.eps || j >= a.max_iter;
+    bool bad = !finite_d(rel);
+    if (j > 0)
+        for (int k = 0; k < a.n_cond; ++k)
+            if (active & (1u << k)) bad |= !finite_d(a.per_cond ? sums[0][k] / sums[1][k] : dn / dp);
+    const bool converged = a.async ? (active == 0) : (rel <= a.eps);
+    const bool stop = bad || converged || j >= a.max_iter;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         PcgScalars* s = a.sc;
         s->iterations = j;
@@ -178,10 +191,11 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
             s->rel_cond[k] = sqrt(sums[2][k] / sk);
         }
         s->iter_b = j;
-        s->status = bad ? -4 : (rel <= a.eps ? 0 : (j >= a.max_iter ? -3 : 0));
+        s->active_b = (int)active;
+        s->status = bad ? -4 : (converged ? 0 : (j >= a.max_iter ? -3 : 0));
         if (stop) s->done = 1;
     }
-    if (stop) return;
+    if (stop || !(active & (1u << c))) return;
 
     // ---- march over the rows of the chunk ----------------------------------------------
     extern __shared__ double lds[];
@@ -292,15 +306,17 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev a)
         const double* src[2] = {a.part_rz[j & 1], a.part_uau};
         const int cnt[2] = {a.chunks_b, a.chunks_a};
         cond_sums<NT, 2>(a.n_cond, cnt, src, sums);
+        const unsigned active = (unsigned)a.sc->active_b;
         double num = 0.0, den = 0.0;
         bool bad = false;
         for (int k = 0; k < a.n_cond; ++k) {
+            if (!(active & (1u << k))) continue;
             num += sums[0][k];
             den += sums[1][k];
             if (a.per_cond) bad |= !finite_d(sums[0][k] / sums[1][k]);
         }
+        if (!a.per_cond) bad |= !finite_d(num / den);
         alpha = a.per_cond ? sums[0][c] / sums[1][c] : num / den;
-        bad |= !finite_d(alpha);
         if (bad) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 a.sc->status = -4;
@@ -309,12 +325,14 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev a)
             return;
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->iter_a = j + 1;
+        if (!(active & (1u << c))) return;
     } else if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.sc->iter_a = 0;
         a.sc->iter_b = 0;
         a.sc->done = 0;
         a.sc->status = 0;
         a.sc->iterations = 0;
+        a.sc->active_b = (1 << a.n_cond) - 1;
     }
 
     const bool spmv = !INIT || a.warm;

@@ -12,6 +12,7 @@
 
 #include "gap_kernels.hpp"
 #include "gap_pcg.hpp"
+#include "gap_adjoint.hpp"
 
 namespace {
 
@@ -204,10 +205,14 @@ struct gap_grid_s {
     size_t pcg_part_stride = 0;
     PcgScalars *sc = nullptr;
     PcgScalars *sc_host = nullptr;                           // pinned
-    int *sched = nullptr;                                    // PCG schedule tables (device)
-    size_t sched_cap = 0;
-    std::vector<int> sched_key;                              // (n_cond, chunks_a, chunks_b, ops) of the tables
-    int sched_blocks_a = 0, sched_blocks_b = 0;
+    struct Sched {                                           // PCG schedule tables (device), by key
+        std::vector<int> key;                                // (n_cond, chunks_a, chunks_b, ops...)
+        int* table = nullptr;
+        int blocks_a = 0, blocks_b = 0;
+    };
+    std::vector<Sched> scheds;
+    double *adj_rhs = nullptr, *adj_lam = nullptr;           // adjoint right-hand sides and solutions
+    double *adj_part = nullptr;                              // sensitivity partials
     int cus = 256;                                           // compute units of the device
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
     int lds_max = 65536;                                     // bytes of LDS one workgroup may use
@@ -220,11 +225,14 @@ struct gap_grid_s {
     int ev_used = 0;
     long long launches[GAP_KERNEL_COUNT] = {0};
     double total_ms[GAP_KERNEL_COUNT] = {0};
-    // captured iteration block (graph replay)
+    // captured iteration blocks (graph replay), by launch arguments; oldest evicted
+    struct Graph {
+        PcgDev args{};
+        int block = 0;
+        hipGraphExec_t exec = nullptr;
+    };
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t exec = nullptr;
-    PcgDev exec_args{};
-    int exec_block = 0;
+    std::vector<Graph> graphs;
 
     TablesDev tables() const
     {
@@ -245,13 +253,15 @@ namespace {
 void release(gap_grid_t g)
 {
     double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->partial,
-                      g->pcg_part};
+                      g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    for (auto& gr : g->graphs)
+        if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
-    if (g->sched) (void)hipFree(g->sched);
+    for (auto& sc : g->scheds)
+        if (sc.table) (void)hipFree(sc.table);
     if (g->sc) (void)hipFree(g->sc);
     if (g->sc_host) (void)hipHostFree(g->sc_host);
     delete g;
@@ -308,6 +318,184 @@ gap_status timing_collect(gap_grid_t g)
     return GAP_OK;
 }
 
+// Run the PCG of Table 1 on the conditions described by `a` (operators, sources, solution,
+// scalar and stopping variants already set): Krylov buffers, partial sums, schedule,
+// initial residual, then blocks of check_every iterations (captured once into a hipGraph and
+// replayed, unless disabled or kernel timing is on) until the device record says done.
+// Leaves the final record in g->sc_host.
+gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_t st)
+{
+    const int check_every = o->check_every ? o->check_every : 32;
+    a.r[0] = g->r0;
+    a.r[1] = g->r1;
+    a.u[0] = g->u0;
+    a.u[1] = g->u1;
+    a.z = g->z;
+    const size_t ps = g->pcg_part_stride;
+    a.part_rz[0] = g->pcg_part;
+    a.part_rz[1] = g->pcg_part + ps;
+    a.part_rr = g->pcg_part + 2 * ps;
+    a.part_ss = g->pcg_part + 3 * ps;
+    a.part_uau = g->pcg_part + 4 * ps;
+    a.sc = g->sc;
+    a.nt = g->nt;
+    a.nz = g->nz;
+    a.omega = o->omega;
+    a.eps = o->eps;
+    a.max_iter = o->max_iter;
+    a.precond = o->precond;
+    pcg_chunks(g->nz, a.n_cond, g->occ[0] * g->cus, a.chunks_a, a.rows_a);
+    pcg_chunks(g->nz, a.n_cond, std::min(g->occ[1], g->occ[2]) * g->cus, a.chunks_b, a.rows_b);
+
+    // schedule tables for this (n_cond, chunk counts, operator map)
+    std::vector<int> key = {a.n_cond, a.chunks_a, a.chunks_b};
+    for (int c = 0; c < a.n_cond; ++c) key.push_back(a.op[c]);
+    gap_grid_s::Sched* sch = nullptr;
+    for (auto& e : g->scheds)
+        if (e.key == key) sch = &e;
+    if (!sch) {
+        const std::vector<int> ta = pcg_schedule(a.chunks_a, a.n_cond, a.op);
+        const std::vector<int> tb = pcg_schedule(a.chunks_b, a.n_cond, a.op);
+        gap_grid_s::Sched e;
+        e.key = key;
+        if (hipMalloc((void**)&e.table, (ta.size() + tb.size()) * sizeof(int)) != hipSuccess)
+            return fail(GAP_ENOMEM, "hipMalloc of a PCG schedule failed");
+        e.blocks_a = (int)ta.size();
+        e.blocks_b = (int)tb.size();
+        g->scheds.push_back(e);
+        sch = &g->scheds.back();
+        HIPCHK(hipMemcpyAsync(sch->table, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(sch->table + ta.size(), tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    a.work_a = sch->table;
+    a.work_b = sch->table + sch->blocks_a;
+    a.blocks_a = sch->blocks_a;
+    a.blocks_b = sch->blocks_b;
+
+    hipError_t le = launch_pcg(2, a, st);
+    if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
+
+    // One block = check_every iterations (A, B launch pairs); after each block the host reads
+    // the device record.  Launches after convergence return at once.
+    auto enqueue_block = [&](hipStream_t s) -> hipError_t {
+        for (int it = 0; it < check_every; ++it) {
+            timing_mark(g, GAP_KERNEL_PCG_A, true, s);
+            hipError_t e1 = launch_pcg(0, a, s);
+            timing_mark(g, GAP_KERNEL_PCG_A, false, s);
+            if (e1 != hipSuccess) return e1;
+            timing_mark(g, GAP_KERNEL_PCG_B, true, s);
+            e1 = launch_pcg(1, a, s);
+            timing_mark(g, GAP_KERNEL_PCG_B, false, s);
+            if (e1 != hipSuccess) return e1;
+        }
+        return hipSuccess;
+    };
+    // Event pairs around each launch need plain launches: events recorded by graph nodes
+    // cannot be read back with hipEventElapsedTime.
+    const bool use_graph = o->graph != 0 && !g->timing;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph) {
+        for (auto& gr : g->graphs)
+            if (gr.block == check_every && std::memcmp(&gr.args, &a, sizeof a) == 0) exec = gr.exec;
+        if (!exec) {
+            if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = enqueue_block(g->cap_stream);
+            hipError_t ee = hipStreamEndCapture(g->cap_stream, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce != hipSuccess ? ce : ee));
+            }
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(GAP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            if (g->graphs.size() >= 4) {
+                (void)hipGraphExecDestroy(g->graphs.front().exec);
+                g->graphs.erase(g->graphs.begin());
+            }
+            gap_grid_s::Graph gr;
+            gr.args = a;
+            gr.block = check_every;
+            gr.exec = exec;
+            g->graphs.push_back(gr);
+        }
+    }
+    const long max_blocks = o->max_iter / check_every + 2;
+    for (long blk = 0; blk < max_blocks; ++blk) {
+        if (use_graph) {
+            HIPCHK(hipGraphLaunch(exec, st));
+        } else {
+            if (g->timing) {
+                gap_status ts = timing_reserve(g, 2 * check_every);
+                if (ts != GAP_OK) return ts;
+            }
+            le = enqueue_block(st);
+            if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a PCG iteration: %s", hipGetErrorString(le));
+        }
+        HIPCHK(hipMemcpyAsync(g->sc_host, g->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (g->timing) {
+            gap_status ts = timing_collect(g);
+            if (ts != GAP_OK) return ts;
+        }
+        if (g->sc_host->done) break;
+    }
+    return GAP_OK;
+}
+
+gap_status validate_opts(const gap_solver_opts* o)
+{
+    if (!o) return fail(GAP_EINVAL, "opts is NULL");
+    if (!is_finite(o->omega) || !(o->omega > 0.0 && o->omega < 2.0)) return fail(GAP_EINVAL, "omega must lie in (0, 2)");
+    if (!is_finite(o->eps) || !(o->eps > 0.0)) return fail(GAP_EINVAL, "eps must be > 0");
+    if (o->max_iter < 1) return fail(GAP_EINVAL, "max_iter must be >= 1");
+    if (o->precond < GAP_PRECOND_JACOBI || o->precond > GAP_PRECOND_ASSOR2) return fail(GAP_EINVAL, "unknown precond");
+    if (o->precond == GAP_PRECOND_ASSOR2 && o->neumann != 1) return fail(GAP_EINVAL, "neumann must be 1");
+    if (o->scalars != GAP_SCALARS_GLOBAL && o->scalars != GAP_SCALARS_PER_COND)
+        return fail(GAP_EINVAL, "unknown scalars mode");
+    if (o->check_every < 0) return fail(GAP_EINVAL, "check_every must be >= 0");
+    if (o->strategy != GAP_STRATEGY_SYNC && o->strategy != GAP_STRATEGY_ASYNC)
+        return fail(GAP_EINVAL, "unknown strategy");
+    return GAP_OK;
+}
+
+// Diagonal preconditioners (Jacobi, ASSOR I) are stored per operator; rebuilt when the kind,
+// omega or the assembled operators change.
+gap_status prepare_precond(gap_grid_t g, const gap_solver_opts* o, hipStream_t st)
+{
+    if (o->precond == GAP_PRECOND_ASSOR2 || (g->minv_kind == o->precond && g->minv_omega == o->omega)) return GAP_OK;
+    if (!g->minv) {
+        gap_status s = dmalloc(&g->minv, g->max_op * g->n);
+        if (s != GAP_OK) return s;
+    }
+    hipLaunchKernelGGL(k_diag_precond, dim3((unsigned)((g->n + GAP_BLOCK - 1) / GAP_BLOCK), g->n_op), dim3(GAP_BLOCK),
+                       0, st, g->gd, o->precond, o->omega, g->kx, g->kz, g->minv, g->n_op);
+    HIPLAUNCHCHK("k_diag_precond");
+    g->minv_kind = o->precond;
+    g->minv_omega = o->omega;
+    return GAP_OK;
+}
+
+// Translate the device record of the last solve into info and a status.
+gap_status finish_solve(gap_grid_t g, int n_cond, gap_solve_info* info)
+{
+    const PcgScalars& h = *g->sc_host;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iterations = h.iterations;
+        info->n_cond = n_cond;
+        info->rel_residual = h.rel;
+        for (int c = 0; c < n_cond; ++c) info->rel_residual_cond[c] = h.rel_cond[c];
+    }
+    gap_status result = GAP_OK;
+    if (h.status == -4) result = fail(GAP_ENONFINITE, "non-finite value in the PCG reductions at iteration %d", h.iterations);
+    else if (h.status == -3 || !h.done) result = fail(GAP_ENOCONV, "no convergence after %d iterations (rel %.3e)", h.iterations, h.rel);
+    if (info) info->status = result;
+    return result;
+}
+
 gap_status validate_geom(const gap_geom* g)
 {
     if (!g) return fail(GAP_EINVAL, "geom is NULL");
@@ -342,7 +530,7 @@ gap_status gap_default_opts(gap_solver_opts* o)
     o->warm_start = 0;
     o->check_every = 32;
     o->graph = 1;
-    o->reserved = 0;
+    o->strategy = GAP_STRATEGY_SYNC;
     return GAP_OK;
 }
 
@@ -551,32 +739,13 @@ gap_status assemble_joint_system(gap_grid_t g, const double e[4], const double e
 gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, gap_solve_info* info, void* stream)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
-    if (!o) return fail(GAP_EINVAL, "opts is NULL");
     if (!p) return fail(GAP_EINVAL, "p is NULL");
+    gap_status vs = validate_opts(o);
+    if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "solve_joint_pcg before assemble_joint_system");
-    if (!is_finite(o->omega) || !(o->omega > 0.0 && o->omega < 2.0)) return fail(GAP_EINVAL, "omega must lie in (0, 2)");
-    if (!is_finite(o->eps) || !(o->eps > 0.0)) return fail(GAP_EINVAL, "eps must be > 0");
-    if (o->max_iter < 1) return fail(GAP_EINVAL, "max_iter must be >= 1");
-    if (o->precond < GAP_PRECOND_JACOBI || o->precond > GAP_PRECOND_ASSOR2) return fail(GAP_EINVAL, "unknown precond");
-    if (o->precond == GAP_PRECOND_ASSOR2 && o->neumann != 1) return fail(GAP_EINVAL, "neumann must be 1");
-    if (o->scalars != GAP_SCALARS_GLOBAL && o->scalars != GAP_SCALARS_PER_COND)
-        return fail(GAP_EINVAL, "unknown scalars mode");
-    if (o->check_every < 0) return fail(GAP_EINVAL, "check_every must be >= 0");
-    const int check_every = o->check_every ? o->check_every : 32;
     hipStream_t st = (hipStream_t)stream;
-    const GeomDev& gd = g->gd;
-
-    if (o->precond != GAP_PRECOND_ASSOR2 && (g->minv_kind != o->precond || g->minv_omega != o->omega)) {
-        if (!g->minv) {
-            gap_status s = dmalloc(&g->minv, g->max_op * g->n);
-            if (s != GAP_OK) return s;
-        }
-        hipLaunchKernelGGL(k_diag_precond, dim3((unsigned)((g->n + GAP_BLOCK - 1) / GAP_BLOCK), g->n_op),
-                           dim3(GAP_BLOCK), 0, st, gd, o->precond, o->omega, g->kx, g->kz, g->minv, g->n_op);
-        HIPLAUNCHCHK("k_diag_precond");
-        g->minv_kind = o->precond;
-        g->minv_omega = o->omega;
-    }
+    gap_status ps = prepare_precond(g, o, st);
+    if (ps != GAP_OK) return ps;
 
     PcgDev a{};
     a.kx = g->kx;
@@ -584,145 +753,84 @@ gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, ga
     a.minv = g->minv;
     a.S = g->S;
     a.p = p;
-    a.r[0] = g->r0;
-    a.r[1] = g->r1;
-    a.u[0] = g->u0;
-    a.u[1] = g->u1;
-    a.z = g->z;
-    const size_t ps = g->pcg_part_stride;
-    a.part_rz[0] = g->pcg_part;
-    a.part_rz[1] = g->pcg_part + ps;
-    a.part_rr = g->pcg_part + 2 * ps;
-    a.part_ss = g->pcg_part + 3 * ps;
-    a.part_uau = g->pcg_part + 4 * ps;
-    a.sc = g->sc;
     for (int c = 0; c < GAP_MAXC; ++c) a.op[c] = g->cd.op[c];
-    a.nt = g->nt;
-    a.nz = g->nz;
     a.n_cond = g->n_cond;
-    pcg_chunks(g->nz, g->n_cond, g->occ[0] * g->cus, a.chunks_a, a.rows_a);
-    pcg_chunks(g->nz, g->n_cond, std::min(g->occ[1], g->occ[2]) * g->cus, a.chunks_b, a.rows_b);
-    {
-        std::vector<int> key = {g->n_cond, a.chunks_a, a.chunks_b};
-        for (int c = 0; c < g->n_cond; ++c) key.push_back(a.op[c]);
-        if (key != g->sched_key) {
-            const std::vector<int> ta = pcg_schedule(a.chunks_a, g->n_cond, a.op);
-            const std::vector<int> tb = pcg_schedule(a.chunks_b, g->n_cond, a.op);
-            const size_t need = ta.size() + tb.size();
-            if (need > g->sched_cap) {
-                if (g->sched) HIPCHK(hipFree(g->sched));
-                g->sched = nullptr;
-                g->sched_cap = 0;
-                if (hipMalloc((void**)&g->sched, need * sizeof(int)) != hipSuccess) {
-                    g->sched = nullptr;
-                    return fail(GAP_ENOMEM, "hipMalloc of the PCG schedule failed");
-                }
-                g->sched_cap = need;
-                if (g->exec) {                 // a captured graph may point at the old table
-                    (void)hipGraphExecDestroy(g->exec);
-                    g->exec = nullptr;
-                }
-            }
-            HIPCHK(hipMemcpyAsync(g->sched, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(g->sched + ta.size(), tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-            HIPCHK(hipStreamSynchronize(st));
-            g->sched_key = key;
-            g->sched_blocks_a = (int)ta.size();
-            g->sched_blocks_b = (int)tb.size();
-        }
-    }
-    a.work_a = g->sched;
-    a.work_b = g->sched + g->sched_blocks_a;
-    a.blocks_a = g->sched_blocks_a;
-    a.blocks_b = g->sched_blocks_b;
-    a.omega = o->omega;
-    a.eps = o->eps;
-    a.max_iter = o->max_iter;
     a.per_cond = o->scalars == GAP_SCALARS_PER_COND;
+    a.async = o->strategy == GAP_STRATEGY_ASYNC;
     a.warm = o->warm_start ? 1 : 0;
-    a.precond = o->precond;
+    gap_status rs = run_pcg(g, a, o, st);
+    if (rs != GAP_OK) return rs;
+    return finish_solve(g, g->n_cond, info);
+}
 
-    hipError_t le = launch_pcg(2, a, st);
-    if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
+gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double* p0, int32_t cavitation, double p_cav,
+                            const double* w, double* J, gap_solve_info* info, void* stream)
+{
+    if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    if (!p0 || !J) return fail(GAP_EINVAL, "p0 and J must be non-NULL");
+    gap_status vs = validate_opts(o);
+    if (vs != GAP_OK) return vs;
+    if (!g->assembled) return fail(GAP_ESTATE, "jacobian_adjoint before assemble_joint_system");
+    if (cavitation != GAP_CAVITATION_NONE && cavitation != GAP_CAVITATION_CLAMP)
+        return fail(GAP_EINVAL, "unknown cavitation mode");
+    if (!is_finite(p_cav)) return fail(GAP_EINVAL, "p_cav must be finite");
+    if (w)
+        for (int i = 0; i < 4; ++i)
+            if (!is_finite(w[i])) return fail(GAP_EINVAL, "w must be finite");
+    const int n_rhs = w ? 1 : 4;
+    if (n_rhs > g->max_cond)
+        return fail(GAP_EINVAL, "the full adjoint Jacobian needs a handle created for 9 conditions (pass w for a "
+                                "vector-Jacobian product)");
+    hipStream_t st = (hipStream_t)stream;
+    gap_status ps = prepare_precond(g, o, st);
+    if (ps != GAP_OK) return ps;
+    const size_t n = g->n;
+    const ChunkMap cm1 = make_chunks(g->nz, 1);
+    if (!g->adj_rhs) {
+        gap_status s1 = dmalloc(&g->adj_rhs, 4 * n);
+        if (s1 == GAP_OK) s1 = dmalloc(&g->adj_lam, 4 * n);
+        if (s1 == GAP_OK) s1 = dmalloc(&g->adj_part, 32 * (size_t)cm1.total);
+        if (s1 != GAP_OK) return s1;
+    }
+    const double w0 = w ? w[0] : 0.0, w1 = w ? w[1] : 0.0, w2 = w ? w[2] : 0.0, w3 = w ? w[3] : 0.0;
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)((n + GAP_BLOCK - 1) / GAP_BLOCK)), dim3(GAP_BLOCK), 0, st, g->gd,
+                       g->cd, g->tables(), p0, cavitation, p_cav, w ? 1 : 0, w0, w1, w2, w3, g->adj_rhs);
+    HIPLAUNCHCHK("k_adjoint_rhs");
 
-    // One block = check_every iterations (A, B launch pairs); after each block the host reads
-    // the device record.  Launches after convergence return at once.
-    auto enqueue_block = [&](hipStream_t s) -> hipError_t {
-        for (int it = 0; it < check_every; ++it) {
-            timing_mark(g, GAP_KERNEL_PCG_A, true, s);
-            hipError_t e1 = launch_pcg(0, a, s);
-            timing_mark(g, GAP_KERNEL_PCG_A, false, s);
-            if (e1 != hipSuccess) return e1;
-            timing_mark(g, GAP_KERNEL_PCG_B, true, s);
-            e1 = launch_pcg(1, a, s);
-            timing_mark(g, GAP_KERNEL_PCG_B, false, s);
-            if (e1 != hipSuccess) return e1;
-        }
-        return hipSuccess;
-    };
-    // Event pairs around each launch need plain launches: events recorded by graph nodes
-    // cannot be read back with hipEventElapsedTime.
-    const bool use_graph = o->graph != 0 && !g->timing;
-    if (use_graph) {
-        const bool same = g->exec && g->exec_block == check_every && std::memcmp(&g->exec_args, &a, sizeof a) == 0;
-        if (!same) {
-            if (g->exec) {
-                (void)hipGraphExecDestroy(g->exec);
-                g->exec = nullptr;
-            }
-            if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            hipGraph_t graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t ce = enqueue_block(g->cap_stream);
-            hipError_t ee = hipStreamEndCapture(g->cap_stream, &graph);
-            if (ce != hipSuccess || ee != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return fail(GAP_EDEVICE, "capturing the PCG block: %s",
-                            hipGetErrorString(ce != hipSuccess ? ce : ee));
-            }
-            hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (ie != hipSuccess) {
-                g->exec = nullptr;
-                return fail(GAP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
-            }
-            g->exec_args = a;
-            g->exec_block = check_every;
-        }
-    }
-    const long max_blocks = o->max_iter / check_every + 2;
-    for (long blk = 0; blk < max_blocks; ++blk) {
-        if (use_graph) {
-            HIPCHK(hipGraphLaunch(g->exec, st));
-        } else {
-            if (g->timing) {
-                gap_status ts = timing_reserve(g, 2 * check_every);
-                if (ts != GAP_OK) return ts;
-            }
-            le = enqueue_block(st);
-            if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a PCG iteration: %s", hipGetErrorString(le));
-        }
-        HIPCHK(hipMemcpyAsync(g->sc_host, g->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (g->timing) {
-            gap_status ts = timing_collect(g);
-            if (ts != GAP_OK) return ts;
-        }
-        if (g->sc_host->done) break;
-    }
-    const PcgScalars& h = *g->sc_host;
-    if (info) {
-        std::memset(info, 0, sizeof *info);
-        info->iterations = h.iterations;
-        info->n_cond = g->n_cond;
-        info->rel_residual = h.rel;
-        for (int c = 0; c < g->n_cond; ++c) info->rel_residual_cond[c] = h.rel_cond[c];
-    }
-    gap_status result = GAP_OK;
-    if (h.status == -4) result = fail(GAP_ENONFINITE, "non-finite value in the PCG reductions at iteration %d", h.iterations);
-    else if (h.status == -3 || !h.done) result = fail(GAP_ENOCONV, "no convergence after %d iterations (rel %.3e)", h.iterations, h.rel);
-    if (info) info->status = result;
-    return result;
+    // A lambda_i = g_i on the operator of condition 0: one recurrence per right-hand side,
+    // each stopped by its own relative residual.
+    gap_solver_opts oa = *o;
+    oa.scalars = GAP_SCALARS_PER_COND;
+    oa.strategy = GAP_STRATEGY_ASYNC;
+    oa.warm_start = 0;
+    PcgDev a{};
+    a.kx = g->kx;
+    a.kz = g->kz;
+    a.minv = g->minv;
+    a.S = g->adj_rhs;
+    a.p = g->adj_lam;
+    for (int c = 0; c < GAP_MAXC; ++c) a.op[c] = 0;
+    a.n_cond = n_rhs;
+    a.per_cond = 1;
+    a.async = 1;
+    a.warm = 0;
+    gap_status rs = run_pcg(g, a, &oa, st);
+    if (rs != GAP_OK) return rs;
+    gap_status fs = finish_solve(g, n_rhs, info);
+    if (fs != GAP_OK) return fs;
+
+    if (w)
+        hipLaunchKernelGGL((k_adjoint_sens<1>), dim3(cm1.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm1, g->tables(),
+                           p0, (const double*)g->adj_lam, cavitation, p_cav, w0, w1, w2, w3, g->adj_part);
+    else
+        hipLaunchKernelGGL((k_adjoint_sens<4>), dim3(cm1.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm1, g->tables(),
+                           p0, (const double*)g->adj_lam, cavitation, p_cav, 0.0, 0.0, 0.0, 0.0, g->adj_part);
+    HIPLAUNCHCHK("k_adjoint_sens");
+    hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm1, w ? 8 : 32,
+                       (const double*)g->adj_part, J);
+    HIPLAUNCHCHK("k_adjoint_finalize");
+    HIPCHK(hipStreamSynchronize(st));
+    return GAP_OK;
 }
 
 gap_status integrate_force_moment(gap_grid_t g, const double* p, int32_t cavitation, double p_cav, double* F,

@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ECONTACT", -3: "GAP_ENOC
 
 GAP_PRECOND_JACOBI, GAP_PRECOND_ASSOR1, GAP_PRECOND_ASSOR2 = 0, 1, 2
 GAP_SCALARS_GLOBAL, GAP_SCALARS_PER_COND = 0, 1
+GAP_STRATEGY_SYNC, GAP_STRATEGY_ASYNC = 0, 1
 GAP_CAVITATION_NONE, GAP_CAVITATION_CLAMP = 0, 1
 GAP_MAX_COND = 9
 GAP_KERNEL_PCG_A, GAP_KERNEL_PCG_B = 0, 1
@@ -51,7 +52,7 @@ class gap_solver_opts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("neumann", ctypes.c_int32), ("scalars", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("strategy", ctypes.c_int32)]
 
 
 class gap_solve_info(ctypes.Structure):
@@ -85,6 +86,8 @@ _SIGNATURES = {
     "integrate_force_moment": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
     "jacobian_fd": [_P, _P, _P, _P],
     "gap_read_system": [_P, ctypes.c_int32, _P, _P, _P, _P],
+    "jacobian_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.c_double, _D8, _P,
+                         ctypes.POINTER(gap_solve_info), _P],
     "gap_kernel_timing": [_P, ctypes.c_int32],
     "gap_kernel_stats": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
 }
@@ -188,6 +191,16 @@ def integrate_force_moment(handle, p_ptr, cavitation, p_cav, F_ptr, stream=None)
 
 def jacobian_fd(handle, F_ptr, J_ptr, stream=None):
     _check(load().jacobian_fd(handle, ctypes.c_void_p(int(F_ptr)), ctypes.c_void_p(int(J_ptr)), _stream(stream)))
+
+
+def jacobian_adjoint(handle, opts, p0_ptr, cavitation, p_cav, w, J_ptr, stream=None):
+    """Adjoint Jacobian (w None: 4 x 8 into J) or vector-Jacobian product (w: 4 weights,
+    8 values into J).  Returns the gap_solve_info of the adjoint solve."""
+    info = gap_solve_info()
+    _check(load().jacobian_adjoint(handle, ctypes.byref(opts), ctypes.c_void_p(int(p0_ptr)), int(cavitation),
+                                   float(p_cav), _darr(w, 4), ctypes.c_void_p(int(J_ptr)), ctypes.byref(info),
+                                   _stream(stream)), info)
+    return info
 
 
 def gap_read_system(handle, k, kx_ptr, kz_ptr, S_ptr, stream=None):

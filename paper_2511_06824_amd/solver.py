@@ -33,6 +33,7 @@ class JointGapSolver:
         self.p = torch.zeros(self.max_cond * self.n, dtype=torch.float64, device=self.device)
         self.F = torch.zeros(self.max_cond * 4, dtype=torch.float64, device=self.device)
         self.J = torch.zeros(32, dtype=torch.float64, device=self.device)
+        self.J_adj = torch.zeros(32, dtype=torch.float64, device=self.device)
         self.n_cond = 0
 
     @classmethod
@@ -61,11 +62,12 @@ class JointGapSolver:
 
     @staticmethod
     def options(omega=1.6, eps=1e-10, max_iter=100000, precond=G.GAP_PRECOND_ASSOR2, scalars=G.GAP_SCALARS_GLOBAL,
-                warm_start=False, check_every=0, neumann=1, graph=True):
+                warm_start=False, check_every=0, neumann=1, graph=True, strategy=G.GAP_STRATEGY_SYNC):
         o = G.gap_default_opts()
         o.omega, o.eps, o.max_iter = float(omega), float(eps), int(max_iter)
         o.precond, o.scalars, o.neumann = int(precond), int(scalars), int(neumann)
         o.warm_start, o.check_every, o.graph = int(bool(warm_start)), int(check_every), int(bool(graph))
+        o.strategy = int(strategy)
         return o
 
     def solve(self, opts=None, raise_on_error=True, **kw):
@@ -86,6 +88,17 @@ class JointGapSolver:
     def jacobian_fd(self):
         G.jacobian_fd(self.handle, self.F.data_ptr(), self.J.data_ptr(), _stream(self.device))
         return self.J.view(4, 8)
+
+    def jacobian_adjoint(self, opts=None, p0=None, cavitation=G.GAP_CAVITATION_NONE, p_cav=0.0, w=None, **kw):
+        """Adjoint derivative of the condition-0 forces: the 4 x 8 Jacobian (w None) or the
+        8-vector w^T J (w: 4 weights).  p0 defaults to the solved pressure of condition 0.
+        Returns (tensor, gap_solve_info of the adjoint solve)."""
+        opts = opts if opts is not None else self.options(**kw)
+        src = self.p if p0 is None else p0
+        info = G.jacobian_adjoint(self.handle, opts, src.data_ptr(), cavitation, p_cav, w, self.J_adj.data_ptr(),
+                                  _stream(self.device))
+        out = self.J_adj[:8].clone() if w is not None else self.J_adj.view(4, 8).clone()
+        return out, info
 
     def read_system(self, k):
         kx = torch.empty(self.n, dtype=torch.float64, device=self.device)

@@ -86,8 +86,9 @@ def test_null_handle_rejected_everywhere():
 
 def test_default_opts():
     o = G.gap_default_opts()
-    assert (o.omega, o.eps, o.max_iter, o.precond, o.neumann, o.scalars, o.warm_start, o.check_every, o.graph) == \
-        (1.6, 1e-10, 100000, G.GAP_PRECOND_ASSOR2, 1, G.GAP_SCALARS_GLOBAL, 0, 32, 1)
+    assert (o.omega, o.eps, o.max_iter, o.precond, o.neumann, o.scalars, o.warm_start, o.check_every, o.graph,
+            o.strategy) == (1.6, 1e-10, 100000, G.GAP_PRECOND_ASSOR2, 1, G.GAP_SCALARS_GLOBAL, 0, 32, 1,
+                            G.GAP_STRATEGY_SYNC)
 
 
 def test_create_rejects_out_of_range_dimples():

@@ -130,3 +130,52 @@ def test_zero_iterations_for_exact_start():
     exact = oracle.solve_band(A, S, gap.n_theta)
     _, it, _ = oracle.pcg(A, S, oracle.jacobi_precond(A), 1e-10, 100, p0=exact)
     assert it == 0
+
+
+def _blocks(case):
+    gap = gap_of(case)
+    tex = texture_of(case)
+    blocks, rhs = [], []
+    for ek, edk in oracle.conditions(case.e, case.edot, case.delta):
+        A, S = oracle.assemble(gap, ek, edk, tex)
+        blocks.append(A)
+        rhs.append(S)
+    return blocks, rhs
+
+
+def test_block_pcg_global_sync_equals_pcg_on_joint_matrix():
+    case = synth.textured_case(48, 24, 1)
+    blocks, rhs = _blocks(case)
+    M = [oracle.assor2_precond(A, 1.6) for A in blocks]
+    pb, itb, hb = oracle.pcg_blocks(blocks, rhs, M, 1e-10, 10000, "global", "sync")
+    AG = sp.block_diag(blocks, format="csr")
+    pG, itG, hG = oracle.pcg(AG, np.concatenate(rhs), oracle.assor2_precond(AG, 1.6), 1e-10, 10000)
+    assert itb == itG
+    assert np.allclose(hb, hG, rtol=1e-8, atol=0)
+    assert np.linalg.norm(np.concatenate(pb) - pG) <= 1e-12 * np.linalg.norm(pG)
+
+
+def test_block_pcg_per_cond_async_equals_solo_solves():
+    """Independent recurrences stopped by their own test are exactly the solo solves."""
+    case = synth.textured_case(48, 24, 2)
+    blocks, rhs = _blocks(case)
+    M = [oracle.assor2_precond(A, 1.6) for A in blocks]
+    pb, itb, _ = oracle.pcg_blocks(blocks, rhs, M, 1e-10, 10000, "per_cond", "async")
+    its = []
+    for k, (A, S) in enumerate(zip(blocks, rhs)):
+        ps, it, _ = oracle.pcg(A, S, M[k], 1e-10, 10000)
+        its.append(it)
+        assert np.array_equal(ps, pb[k])
+    assert itb == max(its)
+
+
+def test_block_pcg_variants_reach_the_solution():
+    case = synth.smooth_case(40, 20, 3)
+    blocks, rhs = _blocks(case)
+    M = [oracle.assor2_precond(A, 1.8) for A in blocks]
+    exact = [oracle.solve_band(A, S, 40) for A, S in zip(blocks, rhs)]
+    for sc in ("global", "per_cond"):
+        for st in ("sync", "async"):
+            pb, it, _ = oracle.pcg_blocks(blocks, rhs, M, 1e-12, 10000, sc, st)
+            for k in range(len(blocks)):
+                assert np.linalg.norm(pb[k] - exact[k]) <= 1e-9 * np.linalg.norm(exact[k]), (sc, st, k)
