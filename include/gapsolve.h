@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 typedef struct gap_grid_s *gap_grid_t;
+typedef struct gap_batch_s *gap_batch_t;
 
 typedef enum {
     GAP_OK = 0,
@@ -54,7 +55,8 @@ typedef enum {
     GAP_ENONFINITE = -4,  /* a NaN/Inf appeared in a reduction; the solve was stopped */
     GAP_ENOMEM = -5,      /* a device or pinned-host allocation failed */
     GAP_EDEVICE = -6,     /* a HIP runtime call failed */
-    GAP_ESTATE = -7       /* call out of order (e.g. solve before assemble) */
+    GAP_ESTATE = -7,      /* call out of order (e.g. solve before assemble) */
+    GAP_EBUDGET = -8      /* no batch slot (or memory budget) is free for another request */
 } gap_status;
 
 enum { GAP_PRECOND_JACOBI = 0, GAP_PRECOND_ASSOR1 = 1, GAP_PRECOND_ASSOR2 = 2 };
@@ -220,6 +222,51 @@ enum {
 };
 gap_status gap_kernel_timing(gap_grid_t grid, int32_t enable);
 gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Device bytes a handle of this geometry holds (create_gap_grid with max_cond) plus the
+ * caller's pressure field of max_cond * n doubles: the figure an admission controller
+ * compares against its HBM budget.  The adjoint buffers (allocated on the first
+ * jacobian_adjoint) are not included.  Errors: GAP_EINVAL. */
+gap_status gap_grid_bytes(const gap_geom *geom, int32_t max_cond, int64_t *bytes);
+
+/* ---- Batched execution (serving): several joint systems, possibly of different grids,
+ * advance together, one launch per PCG kernel per iteration over all active requests.
+ * Each request keeps its own scalars, stopping test and Krylov state on the device (in its
+ * grid handle), so requests can join and leave between steps.  The work split of a request
+ * depends only on its own grid and condition count, so its result is bitwise the same alone
+ * and in any mix.  All calls of one batch must use the same stream; not thread-safe. */
+
+/* Create an empty batch.  Errors: GAP_EINVAL, GAP_ENOMEM, GAP_EDEVICE. */
+gap_status gap_batch_create(gap_batch_t *out);
+
+/* Destroy a batch (the grid handles of its requests are not touched).  NULL is a no-op. */
+gap_status gap_batch_destroy(gap_batch_t batch);
+
+/* Add a request: `grid` must be assembled (its conditions form the joint system), p is its
+ * device solution array (n_cond * n doubles; the initial guess if opts->warm_start), opts as
+ * for solve_joint_pcg (check_every and graph are ignored here).  Computes the initial
+ * residual on `stream` and returns the request id in *id.  The grid, p and opts must stay
+ * unchanged until the request is removed.  Errors: GAP_EINVAL, GAP_ESTATE, GAP_EBUDGET (all
+ * 128 slots in use), GAP_ENOMEM, GAP_EDEVICE. */
+gap_status gap_batch_add(gap_batch_t batch, gap_grid_t grid, const gap_solver_opts *opts, double *p, int32_t *id,
+                         void *stream);
+
+/* Run `iterations` PCG iterations of every active request (use_graph nonzero: the block of
+ * launches is captured once into a hipGraph and replayed while the set of requests is
+ * unchanged), then read every request's device record.  *n_done (may be NULL) receives the
+ * number of requests that have finished (converged or stopped).  Synchronizes stream.
+ * Errors: GAP_EINVAL, GAP_EDEVICE. */
+gap_status gap_batch_step(gap_batch_t batch, int32_t iterations, int32_t use_graph, int32_t *n_done, void *stream);
+
+/* Ids of the finished requests (as of the last step): up to cap ids into ids (may be NULL),
+ * the total count into *count.  Errors: GAP_EINVAL. */
+gap_status gap_batch_poll(gap_batch_t batch, int32_t *ids, int32_t cap, int32_t *count);
+
+/* Remove a request (finished, or cancelled before that) and fill info (host, may be NULL)
+ * with its iterations and residuals.  Returns GAP_OK for a converged request, GAP_ENOCONV
+ * for one removed early or stopped at max_iter, GAP_ENONFINITE.  Its p holds the last
+ * iterate.  Errors: GAP_EINVAL (unknown id), GAP_EDEVICE. */
+gap_status gap_batch_remove(gap_batch_t batch, int32_t id, gap_solve_info *info, void *stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char *gap_last_error(void);

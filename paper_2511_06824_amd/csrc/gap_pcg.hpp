@@ -56,28 +56,24 @@ struct PcgDev {
     int nt, nz, n_cond;
     int chunks_a, rows_a;       // row chunks per condition of the A launch
     int chunks_b, rows_b;       // row chunks per condition of the B launches
-    const int* work_a;          // block -> (chunk << 4 | condition), -1 = idle (A launch)
-    const int* work_b;          // same for the B launches
-    int blocks_a, blocks_b;
     double omega, eps;
     int max_iter, per_cond, warm, precond;   // precond: 0 Jacobi, 1 ASSOR I, 2 ASSOR II
     int async;                  // 1: each condition stops at its own test (Eq 3.10) and is frozen
 };
 
-// Block -> (condition, chunk) from a schedule table built on the host (see gapsolve.hip:
-// workgroups reach the XCDs round-robin, and the table places the conditions that share an
-// operator on one XCD so that their face-conductance reads meet in its L2).
-// slot = c * chunks + k indexes the partial sums.  Returns false for idle padding blocks.
-__device__ __forceinline__ bool pcg_chunk(const int* work, int b, int chunks, int rows, int nz, int& c, int& j0,
-                                          int& j1, int& slot)
+// A launch covers one or more joint systems ("requests"), each described by a PcgDev in
+// device memory.  Block b takes work entry work[b] = request << 24 | chunk << 4 | condition
+// (-1: idle padding) from a schedule table built on the host: workgroups reach the XCDs
+// round-robin, and the table places the conditions of a request that share an operator on
+// one XCD, so that their face-conductance reads meet in its L2.
+// slot = c * chunks + k indexes the request's partial sums.
+__device__ __forceinline__ bool pcg_work(const int* work, int b, int& req, int& c, int& k)
 {
     const int w = work[b];
     if (w < 0) return false;
-    const int k = w >> 4;
+    req = w >> 24;
+    k = (w >> 4) & 0xFFFFF;
     c = w & 15;
-    j0 = k * rows;
-    j1 = min(j0 + rows, nz);
-    slot = c * chunks + k;
     return true;
 }
 
@@ -140,11 +136,14 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV])
 // ---------------------------------------------------------------------------------------
 // A(j): u = z + beta u_prev, partial u^T A u.
 template <int NT, int Q>
-__global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
+__global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, const int* __restrict__ work)
 {
+    int req, c, kc;
+    if (!pcg_work(work, blockIdx.x, req, c, kc)) return;
+    const PcgDev& a = reqs[req];
     if (a.sc->done) return;
-    int c, j0, j1, slot;
-    if (!pcg_chunk(a.work_a, blockIdx.x, a.chunks_a, a.rows_a, a.nz, c, j0, j1, slot)) return;
+    const int j0 = kc * a.rows_a, j1 = min(j0 + a.rows_a, a.nz), slot = c * a.chunks_a + kc;
+    const bool writer = (c == 0 && kc == 0);   // publishes the request's device record
     const int j = a.sc->iter_a;
     const int nt = a.nt, nz = a.nz;
     const size_t n = (size_t)nt * nz;
@@ -182,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
             if (active & (1u << k)) bad |= !finite_d(a.per_cond ? sums[0][k] / sums[1][k] : dn / dp);
     const bool converged = a.async ? (active == 0) : (rel <= a.eps);
     const bool stop = bad || converged || j >= a.max_iter;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (writer && threadIdx.x == 0) {
         PcgScalars* s = a.sc;
         s->iterations = j;
         s->rel = rel;
@@ -290,11 +289,14 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev a)
 // ---------------------------------------------------------------------------------------
 // B(j) (INIT = false) or the initial residual (INIT = true).
 template <int NT, int Q, bool INIT>
-__global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev a)
+__global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, const int* __restrict__ work)
 {
+    int req, c, kc;
+    if (!pcg_work(work, blockIdx.x, req, c, kc)) return;
+    const PcgDev& a = reqs[req];
     if (!INIT && a.sc->done) return;
-    int c, j0, j1, slot;
-    if (!pcg_chunk(a.work_b, blockIdx.x, a.chunks_b, a.rows_b, a.nz, c, j0, j1, slot)) return;
+    const int j0 = kc * a.rows_b, j1 = min(j0 + a.rows_b, a.nz), slot = c * a.chunks_b + kc;
+    const bool writer = (c == 0 && kc == 0);   // publishes the request's device record
     const int j = INIT ? -1 : a.sc->iter_b;
     const int nt = a.nt, nz = a.nz;
     const size_t n = (size_t)nt * nz;
@@ -318,15 +320,15 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev a)
         if (!a.per_cond) bad |= !finite_d(num / den);
         alpha = a.per_cond ? sums[0][c] / sums[1][c] : num / den;
         if (bad) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (writer && threadIdx.x == 0) {
                 a.sc->status = -4;
                 a.sc->done = 1;
             }
             return;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->iter_a = j + 1;
+        if (writer && threadIdx.x == 0) a.sc->iter_a = j + 1;
         if (!(active & (1u << c))) return;
-    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    } else if (writer && threadIdx.x == 0) {
         a.sc->iter_a = 0;
         a.sc->iter_b = 0;
         a.sc->done = 0;

@@ -86,23 +86,29 @@ void pcg_chunks(int nz, int n_cond, int slots, int& chunks, int& rows)
     chunks = (nz + rows - 1) / rows;
 }
 
-// Schedule of one PCG launch.  Workgroup b is dispatched to XCD b % 8; the conditions of
-// one chunk row that share an operator form a group that is kept on one XCD (their reads of
-// the operator then meet in that XCD's L2), groups are spread so that every XCD gets the
-// same number of workgroups (largest groups first, to the least loaded XCD), and idle
-// entries (-1) pad the XCD lists to equal length.  Entry = chunk << 4 | condition.
-std::vector<int> pcg_schedule(int chunks, int n_cond, const int* op)
+// Packed work entry of a PCG launch: request << 24 | chunk << 4 | condition.
+inline int pcg_entry(int req, int k, int c) { return (req << 24) | (k << 4) | c; }
+
+// Work groups of one request: per chunk row, the conditions that share an operator.
+void pcg_groups(int req, int chunks, int n_cond, const int* op, std::vector<std::vector<int>>& groups)
+{
+    for (int k = 0; k < chunks; ++k) {
+        std::vector<std::vector<int>> by_op(GAP_MAXC);
+        for (int c = 0; c < n_cond; ++c) by_op[op[c]].push_back(pcg_entry(req, k, c));
+        for (auto& gcl : by_op)
+            if (!gcl.empty()) groups.push_back(gcl);
+    }
+}
+
+// Schedule table of one PCG launch.  Workgroup b is dispatched to XCD b % 8; each group is
+// kept on one XCD (the conditions in it read the same operator, so the repeats hit that
+// XCD's L2), groups go largest first to the least loaded XCD, and idle entries (-1) pad the
+// XCD lists to equal length.
+std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
 {
     constexpr int X = 8;
     std::vector<std::vector<int>> lists(X);
     std::vector<int> load(X, 0);
-    std::vector<std::vector<int>> groups;
-    for (int k = 0; k < chunks; ++k) {
-        std::vector<std::vector<int>> by_op(GAP_MAXC);
-        for (int c = 0; c < n_cond; ++c) by_op[op[c]].push_back((k << 4) | c);
-        for (auto& gcl : by_op)
-            if (!gcl.empty()) groups.push_back(gcl);
-    }
     std::stable_sort(groups.begin(), groups.end(),
                      [](const std::vector<int>& x, const std::vector<int>& y) { return x.size() > y.size(); });
     for (const auto& gcl : groups) {
@@ -132,7 +138,7 @@ hipError_t pcg_prepare_t(int which, int nt, int* occupancy)
 {
     const void* fn = pcg_fn<NT, Q>(which);
     const size_t lds = pcg_lds_bytes(which, nt);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pcg_lds_bytes(1, NT * Q));
     if (e != hipSuccess) return e;
     int nb = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds);
@@ -142,17 +148,17 @@ hipError_t pcg_prepare_t(int which, int nt, int* occupancy)
 }
 
 template <int NT, int Q>
-hipError_t launch_pcg_t(int which, const PcgDev& a, hipStream_t st)
+hipError_t launch_pcg_t(int which, int lds_nt, const PcgDev* reqs, const int* work, int blocks, hipStream_t st)
 {
-    const size_t lds = pcg_lds_bytes(which, a.nt);
-    const int blocks = which == 0 ? a.blocks_a : a.blocks_b;
-    if (which == 0) hipLaunchKernelGGL((k_pcg_a<NT, Q>), dim3(blocks), dim3(NT), lds, st, a);
-    else if (which == 1) hipLaunchKernelGGL((k_pcg_b<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL((k_pcg_b<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, a);
+    const size_t lds = pcg_lds_bytes(which, lds_nt);
+    if (which == 0) hipLaunchKernelGGL((k_pcg_a<NT, Q>), dim3(blocks), dim3(NT), lds, st, reqs, work);
+    else if (which == 1) hipLaunchKernelGGL((k_pcg_b<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, reqs, work);
+    else hipLaunchKernelGGL((k_pcg_b<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, reqs, work);
     return hipGetLastError();
 }
 
-// Set the LDS attribute of a kernel and read how many of its workgroups fit on one CU.
+// Set the LDS attribute of a kernel and read how many of its workgroups fit on one CU when
+// its rings have nt cells.
 hipError_t pcg_prepare(int which, int nt, int* occupancy)
 {
     int NT_, Q_;
@@ -167,19 +173,42 @@ hipError_t pcg_prepare(int which, int nt, int* occupancy)
     }
 }
 
-// which: 0 = A(j), 1 = B(j), 2 = initial residual.
-hipError_t launch_pcg(int which, const PcgDev& a, hipStream_t st)
+// which: 0 = A(j), 1 = B(j), 2 = initial residual.  The kernel shape follows shape_nt (the
+// largest ring of the requests in the launch); blocks = entries of the work table.
+hipError_t launch_pcg(int which, int shape_nt, const PcgDev* reqs, const int* work, int blocks, hipStream_t st)
 {
     int NT_, Q_;
-    pcg_shape(a.nt, NT_, Q_);
+    pcg_shape(shape_nt, NT_, Q_);
     switch (NT_ * 16 + Q_) {
-    case 64 * 16 + 1: return launch_pcg_t<64, 1>(which, a, st);
-    case 128 * 16 + 1: return launch_pcg_t<128, 1>(which, a, st);
-    case 256 * 16 + 1: return launch_pcg_t<256, 1>(which, a, st);
-    case 512 * 16 + 1: return launch_pcg_t<512, 1>(which, a, st);
-    case 512 * 16 + 2: return launch_pcg_t<512, 2>(which, a, st);
-    default: return launch_pcg_t<512, 4>(which, a, st);
+    case 64 * 16 + 1: return launch_pcg_t<64, 1>(which, shape_nt, reqs, work, blocks, st);
+    case 128 * 16 + 1: return launch_pcg_t<128, 1>(which, shape_nt, reqs, work, blocks, st);
+    case 256 * 16 + 1: return launch_pcg_t<256, 1>(which, shape_nt, reqs, work, blocks, st);
+    case 512 * 16 + 1: return launch_pcg_t<512, 1>(which, shape_nt, reqs, work, blocks, st);
+    case 512 * 16 + 2: return launch_pcg_t<512, 2>(which, shape_nt, reqs, work, blocks, st);
+    default: return launch_pcg_t<512, 4>(which, shape_nt, reqs, work, blocks, st);
     }
+}
+
+// Capture `iters` iterations (A, B launch pairs) into a graph.
+hipError_t capture_block(hipStream_t cap, int iters, int shape_nt, const PcgDev* reqs, const int* work_a, int blocks_a,
+                         const int* work_b, int blocks_b, hipGraphExec_t* exec)
+{
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int it = 0; it < iters && le == hipSuccess; ++it) {
+        le = launch_pcg(0, shape_nt, reqs, work_a, blocks_a, cap);
+        if (le == hipSuccess) le = launch_pcg(1, shape_nt, reqs, work_b, blocks_b, cap);
+    }
+    e = hipStreamEndCapture(cap, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le != hipSuccess ? le : e;
+    }
+    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e;
 }
 
 }  // namespace
@@ -211,6 +240,7 @@ struct gap_grid_s {
         int blocks_a = 0, blocks_b = 0;
     };
     std::vector<Sched> scheds;
+    PcgDev *req_dev = nullptr, *req_host = nullptr;          // the request record of this handle's launches
     double *adj_rhs = nullptr, *adj_lam = nullptr;           // adjoint right-hand sides and solutions
     double *adj_part = nullptr;                              // sensitivity partials
     int cus = 256;                                           // compute units of the device
@@ -227,7 +257,7 @@ struct gap_grid_s {
     double total_ms[GAP_KERNEL_COUNT] = {0};
     // captured iteration blocks (graph replay), by launch arguments; oldest evicted
     struct Graph {
-        PcgDev args{};
+        const int* table = nullptr;                          // schedule the graph was captured with
         int block = 0;
         hipGraphExec_t exec = nullptr;
     };
@@ -262,6 +292,8 @@ void release(gap_grid_t g)
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
     for (auto& sc : g->scheds)
         if (sc.table) (void)hipFree(sc.table);
+    if (g->req_dev) (void)hipFree(g->req_dev);
+    if (g->req_host) (void)hipHostFree(g->req_host);
     if (g->sc) (void)hipFree(g->sc);
     if (g->sc_host) (void)hipHostFree(g->sc_host);
     delete g;
@@ -323,9 +355,9 @@ gap_status timing_collect(gap_grid_t g)
 // initial residual, then blocks of check_every iterations (captured once into a hipGraph and
 // replayed, unless disabled or kernel timing is on) until the device record says done.
 // Leaves the final record in g->sc_host.
-gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_t st)
+// Fill the per-request fields of a PcgDev that come from the handle and the options.
+void fill_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o)
 {
-    const int check_every = o->check_every ? o->check_every : 32;
     a.r[0] = g->r0;
     a.r[1] = g->r1;
     a.u[0] = g->u0;
@@ -344,6 +376,12 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     a.eps = o->eps;
     a.max_iter = o->max_iter;
     a.precond = o->precond;
+}
+
+gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_t st)
+{
+    const int check_every = o->check_every ? o->check_every : 32;
+    fill_pcg(g, a, o);
     pcg_chunks(g->nz, a.n_cond, g->occ[0] * g->cus, a.chunks_a, a.rows_a);
     pcg_chunks(g->nz, a.n_cond, std::min(g->occ[1], g->occ[2]) * g->cus, a.chunks_b, a.rows_b);
 
@@ -354,8 +392,10 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     for (auto& e : g->scheds)
         if (e.key == key) sch = &e;
     if (!sch) {
-        const std::vector<int> ta = pcg_schedule(a.chunks_a, a.n_cond, a.op);
-        const std::vector<int> tb = pcg_schedule(a.chunks_b, a.n_cond, a.op);
+        std::vector<std::vector<int>> ga, gb;
+        pcg_groups(0, a.chunks_a, a.n_cond, a.op, ga);
+        pcg_groups(0, a.chunks_b, a.n_cond, a.op, gb);
+        const std::vector<int> ta = pcg_schedule(ga), tb = pcg_schedule(gb);
         gap_grid_s::Sched e;
         e.key = key;
         if (hipMalloc((void**)&e.table, (ta.size() + tb.size()) * sizeof(int)) != hipSuccess)
@@ -368,12 +408,24 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         HIPCHK(hipMemcpyAsync(sch->table + ta.size(), tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
     }
-    a.work_a = sch->table;
-    a.work_b = sch->table + sch->blocks_a;
-    a.blocks_a = sch->blocks_a;
-    a.blocks_b = sch->blocks_b;
+    const int* work_a = sch->table;
+    const int* work_b = sch->table + sch->blocks_a;
+    // the request record the kernels read (pinned staging, stream-ordered copy)
+    if (!g->req_dev) {
+        if (hipMalloc((void**)&g->req_dev, sizeof(PcgDev)) != hipSuccess) {
+            g->req_dev = nullptr;
+            return fail(GAP_ENOMEM, "hipMalloc of the request record failed");
+        }
+        if (hipHostMalloc((void**)&g->req_host, sizeof(PcgDev), hipHostMallocDefault) != hipSuccess) {
+            g->req_host = nullptr;
+            return fail(GAP_ENOMEM, "hipHostMalloc of the request record failed");
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));           // the staging record may still feed an earlier copy
+    *g->req_host = a;
+    HIPCHK(hipMemcpyAsync(g->req_dev, g->req_host, sizeof(PcgDev), hipMemcpyHostToDevice, st));
 
-    hipError_t le = launch_pcg(2, a, st);
+    hipError_t le = launch_pcg(2, g->nt, g->req_dev, work_b, sch->blocks_b, st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
 
     // One block = check_every iterations (A, B launch pairs); after each block the host reads
@@ -381,42 +433,35 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     auto enqueue_block = [&](hipStream_t s) -> hipError_t {
         for (int it = 0; it < check_every; ++it) {
             timing_mark(g, GAP_KERNEL_PCG_A, true, s);
-            hipError_t e1 = launch_pcg(0, a, s);
+            hipError_t e1 = launch_pcg(0, g->nt, g->req_dev, work_a, sch->blocks_a, s);
             timing_mark(g, GAP_KERNEL_PCG_A, false, s);
             if (e1 != hipSuccess) return e1;
             timing_mark(g, GAP_KERNEL_PCG_B, true, s);
-            e1 = launch_pcg(1, a, s);
+            e1 = launch_pcg(1, g->nt, g->req_dev, work_b, sch->blocks_b, s);
             timing_mark(g, GAP_KERNEL_PCG_B, false, s);
             if (e1 != hipSuccess) return e1;
         }
         return hipSuccess;
     };
     // Event pairs around each launch need plain launches: events recorded by graph nodes
-    // cannot be read back with hipEventElapsedTime.
+    // cannot be read back with hipEventElapsedTime.  The kernels read the request record
+    // from device memory, so one graph per (schedule, block size) serves every solve.
     const bool use_graph = o->graph != 0 && !g->timing;
     hipGraphExec_t exec = nullptr;
     if (use_graph) {
         for (auto& gr : g->graphs)
-            if (gr.block == check_every && std::memcmp(&gr.args, &a, sizeof a) == 0) exec = gr.exec;
+            if (gr.block == check_every && gr.table == sch->table) exec = gr.exec;
         if (!exec) {
             if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            hipGraph_t graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t ce = enqueue_block(g->cap_stream);
-            hipError_t ee = hipStreamEndCapture(g->cap_stream, &graph);
-            if (ce != hipSuccess || ee != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce != hipSuccess ? ce : ee));
-            }
-            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (ie != hipSuccess) return fail(GAP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            hipError_t ce = capture_block(g->cap_stream, check_every, g->nt, g->req_dev, work_a, sch->blocks_a, work_b,
+                                          sch->blocks_b, &exec);
+            if (ce != hipSuccess) return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce));
             if (g->graphs.size() >= 4) {
                 (void)hipGraphExecDestroy(g->graphs.front().exec);
                 g->graphs.erase(g->graphs.begin());
             }
             gap_grid_s::Graph gr;
-            gr.args = a;
+            gr.table = sch->table;
             gr.block = check_every;
             gr.exec = exec;
             g->graphs.push_back(gr);
@@ -898,6 +943,306 @@ gap_status gap_read_system(gap_grid_t g, int32_t k, double* kx, double* kz, doub
     if (kx) HIPCHK(hipMemcpyAsync(kx, g->kx + o * n, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (kz) HIPCHK(hipMemcpyAsync(kz, g->kz + o * (n + nt), (n + nt) * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (S) HIPCHK(hipMemcpyAsync(S, g->S + k * n, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return GAP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Batched execution of several joint systems (requests) of possibly different grids.
+
+__global__ void k_gather_records(const PcgDev* __restrict__ reqs, int cap, PcgScalars* __restrict__ out)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < cap && reqs[s].sc) out[s] = *reqs[s].sc;
+}
+
+struct gap_batch_s {
+    static constexpr int kCap = 128;                         // request slots (work entries hold 8 bits)
+    struct Req {
+        int id = 0, slot = 0;
+        gap_grid_t g = nullptr;
+        bool done = false;
+    };
+    std::vector<Req> reqs;
+    PcgDev *reqs_dev = nullptr, *reqs_host = nullptr;        // slot-indexed request records
+    PcgScalars *rec_dev = nullptr, *rec_host = nullptr;      // slot-indexed copies of their device records
+    int* work = nullptr;                                     // tables A then B
+    size_t work_cap = 0;
+    int blocks_a = 0, blocks_b = 0;
+    bool dirty = true;
+    int* init_work = nullptr;
+    size_t init_cap = 0;
+    int occ_a = 1, occ_b = 1, cus = 256;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0;
+    const int* exec_work = nullptr;
+    int next_id = 1;
+};
+
+namespace {
+
+constexpr int kBatchShape = 2048;   // batch launches use the kernel shape of the largest ring
+
+void batch_release(gap_batch_t b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->reqs_dev) (void)hipFree(b->reqs_dev);
+    if (b->reqs_host) (void)hipHostFree(b->reqs_host);
+    if (b->rec_dev) (void)hipFree(b->rec_dev);
+    if (b->rec_host) (void)hipHostFree(b->rec_host);
+    if (b->work) (void)hipFree(b->work);
+    if (b->init_work) (void)hipFree(b->init_work);
+    delete b;
+}
+
+gap_status ensure_ints(int** p, size_t* cap, size_t need)
+{
+    if (need <= *cap) return GAP_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)p, need * sizeof(int)) != hipSuccess) {
+        *p = nullptr;
+        return fail(GAP_ENOMEM, "hipMalloc of a schedule table failed");
+    }
+    *cap = need;
+    return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gap_status gap_grid_bytes(const gap_geom* geom, int32_t max_cond, int64_t* bytes)
+{
+    if (!bytes) return fail(GAP_EINVAL, "bytes is NULL");
+    gap_status st = validate_geom(geom);
+    if (st != GAP_OK) return st;
+    if (max_cond != 1 && max_cond != GAP_MAX_COND) return fail(GAP_EINVAL, "max_cond must be 1 or 9");
+    const int64_t nt = geom->n_theta, nz = geom->n_axial, n = nt * nz;
+    const int64_t max_op = max_cond == GAP_MAX_COND ? 5 : 1;
+    const ChunkMap cm1 = make_chunks((int)nz, 1), cm9 = make_chunks((int)nz, GAP_MAX_COND);
+    int64_t d = 4 * nt + 2 * n + (nz + 1) * nt;              // tables and texture samples
+    d += max_op * n + max_op * (n + nt);                     // face conductances
+    d += 6 * (int64_t)max_cond * n;                          // S, r (2), u (2), z
+    d += 4 * (int64_t)std::max(cm1.total, cm9.total);        // force partials
+    d += 5 * (int64_t)max_cond * nz;                         // PCG partials
+    d += (int64_t)max_cond * n;                              // the caller's pressure field
+    *bytes = d * (int64_t)sizeof(double) + 4096;
+    return GAP_OK;
+}
+
+gap_status gap_batch_create(gap_batch_t* out)
+{
+    if (!out) return fail(GAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    gap_batch_t b = new gap_batch_s;
+    const int cap = gap_batch_s::kCap;
+    if (hipMalloc((void**)&b->reqs_dev, cap * sizeof(PcgDev)) != hipSuccess ||
+        hipHostMalloc((void**)&b->reqs_host, cap * sizeof(PcgDev), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&b->rec_dev, cap * sizeof(PcgScalars)) != hipSuccess ||
+        hipHostMalloc((void**)&b->rec_host, cap * sizeof(PcgScalars), hipHostMallocDefault) != hipSuccess) {
+        batch_release(b);
+        return fail(GAP_ENOMEM, "allocating the batch records failed");
+    }
+    std::memset(b->reqs_host, 0, cap * sizeof(PcgDev));
+    std::memset(b->rec_host, 0, cap * sizeof(PcgScalars));
+    hipError_t e = hipMemcpy(b->reqs_dev, b->reqs_host, cap * sizeof(PcgDev), hipMemcpyHostToDevice);
+    int dev = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess && hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        b->cus = 256;
+    if (e == hipSuccess) e = pcg_prepare(0, kBatchShape, &b->occ_a);
+    int occ_b = 1, occ_i = 1;
+    if (e == hipSuccess) e = pcg_prepare(1, kBatchShape, &occ_b);
+    if (e == hipSuccess) e = pcg_prepare(2, kBatchShape, &occ_i);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return fail(GAP_EDEVICE, "creating the batch: %s", hipGetErrorString(e));
+    }
+    b->occ_b = std::min(occ_b, occ_i);
+    *out = b;
+    return GAP_OK;
+}
+
+gap_status gap_batch_destroy(gap_batch_t b)
+{
+    if (!b) return GAP_OK;
+    (void)hipDeviceSynchronize();
+    batch_release(b);
+    return GAP_OK;
+}
+
+gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, double* p, int32_t* id, void* stream)
+{
+    if (!b || !g || !p || !id) return fail(GAP_EINVAL, "batch, grid, p and id must be non-NULL");
+    gap_status vs = validate_opts(o);
+    if (vs != GAP_OK) return vs;
+    if (!g->assembled) return fail(GAP_ESTATE, "gap_batch_add needs an assembled grid");
+    for (const auto& r : b->reqs)
+        if (r.g == g) return fail(GAP_EINVAL, "this grid is already in the batch");
+    int slot = -1;
+    std::vector<bool> used(gap_batch_s::kCap, false);
+    for (const auto& r : b->reqs) used[r.slot] = true;
+    for (int s = 0; s < gap_batch_s::kCap && slot < 0; ++s)
+        if (!used[s]) slot = s;
+    if (slot < 0) return fail(GAP_EBUDGET, "all %d batch slots are in use", gap_batch_s::kCap);
+    hipStream_t st = (hipStream_t)stream;
+    gap_status ps = prepare_precond(g, o, st);
+    if (ps != GAP_OK) return ps;
+
+    PcgDev a{};
+    a.kx = g->kx;
+    a.kz = g->kz;
+    a.minv = g->minv;
+    a.S = g->S;
+    a.p = p;
+    for (int c = 0; c < GAP_MAXC; ++c) a.op[c] = g->cd.op[c];
+    a.n_cond = g->n_cond;
+    a.per_cond = o->scalars == GAP_SCALARS_PER_COND;
+    a.async = o->strategy == GAP_STRATEGY_ASYNC;
+    a.warm = o->warm_start ? 1 : 0;
+    fill_pcg(g, a, o);
+    // chunking depends only on the request and the batch kernel shape, so a request gets
+    // the same reduction order (bitwise the same result) alone and in any mix
+    pcg_chunks(g->nz, a.n_cond, b->occ_a * b->cus, a.chunks_a, a.rows_a);
+    pcg_chunks(g->nz, a.n_cond, b->occ_b * b->cus, a.chunks_b, a.rows_b);
+    HIPCHK(hipStreamSynchronize(st));
+    b->reqs_host[slot] = a;
+    HIPCHK(hipMemcpyAsync(b->reqs_dev + slot, b->reqs_host + slot, sizeof(PcgDev), hipMemcpyHostToDevice, st));
+
+    std::vector<std::vector<int>> gb;
+    pcg_groups(slot, a.chunks_b, a.n_cond, a.op, gb);
+    const std::vector<int> tb = pcg_schedule(gb);
+    gap_status es = ensure_ints(&b->init_work, &b->init_cap, tb.size());
+    if (es != GAP_OK) return es;
+    HIPCHK(hipMemcpyAsync(b->init_work, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    hipError_t le = launch_pcg(2, kBatchShape, b->reqs_dev, b->init_work, (int)tb.size(), st);
+    if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
+    HIPCHK(hipStreamSynchronize(st));
+
+    gap_batch_s::Req r;
+    r.id = b->next_id++;
+    r.slot = slot;
+    r.g = g;
+    b->reqs.push_back(r);
+    b->dirty = true;
+    *id = r.id;
+    return GAP_OK;
+}
+
+gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, int32_t* n_done, void* stream)
+{
+    if (!b) return fail(GAP_EINVAL, "batch is NULL");
+    if (iterations < 1) return fail(GAP_EINVAL, "iterations must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    if (b->dirty) {
+        std::vector<std::vector<int>> ga, gb;
+        for (const auto& r : b->reqs) {
+            if (r.done) continue;
+            const PcgDev& a = b->reqs_host[r.slot];
+            pcg_groups(r.slot, a.chunks_a, a.n_cond, a.op, ga);
+            pcg_groups(r.slot, a.chunks_b, a.n_cond, a.op, gb);
+        }
+        const std::vector<int> ta = pcg_schedule(ga), tb = pcg_schedule(gb);
+        gap_status es = ensure_ints(&b->work, &b->work_cap, ta.size() + tb.size() + 1);
+        if (es != GAP_OK) return es;
+        if (!ta.empty()) HIPCHK(hipMemcpyAsync(b->work, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        if (!tb.empty())
+            HIPCHK(hipMemcpyAsync(b->work + ta.size(), tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        b->blocks_a = (int)ta.size();
+        b->blocks_b = (int)tb.size();
+        b->dirty = false;
+    }
+    if (b->blocks_a > 0) {
+        const int* wa = b->work;
+        const int* wb = b->work + b->blocks_a;
+        if (use_graph) {
+            if (!b->exec || b->exec_iters != iterations || b->exec_blocks_a != b->blocks_a ||
+                b->exec_blocks_b != b->blocks_b || b->exec_work != b->work) {
+                if (b->exec) (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+                if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+                hipError_t ce = capture_block(b->cap_stream, iterations, kBatchShape, b->reqs_dev, wa, b->blocks_a, wb,
+                                              b->blocks_b, &b->exec);
+                if (ce != hipSuccess) {
+                    b->exec = nullptr;
+                    return fail(GAP_EDEVICE, "capturing the batch block: %s", hipGetErrorString(ce));
+                }
+                b->exec_iters = iterations;
+                b->exec_blocks_a = b->blocks_a;
+                b->exec_blocks_b = b->blocks_b;
+                b->exec_work = b->work;
+            }
+            HIPCHK(hipGraphLaunch(b->exec, st));
+        } else {
+            for (int it = 0; it < iterations; ++it) {
+                hipError_t le = launch_pcg(0, kBatchShape, b->reqs_dev, wa, b->blocks_a, st);
+                if (le == hipSuccess) le = launch_pcg(1, kBatchShape, b->reqs_dev, wb, b->blocks_b, st);
+                if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a batch iteration: %s", hipGetErrorString(le));
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_gather_records, dim3(1), dim3(gap_batch_s::kCap), 0, st, (const PcgDev*)b->reqs_dev,
+                       gap_batch_s::kCap, b->rec_dev);
+    HIPLAUNCHCHK("k_gather_records");
+    HIPCHK(hipMemcpyAsync(b->rec_host, b->rec_dev, gap_batch_s::kCap * sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int done = 0;
+    for (auto& r : b->reqs) {
+        if (!r.done && b->rec_host[r.slot].done) {
+            r.done = true;
+            b->dirty = true;
+        }
+        done += r.done ? 1 : 0;
+    }
+    if (n_done) *n_done = done;
+    return GAP_OK;
+}
+
+gap_status gap_batch_poll(gap_batch_t b, int32_t* ids, int32_t cap, int32_t* count)
+{
+    if (!b || !count) return fail(GAP_EINVAL, "batch and count must be non-NULL");
+    int k = 0;
+    for (const auto& r : b->reqs)
+        if (r.done) {
+            if (ids && k < cap) ids[k] = r.id;
+            ++k;
+        }
+    *count = k;
+    return GAP_OK;
+}
+
+gap_status gap_batch_remove(gap_batch_t b, int32_t id, gap_solve_info* info, void* stream)
+{
+    if (!b) return fail(GAP_EINVAL, "batch is NULL");
+    auto it = std::find_if(b->reqs.begin(), b->reqs.end(), [&](const gap_batch_s::Req& r) { return r.id == id; });
+    if (it == b->reqs.end()) return fail(GAP_EINVAL, "no request %d in the batch", id);
+    hipStream_t st = (hipStream_t)stream;
+    const PcgScalars& h = b->rec_host[it->slot];
+    gap_status result = GAP_OK;
+    if (!it->done) result = fail(GAP_ENOCONV, "request %d removed before convergence", id);
+    else if (h.status == -4) result = fail(GAP_ENONFINITE, "request %d: non-finite value", id);
+    else if (h.status == -3) result = fail(GAP_ENOCONV, "request %d: no convergence after %d iterations", id, h.iterations);
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iterations = h.iterations;
+        info->n_cond = b->reqs_host[it->slot].n_cond;
+        info->rel_residual = h.rel;
+        for (int c = 0; c < info->n_cond; ++c) info->rel_residual_cond[c] = h.rel_cond[c];
+        info->status = result;
+    }
+    // clear the slot so the record gather skips it
+    HIPCHK(hipStreamSynchronize(st));
+    std::memset(b->reqs_host + it->slot, 0, sizeof(PcgDev));
+    HIPCHK(hipMemcpyAsync(b->reqs_dev + it->slot, b->reqs_host + it->slot, sizeof(PcgDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    b->reqs.erase(it);
+    b->dirty = true;
     return GAP_OK;
 }
 

@@ -22,8 +22,10 @@ GAP_ENONFINITE = -4
 GAP_ENOMEM = -5
 GAP_EDEVICE = -6
 GAP_ESTATE = -7
+GAP_EBUDGET = -8
 STATUS_NAMES = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ECONTACT", -3: "GAP_ENOCONV",
-                -4: "GAP_ENONFINITE", -5: "GAP_ENOMEM", -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
+                -4: "GAP_ENONFINITE", -5: "GAP_ENOMEM", -6: "GAP_EDEVICE", -7: "GAP_ESTATE",
+                -8: "GAP_EBUDGET"}
 
 GAP_PRECOND_JACOBI, GAP_PRECOND_ASSOR1, GAP_PRECOND_ASSOR2 = 0, 1, 2
 GAP_SCALARS_GLOBAL, GAP_SCALARS_PER_COND = 0, 1
@@ -88,6 +90,13 @@ _SIGNATURES = {
     "gap_read_system": [_P, ctypes.c_int32, _P, _P, _P, _P],
     "jacobian_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.c_double, _D8, _P,
                          ctypes.POINTER(gap_solve_info), _P],
+    "gap_grid_bytes": [ctypes.POINTER(gap_geom), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
+    "gap_batch_create": [ctypes.POINTER(_P)],
+    "gap_batch_destroy": [_P],
+    "gap_batch_add": [_P, _P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(ctypes.c_int32), _P],
+    "gap_batch_step": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
+    "gap_batch_poll": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "gap_batch_remove": [_P, ctypes.c_int32, ctypes.POINTER(gap_solve_info), _P],
     "gap_kernel_timing": [_P, ctypes.c_int32],
     "gap_kernel_stats": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
 }
@@ -219,3 +228,48 @@ def gap_kernel_stats(handle, kernel):
     ms = ctypes.c_double(0.0)
     _check(load().gap_kernel_stats(handle, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def gap_grid_bytes(geom, max_cond):
+    b = ctypes.c_int64(0)
+    _check(load().gap_grid_bytes(ctypes.byref(geom), int(max_cond), ctypes.byref(b)))
+    return b.value
+
+
+def gap_batch_create():
+    h = ctypes.c_void_p()
+    _check(load().gap_batch_create(ctypes.byref(h)))
+    return h
+
+
+def gap_batch_destroy(batch):
+    _check(load().gap_batch_destroy(batch))
+
+
+def gap_batch_add(batch, grid, opts, p_ptr, stream=None):
+    rid = ctypes.c_int32(0)
+    _check(load().gap_batch_add(batch, grid, ctypes.byref(opts), ctypes.c_void_p(int(p_ptr)), ctypes.byref(rid),
+                                _stream(stream)))
+    return rid.value
+
+
+def gap_batch_step(batch, iterations, use_graph=True, stream=None):
+    nd = ctypes.c_int32(0)
+    _check(load().gap_batch_step(batch, int(iterations), int(bool(use_graph)), ctypes.byref(nd), _stream(stream)))
+    return nd.value
+
+
+def gap_batch_poll(batch, cap=128):
+    ids = (ctypes.c_int32 * cap)()
+    count = ctypes.c_int32(0)
+    _check(load().gap_batch_poll(batch, ids, int(cap), ctypes.byref(count)))
+    return [ids[k] for k in range(min(count.value, cap))]
+
+
+def gap_batch_remove(batch, rid, stream=None, raise_on_error=True):
+    """Returns (status, gap_solve_info)."""
+    info = gap_solve_info()
+    st = load().gap_batch_remove(batch, int(rid), ctypes.byref(info), _stream(stream))
+    if raise_on_error:
+        _check(st, info)
+    return st, info

@@ -1,0 +1,207 @@
+"""Continuous-batching service for joint piston-gap solves.
+
+Requests (one joint 9-condition solve each, any grid size) arrive over time.  A request is
+admitted as soon as its device footprint fits the HBM budget and a batch slot is free; it is
+then assembled and joins the running batch, whose every step advances all active requests
+by a block of PCG iterations with one launch per kernel per iteration (gap_batch_* in the
+HIP library).  Finished requests are integrated (forces, FD Jacobian), their memory is
+released and the next queued requests are admitted.  Latency = completion - arrival.
+
+The admission and scheduling logic (``AdmissionController``, ``GapServer``) is independent
+of the device: ``BatchBackend`` drives the HIP library, tests may substitute a fake backend
+with its own clock.
+"""
+
+import time
+from dataclasses import dataclass, field
+from typing import Any, List, Optional
+
+import numpy as np
+
+
+class AdmissionController:
+    """Admits requests while their summed device footprint stays within a byte budget."""
+
+    def __init__(self, budget_bytes, max_active=128):
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.used = 0
+        self.active = 0
+
+    def fits(self, nbytes):
+        return self.active < self.max_active and self.used + nbytes <= self.budget
+
+    def admit(self, nbytes):
+        if not self.fits(nbytes):
+            return False
+        self.used += nbytes
+        self.active += 1
+        return True
+
+    def release(self, nbytes):
+        self.used -= nbytes
+        self.active -= 1
+        assert self.used >= 0 and self.active >= 0
+
+
+@dataclass
+class Request:
+    rid: int
+    case: Any
+    arrival: float
+    nbytes: int = 0
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    iterations: int = 0
+    status: int = 0
+    F: Optional[np.ndarray] = None
+    J: Optional[np.ndarray] = None
+    p: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def size_class(self):
+        return f"{self.case.n_theta}x{self.case.n_axial}"
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def sleep_until(self, t):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(dt)
+
+
+class BatchBackend:
+    """Drives the HIP library: one JointGapSolver handle per request, one gap_batch."""
+
+    def __init__(self, device="cuda:0", iterations_per_step=16, use_graph=True, keep_pressure=False):
+        import torch
+        from . import gapsolve as G
+        from .solver import JointGapSolver
+        self.torch, self.G, self.Solver = torch, G, JointGapSolver
+        self.device = torch.device(device)
+        self.iters = int(iterations_per_step)
+        self.use_graph = use_graph
+        self.keep_pressure = keep_pressure
+        self.batch = G.gap_batch_create()
+        self.live = {}
+
+    def footprint(self, case):
+        return self.Solver.device_bytes(case.n_theta, case.n_axial, 9)
+
+    def start(self, req):
+        case = req.case
+        s = self.Solver.from_case(case, max_cond=9, device=self.device)
+        s.assemble(case.e, case.edot, case.delta, 9)
+        opts = s.options(omega=case.omega, eps=case.eps)
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        bid = self.G.gap_batch_add(self.batch, s.handle, opts, s.p.data_ptr(), stream)
+        self.live[bid] = (s, req, opts)
+
+    def step(self):
+        """Advance every active request; return the requests finished in this step."""
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        self.G.gap_batch_step(self.batch, self.iters, self.use_graph, stream)
+        out = []
+        for bid in self.G.gap_batch_poll(self.batch):
+            s, req, _ = self.live.pop(bid)
+            st, info = self.G.gap_batch_remove(self.batch, bid, stream, raise_on_error=False)
+            req.status, req.iterations = st, info.iterations
+            req.F = s.integrate().cpu().numpy().copy()
+            req.J = s.jacobian_fd().cpu().numpy().copy()
+            if self.keep_pressure:
+                req.p = s.pressure().cpu().numpy().copy()
+            s.close()
+            out.append(req)
+        return out
+
+    def idle(self):
+        return not self.live
+
+    def close(self):
+        for s, _, _ in self.live.values():
+            s.close()
+        self.live.clear()
+        self.G.gap_batch_destroy(self.batch)
+
+
+class GapServer:
+    """Event loop: admit by arrival order and budget, step the batch, retire finished work."""
+
+    def __init__(self, backend, budget_bytes, clock=None):
+        self.backend = backend
+        self.admission = AdmissionController(budget_bytes)
+        self.clock = clock or WallClock()
+
+    def run(self, requests: List[Request]):
+        pending = sorted(requests, key=lambda r: r.arrival)
+        for r in pending:
+            r.nbytes = self.backend.footprint(r.case)
+            if r.nbytes > self.admission.budget:
+                raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
+        done = []
+        queue = []
+        while pending or queue or not self.backend.idle():
+            now = self.clock.now()
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.pop(0))
+            # admit in arrival order while memory and slots allow (no overtaking)
+            while queue and self.admission.admit(queue[0].nbytes):
+                r = queue.pop(0)
+                r.admitted = self.clock.now()
+                self.backend.start(r)
+            if self.backend.idle():
+                if pending:
+                    self.clock.sleep_until(pending[0].arrival)
+                continue
+            for r in self.backend.step():
+                r.finished = self.clock.now()
+                self.admission.release(r.nbytes)
+                done.append(r)
+        return done
+
+
+def latency_stats(done):
+    """p50 / p99 latency overall and per size class, and throughput."""
+    lat = np.array([r.latency for r in done])
+    t_first = min(r.arrival for r in done)
+    t_last = max(r.finished for r in done)
+    out = {"requests": len(done), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "mean_s": float(lat.mean()), "solves_per_s": len(done) / (t_last - t_first), "per_class": {}}
+    for cls in sorted({r.size_class for r in done}, key=lambda c: int(c.split("x")[0])):
+        lc = np.array([r.latency for r in done if r.size_class == cls])
+        out["per_class"][cls] = {"n": int(lc.size), "p50_s": float(np.percentile(lc, 50)),
+                                 "p99_s": float(np.percentile(lc, 99))}
+    return out
+
+
+def run_fifo(requests, device="cuda:0", clock=None):
+    """Baseline: the same requests solved one at a time in arrival order (plain handles,
+    no batching)."""
+    import torch
+    from .solver import JointGapSolver
+    clock = clock or WallClock()
+    done = []
+    for r in sorted(requests, key=lambda q: q.arrival):
+        clock.sleep_until(r.arrival)
+        r.admitted = clock.now()
+        s = JointGapSolver.from_case(r.case, max_cond=9, device=torch.device(device))
+        s.assemble(r.case.e, r.case.edot, r.case.delta, 9)
+        _, info = s.solve(omega=r.case.omega, eps=r.case.eps)
+        r.iterations = info.iterations
+        r.F = s.integrate().cpu().numpy().copy()
+        r.J = s.jacobian_fd().cpu().numpy().copy()
+        s.close()
+        r.finished = clock.now()
+        done.append(r)
+    return done

@@ -36,6 +36,15 @@ class JointGapSolver:
         self.J_adj = torch.zeros(32, dtype=torch.float64, device=self.device)
         self.n_cond = 0
 
+    @staticmethod
+    def device_bytes(n_theta, n_axial, max_cond=9, **geom):
+        """Device bytes one solver of this grid holds (library buffers + its pressure field)."""
+        d = dict(R=0.01, clearance=2e-5, length=0.04, mu=0.04, U=0.0, V=0.0, p_in=0.0, p_out=0.0)
+        d.update(geom)
+        g = G.make_geom(d["R"], d["clearance"], d["length"], d["mu"], d["U"], d["V"], d["p_in"], d["p_out"],
+                        n_theta, n_axial)
+        return G.gap_grid_bytes(g, max_cond) + (max_cond * 4 + 64) * 8
+
     @classmethod
     def from_case(cls, case, max_cond=9, device="cuda:0"):
         dimples = None

@@ -1,0 +1,100 @@
+"""Admission and scheduling logic of the serving loop, on the CPU with a fake backend
+(mock footprints and durations, virtual clock)."""
+
+from types import SimpleNamespace
+
+import pytest
+
+from paper_2511_06824_amd.serve import AdmissionController, GapServer, Request, latency_stats
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep_until(self, t):
+        self.t = max(self.t, t)
+
+
+class FakeBackend:
+    """Every step costs step_time of virtual time and advances all active requests."""
+
+    def __init__(self, clock, step_time=1.0):
+        self.clock, self.step_time = clock, step_time
+        self.live = []
+        self.max_active = 0
+        self.started = []
+
+    def footprint(self, case):
+        return case.fake_bytes
+
+    def start(self, req):
+        self.live.append([req, req.case.fake_steps])
+        self.started.append(req.rid)
+        self.max_active = max(self.max_active, len(self.live))
+
+    def step(self):
+        self.clock.t += self.step_time
+        out = []
+        for item in self.live:
+            item[1] -= 1
+        for item in [x for x in self.live if x[1] <= 0]:
+            self.live.remove(item)
+            out.append(item[0])
+        return out
+
+    def idle(self):
+        return not self.live
+
+
+def req(rid, arrival, nbytes, steps, nt=64, nz=32):
+    return Request(rid=rid, case=SimpleNamespace(fake_bytes=nbytes, fake_steps=steps, n_theta=nt, n_axial=nz),
+                   arrival=arrival)
+
+
+def test_admission_controller_budget_and_slots():
+    a = AdmissionController(100, max_active=2)
+    assert a.admit(60) and not a.fits(50) and a.admit(40) and not a.admit(0)
+    a.release(60)
+    assert a.fits(50) and a.used == 40
+    with pytest.raises(AssertionError):
+        a.release(1000)
+
+
+def test_requests_overlap_and_respect_the_budget():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = GapServer(be, budget_bytes=100, clock=clock)
+    rs = [req(0, 0.0, 50, 5), req(1, 0.5, 50, 2), req(2, 0.6, 50, 1), req(3, 10.0, 30, 1)]
+    done = srv.run(rs)
+    assert sorted(r.rid for r in done) == [0, 1, 2, 3]
+    assert be.max_active == 2                       # never more than the budget allows
+    assert be.started == [0, 1, 2, 3]              # admitted in arrival order
+    r2 = next(r for r in done if r.rid == 2)
+    r1 = next(r for r in done if r.rid == 1)
+    assert r2.admitted >= r1.finished              # waited for memory to free up
+    r3 = next(r for r in done if r.rid == 3)
+    assert r3.admitted == 10.0                     # idle server sleeps until the arrival
+    assert all(r.latency > 0 for r in done)
+    stats = latency_stats(done)
+    assert stats["requests"] == 4 and stats["p99_s"] >= stats["p50_s"] > 0
+
+
+def test_no_overtaking_in_the_queue():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = GapServer(be, budget_bytes=100, clock=clock)
+    # a big request at the head blocks smaller ones behind it until it fits
+    rs = [req(0, 0.0, 80, 3), req(1, 0.1, 90, 1), req(2, 0.2, 10, 1)]
+    srv.run(rs)
+    assert be.started == [0, 1, 2]
+
+
+def test_request_larger_than_budget_is_rejected():
+    clock = FakeClock()
+    srv = GapServer(FakeBackend(clock), budget_bytes=10, clock=clock)
+    with pytest.raises(ValueError):
+        srv.run([req(0, 0.0, 11, 1)])
