@@ -60,6 +60,100 @@ def run_cpu_baseline(case, iterations_gpu, n_cond):
             "sample_seconds": t3 - t0, "seconds_per_solve": solve_s}
 
 
+def kernel_source_digest():
+    """sha256 of the PCG kernel sources: counter figures taken for other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gap_pcg.hpp", "gap_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2511_06824_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it was
+    taken with the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "pcg_joint_textured_2048x1024_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest = None
+    value = None
+    for line in open(path):
+        if line.startswith("kernel source digest:"):
+            digest = line.split(":", 1)[1].strip()
+        if line.startswith(f"traffic bytes per launch {kernel}:"):
+            value = int(line.split(":", 1)[1].strip())
+    return value if digest == kernel_source_digest() else None
+
+
+def run_serving(torch, count=24, seed=0, load=0.8):
+    """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
+    128x64 ... 2048x1024, smooth or with 0-200 random dimples.  Capacity is the back-to-back
+    rate of one-at-a-time solves of the same requests; arrivals run at `load` x capacity."""
+    import numpy as np
+    import synth
+    from paper_2511_06824_amd.serve import BatchBackend, GapServer, Request, latency_stats, run_fifo
+
+    def make(arrivals):
+        rng = np.random.default_rng(seed)
+        return [Request(rid=k, case=synth.served_request(rng, seed * 1000 + k), arrival=float(arrivals[k]))
+                for k in range(count)]
+
+    warm = make(np.zeros(count))[:3]
+    run_fifo(warm)
+    back = run_fifo(make(np.zeros(count)))
+    capacity = count / max(r.finished for r in back)
+    rate = load * capacity
+    arrivals = synth.poisson_arrivals(np.random.default_rng(seed + 1), rate, count)
+    free, total = torch.cuda.mem_get_info()
+    be = BatchBackend(iterations_per_step=16)
+    done = GapServer(be, budget_bytes=int(0.8 * free)).run(make(arrivals))
+    be.close()
+    fifo = run_fifo(make(arrivals))
+    bs, fs = latency_stats(done), latency_stats(fifo)
+    return {"requests": count, "arrival_rate_per_s": round(rate, 3), "capacity_one_at_a_time_per_s": round(capacity, 3),
+            "batched": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in bs.items()},
+            "one_at_a_time": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in fs.items()},
+            "hbm_budget_bytes": int(0.8 * free)}
+
+
+def run_adjoint_vs_fd(torch, JointGapSolver, dev):
+    """Cost of the 4 x 8 Jacobian on the 1024 x 512 textured workload: the 9-condition
+    forward-difference solve against one base solve plus the 4 adjoint solves."""
+    import synth
+    case = synth.make_case("adjoint_textured_1024x512", 0)
+    s = JointGapSolver.from_case(case, max_cond=9, device=dev)
+    opts = s.options(omega=case.omega, eps=case.eps)
+
+    def fd():
+        s.assemble(case.e, case.edot, case.delta, 9)
+        _, info = s.solve(opts)
+        s.integrate()
+        s.jacobian_fd()
+        return info.iterations
+
+    def adj():
+        s.assemble(case.e, case.edot, None, 1)
+        _, info = s.solve(opts)
+        s.integrate()
+        _, ainfo = s.jacobian_adjoint(opts)
+        return info.iterations, ainfo.iterations
+
+    fd(), adj()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_fd = fd()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    it_adj = adj()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    return {"workload": "adjoint_textured_1024x512", "fd_seconds": round(t1 - t0, 5), "fd_iterations": it_fd,
+            "adjoint_seconds": round(t2 - t1, 5), "adjoint_iterations": {"base": it_adj[0], "adjoint": it_adj[1]},
+            "fd_over_adjoint": round((t1 - t0) / (t2 - t1), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +163,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
@@ -138,12 +234,21 @@ def main():
     dominant = max((k for k in stats if k in nbytes), key=lambda k: stats[k]["total_ms"])
     achieved = nbytes[dominant] / (stats[dominant]["avg_us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dominant), "kernel": dominant,
                 "bytes_per_launch": nbytes[dominant], "avg_launch_us": round(stats[dominant]["avg_us"], 2)}
 
     plain = None
     if not args.no_plain:
         plain = run_plain(case, G, JointGapSolver, dev)
+
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(torch)
+        print(f"bench: served stream p50 {serving['batched']['p50_s']:.3f} s p99 {serving['batched']['p99_s']:.3f} s",
+              file=sys.stderr, flush=True)
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = run_adjoint_vs_fd(torch, JointGapSolver, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -162,7 +267,8 @@ def main():
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
-        "roofline": roofline, "plain_baseline": plain, "cpu_baseline": cpu,
+        "roofline": roofline, "plain_baseline": plain, "serving": serving, "adjoint_vs_fd": adjoint,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     solver.close()
