@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default PCG kernel configuration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
@@ -184,6 +185,16 @@ def main():
     opts = solver.options(omega=case.omega, eps=case.eps)
     print(f"bench: {case.label}, {n_cond} conditions, n = {n}, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
+
+    # autotuner: kernel shape and row chunking, timed on this system (outside the timed region)
+    tune = None
+    if not args.no_tune:
+        solver.assemble(case.e, case.edot, case.delta, 9)
+        torch.cuda.synchronize()
+        tt0 = time.perf_counter()
+        cfg, us = solver.tune(opts, iterations=20)
+        tune = {"config": cfg, "us_per_iteration": round(us, 2), "seconds": round(time.perf_counter() - tt0, 3)}
+        print(f"bench: tuned {cfg} {us:.1f} us/iteration", file=sys.stderr, flush=True)
 
     for w in range(args.warmup):
         _, _, info = solver.step(case.e, case.edot, case.delta, opts)
@@ -239,7 +250,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        plain = run_plain(case, G, JointGapSolver, dev)
+        plain = run_plain(case, G, JointGapSolver, dev, tune=not args.no_tune)
 
     serving = None
     if not args.no_serving:
@@ -264,6 +275,7 @@ def main():
                    "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "seed": args.seed},
         "gdof_iter_per_s": round(gdof, 3), "iterations": mean_iters,
         "graph_solves_per_s": round(graph_solves_per_s, 5),
+        "pcg_config": solver.pcg_config, "tune": tune,
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
@@ -274,7 +286,7 @@ def main():
     solver.close()
 
 
-def run_plain(case, G, JointGapSolver, dev):
+def run_plain(case, G, JointGapSolver, dev, tune=True):
     """The same 9 conditions solved one at a time (sequential GPU acceleration): same
     kernels, eps and omega, a host read of the residual after every iteration, forces per
     condition, the FD quotient of Eq 2.13-2.14 on the host."""
@@ -291,6 +303,8 @@ def run_plain(case, G, JointGapSolver, dev):
     s1 = JointGapSolver.from_case(case, max_cond=1, device=dev)
     opts = s1.options(omega=case.omega, eps=case.eps, check_every=1)
     s1.assemble(conds[0][0], conds[0][1], None, 1)
+    if tune:
+        s1.tune(opts, iterations=20)
     s1.solve(opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -64,6 +64,32 @@ def source(gap: Gap, e, edot, texture=no_texture):
     return S + dirichlet
 
 
+def cell_values(gap: Gap, e, edot, i, j, texture=no_texture):
+    """Entries of the assembled system at the cells (i, j) (index arrays of one shape):
+    kx(i, j), kz on the south face j and on the north face j + 1 of the cell, and S(i, j).
+    The same expressions as ``face_conductances`` and ``source``, evaluated cell by cell, so
+    that a grid too large to assemble here can be checked at sampled cells."""
+    th, z, dth, dz = cell_centers(gap)
+    dx = gap.R * dth
+    i = np.asarray(i)
+    j = np.asarray(j)
+    TH, Z = th[i], z[j]
+    zf = np.arange(gap.n_axial + 1) * dz
+    kx = film(gap, e, TH + 0.5 * dth, Z, texture) ** 3 / (12.0 * gap.mu) * (dz / dx)
+    kz_s = film(gap, e, TH, zf[j], texture) ** 3 / (12.0 * gap.mu) * (dx / dz)
+    kz_n = film(gap, e, TH, zf[j + 1], texture) ** 3 / (12.0 * gap.mu) * (dx / dz)
+    kz_s = np.where(j == 0, 2.0 * kz_s, kz_s)
+    kz_n = np.where(j == gap.n_axial - 1, 2.0 * kz_n, kz_n)
+    h_e = film(gap, e, TH + 0.5 * dth, Z, texture)
+    h_w = film(gap, e, TH - 0.5 * dth, Z, texture)
+    h_n = film(gap, e, TH, Z + 0.5 * dz, texture)
+    h_s = film(gap, e, TH, Z - 0.5 * dz, texture)
+    hdot = film_rate(gap, e, edot, TH, Z)
+    S = -(0.5 * gap.U) * (h_e - h_w) * dz - (0.5 * gap.V) * (h_n - h_s) * dx - hdot * dx * dz
+    S = S + np.where(j == 0, kz_s * gap.p_in, 0.0) + np.where(j == gap.n_axial - 1, kz_n * gap.p_out, 0.0)
+    return kx, kz_s, kz_n, S
+
+
 def stencil_matrix(gap: Gap, kx, kz):
     """Sparse n x n matrix from the face conductances (natural order, theta fastest)."""
     nt, nz = gap.n_theta, gap.n_axial

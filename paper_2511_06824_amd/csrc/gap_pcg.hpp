@@ -135,8 +135,11 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV])
 
 // ---------------------------------------------------------------------------------------
 // A(j): u = z + beta u_prev, partial u^T A u.
+// Register budgets: at least 4 waves per SIMD (<= 128 VGPRs) for A and for B with up to two
+// columns per thread; B with four columns per thread keeps 20 row values per column live and
+// runs at 2 waves per SIMD.
 template <int NT, int Q>
-__global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, const int* __restrict__ work)
+__global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs, const int* __restrict__ work)
 {
     int req, c, kc;
     if (!pcg_work(work, blockIdx.x, req, c, kc)) return;
@@ -199,7 +202,6 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
     // ---- march over the rows of the chunk ----------------------------------------------
     extern __shared__ double lds[];
     double* su = lds;             // [2][nt]  u of the current row, by row parity
-    double* skx = lds + 2 * nt;   // [2][nt]  kx of the current row
     const int op = a.op[c];
     const double* kx = a.kx + (size_t)op * n;
     const double* kz = a.kz + (size_t)op * (n + nt);
@@ -209,15 +211,17 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
     const bool first = (j == 0);
     const int t = threadIdx.x;
 
-    // registers: u of rows s-1, s, s+1; face conductances of faces s, s+1; kx of row s;
-    // and the loads of the next row step, issued one step ahead
-    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q];
-    double nz_[Q], nu_[Q], nkx[Q], nkz[Q];
+    // registers: u of rows s-1, s, s+1; face conductances of faces s, s+1; kx of row s at
+    // the own and at the western column (periodic); and the loads of the next row step,
+    // issued one step ahead.  The western kx is a second load of the same cache lines.
+    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], kwc[Q];
+    double nz_[Q], nu_[Q], nkx[Q], nkw[Q], nkz[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
-        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = 0.0;
-        nz_[q] = nu_[q] = nkx[q] = nkz[q] = 0.0;
+        const int dw = i ? -1 : nt - 1;
+        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = kwc[q] = 0.0;
+        nz_[q] = nu_[q] = nkx[q] = nkw[q] = nkz[q] = 0.0;
         if (i < nt) {
             if (j0 > 0) {
                 const size_t g = (size_t)(j0 - 1) * nt + i;
@@ -227,6 +231,7 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
             uc[q] = first ? zc[g] : zc[g] + beta * ui[g];
             kzS[q] = kz[g];
             kxc[q] = kx[g];
+            kwc[q] = kx[g + dw];
             g += nt;
             kzN[q] = kz[g];
             if (j0 + 1 < nz) {
@@ -244,16 +249,14 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
             if (i < nt && s + 1 < j1) {
                 const size_t g1 = (size_t)(s + 1) * nt + i;
                 nkx[q] = kx[g1];
+                nkw[q] = kx[g1 + (i ? -1 : nt - 1)];
                 nkz[q] = kz[g1 + nt];
                 if (s + 2 < nz) {
                     nz_[q] = zc[g1 + nt];
                     if (!first) nu_[q] = ui[g1 + nt];
                 }
             }
-            if (i < nt) {
-                su[buf * nt + i] = uc[q];
-                skx[buf * nt + i] = kxc[q];
-            }
+            if (i < nt) su[buf * nt + i] = uc[q];
         }
         __syncthreads();
 #pragma unroll
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
             if (i < nt) {
                 const int iw = i ? i - 1 : nt - 1;
                 const int ie = (i + 1 < nt) ? i + 1 : 0;
-                const double kW = skx[buf * nt + iw];
+                const double kW = kwc[q];
                 const double D = ((kxc[q] + kW) + kzS[q]) + kzN[q];
                 double v = D * uc[q] - kxc[q] * su[buf * nt + ie] - kW * su[buf * nt + iw];
                 if (s > 0) v -= kzS[q] * um[q];
@@ -278,6 +281,7 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
             kzS[q] = kzN[q];
             kzN[q] = nkz[q];
             kxc[q] = nkx[q];
+            kwc[q] = nkw[q];
             up[q] = (s + 2 < nz) ? (first ? nz_[q] : nz_[q] + beta * nu_[q]) : 0.0;
         }
     }
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(NT) void k_pcg_a(const PcgDev* __restrict__ reqs, c
 // ---------------------------------------------------------------------------------------
 // B(j) (INIT = false) or the initial residual (INIT = true).
 template <int NT, int Q, bool INIT>
-__global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, const int* __restrict__ work)
+__global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __restrict__ reqs, const int* __restrict__ work)
 {
     int req, c, kc;
     if (!pcg_work(work, blockIdx.x, req, c, kc)) return;
@@ -353,9 +357,8 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
 
     extern __shared__ double lds[];
     double* su = lds;             // u row s
-    double* skx = lds + nt;       // kx row s
-    double* sy = lds + 2 * nt;    // y = D^-1 r' row s
-    double* sv = lds + 3 * nt;    // [2][nt]: (I - w D^-1 L) y, rows by parity
+    double* sy = lds + nt;        // y = D^-1 r' row s
+    double* sv = lds + 2 * nt;    // [2][nt]: (I - w D^-1 L) y, rows by parity
 
     // rows visited: the chunk plus, for the ASSOR sweeps, one halo row on each side
     const int s_begin = assor ? max(j0 - 1, 0) : j0;
@@ -363,18 +366,19 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
     const bool updates_p = !INIT || !a.warm;   // B writes p += alpha u; cold init writes p = 0
 
     const int t = threadIdx.x;
-    // state of rows s-1, s, s+1 and of the row below (for the lagged Eq 3.6 sweep)
-    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], rc[Q], pc[Q];
+    // state of rows s-1, s, s+1 and of the row below (for the lagged Eq 3.6 sweep); kwc is
+    // kx of the western column (periodic), a second load of the same cache lines as kxc
+    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], kwc[Q], rc[Q], pc[Q];
     double yprev[Q], vprev[Q], dinvprev[Q], kxprev[Q], rpprev[Q];
     // loads of the next row step, issued one step ahead
-    double nu[Q], nkx[Q], nkz[Q], nr[Q], np[Q];
-    double kxwrap_prev = 0.0;
+    double nu[Q], nkx[Q], nkw[Q], nkz[Q], nr[Q], np[Q];
+    double kxwrap_prev = 0.0;     // thread 0: kx(nt-1) of the previous row, the west wrap of column 0
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
-        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = rc[q] = pc[q] = 0.0;
+        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = kwc[q] = rc[q] = pc[q] = 0.0;
         yprev[q] = vprev[q] = dinvprev[q] = kxprev[q] = rpprev[q] = 0.0;
-        nu[q] = nkx[q] = nkz[q] = nr[q] = np[q] = 0.0;
+        nu[q] = nkx[q] = nkw[q] = nkz[q] = nr[q] = np[q] = 0.0;
         if (i < nt) {
             const size_t g = (size_t)s_begin * nt + i;
             if (spmv) {
@@ -385,6 +389,7 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
             kzS[q] = kz[g];
             kzN[q] = kz[g + nt];
             kxc[q] = kx[g];
+            kwc[q] = kx[g + (i ? -1 : nt - 1)];
             rc[q] = rin[g];
             if (!INIT && s_begin >= j0) pc[q] = pp[g];
         }
@@ -402,6 +407,7 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
                     const size_t g1 = (size_t)(s + 1) * nt + i;
                     nu[q] = (spmv && s + 2 < nz) ? uu[g1 + nt] : 0.0;
                     nkx[q] = kx[g1];
+                    nkw[q] = kx[g1 + (i ? -1 : nt - 1)];
                     nkz[q] = kz[g1 + nt];
                     nr[q] = rin[g1];
                     np[q] = (!INIT && s + 1 >= j0 && s + 1 < j1) ? pp[g1] : 0.0;
@@ -411,24 +417,19 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = t + q * NT;
-            if (i < nt) {
-                su[i] = uc[q];
-                skx[i] = kxc[q];
-            }
+            if (i < nt) su[i] = uc[q];
         }
         __syncthreads();
-        const double kxwrap = skx[nt - 1];
-        double rp[Q], dinv[Q], y[Q], kWq[Q];
+        double rp[Q], dinv[Q], y[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = t + q * NT;
-            rp[q] = dinv[q] = y[q] = kWq[q] = 0.0;
+            rp[q] = dinv[q] = y[q] = 0.0;
             if (i < nt) {
                 const size_t g = (size_t)s * nt + i;
                 const int iw = i ? i - 1 : nt - 1;
                 const int ie = (i + 1 < nt) ? i + 1 : 0;
-                const double kW = skx[iw];
-                kWq[q] = kW;   // skx may be rewritten by the next row before the sweep below
+                const double kW = kwc[q];
                 const double D = ((kxc[q] + kW) + kzS[q]) + kzN[q];
                 const double r0 = rc[q];
                 double r1 = r0;
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
                 if (i < nt) {
                     // Eq 3.5: v = y + w D^-1 (couplings to west, south and the east wrap)
                     double lo = 0.0;
-                    if (i > 0) lo += kWq[q] * sy[i - 1];
+                    if (i > 0) lo += kwc[q] * sy[i - 1];
                     if (i == nt - 1) lo += kxc[q] * sy[0];
                     if (s > 0) lo += kzS[q] * yprev[q];
                     const double v = y[q] + om * dinv[q] * lo;
@@ -502,7 +503,9 @@ __global__ __launch_bounds__(NT) void k_pcg_b(const PcgDev* __restrict__ reqs, c
             rc[q] = nr[q];
             pc[q] = np[q];
         }
-        kxwrap_prev = kxwrap;
+        kxwrap_prev = kwc[0];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) kwc[q] = nkw[q];
     }
     // last row of the ring: no northern neighbour
     if (assor && j1 == nz) {

@@ -60,20 +60,39 @@ ChunkMap make_chunks(int nz, int n_cond)
     return cm;
 }
 
-// Threads per workgroup and ring columns per thread for a ring of nt cells.
-void pcg_shape(int nt, int& NT, int& Q)
+// Kernel shape of the PCG iteration kernels: NT threads per workgroup, Q ring columns per
+// thread (thread t handles columns t, t + NT, ...), NT * Q >= n_theta.
+struct PcgShape {
+    int NT = 512, Q = 4;
+};
+
+// Every instantiated shape.
+#define GAP_PCG_SHAPES(X) \
+    X(64, 1) X(128, 1) X(128, 2) X(256, 1) X(256, 2) X(256, 4) X(512, 1) X(512, 2) X(512, 4) X(1024, 1) X(1024, 2)
+
+bool shape_known(PcgShape sh)
 {
-    if (nt <= 64) { NT = 64; Q = 1; }
-    else if (nt <= 128) { NT = 128; Q = 1; }
-    else if (nt <= 256) { NT = 256; Q = 1; }
-    else if (nt <= 512) { NT = 512; Q = 1; }
-    else if (nt <= 1024) { NT = 512; Q = 2; }
-    else { NT = 512; Q = 4; }      // n_theta <= 2048 (validated at create)
+#define GAP_SHAPE_CASE(nt_, q_) if (sh.NT == nt_ && sh.Q == q_) return true;
+    GAP_PCG_SHAPES(GAP_SHAPE_CASE)
+#undef GAP_SHAPE_CASE
+    return false;
 }
 
-// Dynamic LDS of the A kernel (u and kx rows, double-buffered) and of the B kernels
-// (u, kx, y rows and two rows of the first ASSOR sweep).
-size_t pcg_lds_bytes(int which, int nt) { return (size_t)(which == 0 ? 4 : 5) * nt * sizeof(double); }
+// Candidate shapes for a ring of nt cells, the default first: at most one idle column slot
+// in two, and wavefront-multiple workgroups.
+std::vector<PcgShape> pcg_candidates(int nt)
+{
+    if (nt <= 64) return {{64, 1}};
+    if (nt <= 128) return {{128, 1}};
+    if (nt <= 256) return {{256, 1}, {128, 2}};
+    if (nt <= 512) return {{512, 1}, {256, 2}};
+    if (nt <= 1024) return {{512, 2}, {1024, 1}, {256, 4}};
+    return {{512, 4}, {1024, 2}};        // n_theta <= 2048 (validated at create)
+}
+
+// Dynamic LDS of the A kernel (u row, double-buffered) and of the B kernels (u and y rows,
+// two rows of the first ASSOR sweep).
+size_t pcg_lds_bytes(int which, int nt) { return (size_t)(which == 0 ? 2 : 4) * nt * sizeof(double); }
 
 // Row chunks per condition: as many workgroups as the device holds at once (occupancy x CUs),
 // so that one launch runs in a single round.
@@ -157,49 +176,40 @@ hipError_t launch_pcg_t(int which, int lds_nt, const PcgDev* reqs, const int* wo
     return hipGetLastError();
 }
 
-// Set the LDS attribute of a kernel and read how many of its workgroups fit on one CU when
-// its rings have nt cells.
-hipError_t pcg_prepare(int which, int nt, int* occupancy)
+// Set the LDS attribute of a kernel of shape sh and read how many of its workgroups fit on
+// one CU when its rings have nt cells.
+hipError_t pcg_prepare(PcgShape sh, int which, int nt, int* occupancy)
 {
-    int NT_, Q_;
-    pcg_shape(nt, NT_, Q_);
-    switch (NT_ * 16 + Q_) {
-    case 64 * 16 + 1: return pcg_prepare_t<64, 1>(which, nt, occupancy);
-    case 128 * 16 + 1: return pcg_prepare_t<128, 1>(which, nt, occupancy);
-    case 256 * 16 + 1: return pcg_prepare_t<256, 1>(which, nt, occupancy);
-    case 512 * 16 + 1: return pcg_prepare_t<512, 1>(which, nt, occupancy);
-    case 512 * 16 + 2: return pcg_prepare_t<512, 2>(which, nt, occupancy);
-    default: return pcg_prepare_t<512, 4>(which, nt, occupancy);
-    }
+#define GAP_SHAPE_CASE(nt_, q_) \
+    if (sh.NT == nt_ && sh.Q == q_) return pcg_prepare_t<nt_, q_>(which, nt, occupancy);
+    GAP_PCG_SHAPES(GAP_SHAPE_CASE)
+#undef GAP_SHAPE_CASE
+    return hipErrorInvalidValue;
 }
 
-// which: 0 = A(j), 1 = B(j), 2 = initial residual.  The kernel shape follows shape_nt (the
-// largest ring of the requests in the launch); blocks = entries of the work table.
-hipError_t launch_pcg(int which, int shape_nt, const PcgDev* reqs, const int* work, int blocks, hipStream_t st)
+// which: 0 = A(j), 1 = B(j), 2 = initial residual.  lds_nt: the largest ring of the
+// requests in the launch; blocks = entries of the work table.
+hipError_t launch_pcg(PcgShape sh, int which, int lds_nt, const PcgDev* reqs, const int* work, int blocks,
+                      hipStream_t st)
 {
-    int NT_, Q_;
-    pcg_shape(shape_nt, NT_, Q_);
-    switch (NT_ * 16 + Q_) {
-    case 64 * 16 + 1: return launch_pcg_t<64, 1>(which, shape_nt, reqs, work, blocks, st);
-    case 128 * 16 + 1: return launch_pcg_t<128, 1>(which, shape_nt, reqs, work, blocks, st);
-    case 256 * 16 + 1: return launch_pcg_t<256, 1>(which, shape_nt, reqs, work, blocks, st);
-    case 512 * 16 + 1: return launch_pcg_t<512, 1>(which, shape_nt, reqs, work, blocks, st);
-    case 512 * 16 + 2: return launch_pcg_t<512, 2>(which, shape_nt, reqs, work, blocks, st);
-    default: return launch_pcg_t<512, 4>(which, shape_nt, reqs, work, blocks, st);
-    }
+#define GAP_SHAPE_CASE(nt_, q_) \
+    if (sh.NT == nt_ && sh.Q == q_) return launch_pcg_t<nt_, q_>(which, lds_nt, reqs, work, blocks, st);
+    GAP_PCG_SHAPES(GAP_SHAPE_CASE)
+#undef GAP_SHAPE_CASE
+    return hipErrorInvalidValue;
 }
 
 // Capture `iters` iterations (A, B launch pairs) into a graph.
-hipError_t capture_block(hipStream_t cap, int iters, int shape_nt, const PcgDev* reqs, const int* work_a, int blocks_a,
-                         const int* work_b, int blocks_b, hipGraphExec_t* exec)
+hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh, int lds_nt, const PcgDev* reqs, const int* work_a,
+                         int blocks_a, const int* work_b, int blocks_b, hipGraphExec_t* exec)
 {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int it = 0; it < iters && le == hipSuccess; ++it) {
-        le = launch_pcg(0, shape_nt, reqs, work_a, blocks_a, cap);
-        if (le == hipSuccess) le = launch_pcg(1, shape_nt, reqs, work_b, blocks_b, cap);
+        le = launch_pcg(sh, 0, lds_nt, reqs, work_a, blocks_a, cap);
+        if (le == hipSuccess) le = launch_pcg(sh, 1, lds_nt, reqs, work_b, blocks_b, cap);
     }
     e = hipStreamEndCapture(cap, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -244,7 +254,9 @@ struct gap_grid_s {
     double *adj_rhs = nullptr, *adj_lam = nullptr;           // adjoint right-hand sides and solutions
     double *adj_part = nullptr;                              // sensitivity partials
     int cus = 256;                                           // compute units of the device
+    PcgShape shape{};                                        // PCG kernel shape in use
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
+    int wg_a = 1, wg_b = 1;                                  // workgroups per CU the row chunking targets
     int lds_max = 65536;                                     // bytes of LDS one workgroup may use
     int minv_kind = -1;
     double minv_omega = 0.0;
@@ -313,8 +325,9 @@ gap_status dmalloc(double** p, size_t count)
 gap_status timing_reserve(gap_grid_t g, int pairs)
 {
     while ((int)g->ev.size() < 2 * pairs) {
+        // timing-only events: no system-scope fence (no cache writeback / invalidate per event)
         hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
         if (r != hipSuccess) return fail(GAP_EDEVICE, "hipEventCreate: %s", hipGetErrorString(r));
         g->ev.push_back(e);
     }
@@ -382,11 +395,12 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
 {
     const int check_every = o->check_every ? o->check_every : 32;
     fill_pcg(g, a, o);
-    pcg_chunks(g->nz, a.n_cond, g->occ[0] * g->cus, a.chunks_a, a.rows_a);
-    pcg_chunks(g->nz, a.n_cond, std::min(g->occ[1], g->occ[2]) * g->cus, a.chunks_b, a.rows_b);
+    pcg_chunks(g->nz, a.n_cond, g->wg_a * g->cus, a.chunks_a, a.rows_a);
+    pcg_chunks(g->nz, a.n_cond, g->wg_b * g->cus, a.chunks_b, a.rows_b);
 
-    // schedule tables for this (n_cond, chunk counts, operator map)
-    std::vector<int> key = {a.n_cond, a.chunks_a, a.chunks_b};
+    // schedule tables for this (kernel shape, n_cond, chunk counts, operator map); graphs are
+    // cached by table, so the shape belongs to the key
+    std::vector<int> key = {g->shape.NT, g->shape.Q, a.n_cond, a.chunks_a, a.chunks_b};
     for (int c = 0; c < a.n_cond; ++c) key.push_back(a.op[c]);
     gap_grid_s::Sched* sch = nullptr;
     for (auto& e : g->scheds)
@@ -425,19 +439,21 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     *g->req_host = a;
     HIPCHK(hipMemcpyAsync(g->req_dev, g->req_host, sizeof(PcgDev), hipMemcpyHostToDevice, st));
 
-    hipError_t le = launch_pcg(2, g->nt, g->req_dev, work_b, sch->blocks_b, st);
+    hipError_t le = launch_pcg(g->shape, 2, g->nt, g->req_dev, work_b, sch->blocks_b, st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
 
     // One block = check_every iterations (A, B launch pairs); after each block the host reads
-    // the device record.  Launches after convergence return at once.
-    auto enqueue_block = [&](hipStream_t s) -> hipError_t {
-        for (int it = 0; it < check_every; ++it) {
+    // the device record.  Launches after convergence return at once.  `closing`: one more A
+    // launch, which ends a solve that has reached max_iter.
+    auto enqueue_block = [&](hipStream_t s, int iters, bool closing) -> hipError_t {
+        for (int it = 0; it < iters + (closing ? 1 : 0); ++it) {
             timing_mark(g, GAP_KERNEL_PCG_A, true, s);
-            hipError_t e1 = launch_pcg(0, g->nt, g->req_dev, work_a, sch->blocks_a, s);
+            hipError_t e1 = launch_pcg(g->shape, 0, g->nt, g->req_dev, work_a, sch->blocks_a, s);
             timing_mark(g, GAP_KERNEL_PCG_A, false, s);
             if (e1 != hipSuccess) return e1;
+            if (it == iters) break;
             timing_mark(g, GAP_KERNEL_PCG_B, true, s);
-            e1 = launch_pcg(1, g->nt, g->req_dev, work_b, sch->blocks_b, s);
+            e1 = launch_pcg(g->shape, 1, g->nt, g->req_dev, work_b, sch->blocks_b, s);
             timing_mark(g, GAP_KERNEL_PCG_B, false, s);
             if (e1 != hipSuccess) return e1;
         }
@@ -453,7 +469,7 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
             if (gr.block == check_every && gr.table == sch->table) exec = gr.exec;
         if (!exec) {
             if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            hipError_t ce = capture_block(g->cap_stream, check_every, g->nt, g->req_dev, work_a, sch->blocks_a, work_b,
+            hipError_t ce = capture_block(g->cap_stream, check_every, g->shape, g->nt, g->req_dev, work_a, sch->blocks_a, work_b,
                                           sch->blocks_b, &exec);
             if (ce != hipSuccess) return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce));
             if (g->graphs.size() >= 4) {
@@ -467,18 +483,26 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
             g->graphs.push_back(gr);
         }
     }
+    // Full blocks while at least check_every iterations remain before max_iter; then the
+    // remaining iterations and the closing A launch, so that a solve limited by max_iter
+    // launches no idle block.
     const long max_blocks = o->max_iter / check_every + 2;
+    long enqueued = 0;
     for (long blk = 0; blk < max_blocks; ++blk) {
-        if (use_graph) {
+        const long remaining = (long)o->max_iter - enqueued;
+        const bool last = remaining < check_every;
+        const int iters = last ? (int)remaining : check_every;
+        if (use_graph && !last) {
             HIPCHK(hipGraphLaunch(exec, st));
         } else {
             if (g->timing) {
-                gap_status ts = timing_reserve(g, 2 * check_every);
+                gap_status ts = timing_reserve(g, 2 * iters + 1);
                 if (ts != GAP_OK) return ts;
             }
-            le = enqueue_block(st);
+            le = enqueue_block(st, iters, last);
             if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a PCG iteration: %s", hipGetErrorString(le));
         }
+        enqueued += iters;
         HIPCHK(hipMemcpyAsync(g->sc_host, g->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (g->timing) {
@@ -488,6 +512,22 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         if (g->sc_host->done) break;
     }
     return GAP_OK;
+}
+
+// Switch the handle to kernel shape sh; wg_a / wg_b: workgroups per CU the row chunking
+// targets (0: as many as fit, i.e. the occupancy).
+hipError_t use_shape(gap_grid_t g, PcgShape sh, int wg_a, int wg_b)
+{
+    int occ[3];
+    for (int which = 0; which < 3; ++which) {
+        hipError_t e = pcg_prepare(sh, which, g->nt, &occ[which]);
+        if (e != hipSuccess) return e;
+    }
+    g->shape = sh;
+    for (int k = 0; k < 3; ++k) g->occ[k] = occ[k];
+    g->wg_a = wg_a > 0 ? wg_a : occ[0];
+    g->wg_b = wg_b > 0 ? wg_b : std::min(occ[1], occ[2]);
+    return hipSuccess;
 }
 
 gap_status validate_opts(const gap_solver_opts* o)
@@ -648,9 +688,8 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
             g->lds_max = lds;
-        int NT, Q;
-        pcg_shape(g->nt, NT, Q);
-        const size_t need = pcg_lds_bytes(1, NT * Q) + 2048;
+        g->shape = pcg_candidates(g->nt)[0];
+        const size_t need = pcg_lds_bytes(1, g->shape.NT * g->shape.Q) + 2048;
         if (need > (size_t)g->lds_max) {
             release(g);
             return fail(GAP_EINVAL, "n_theta = %d needs %zu bytes of LDS per workgroup, the device allows %d",
@@ -660,8 +699,8 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     // PCG partial sums: at most one slot per row of every condition
     const size_t max_pcg = (size_t)max_cond * g->nz;
     g->pcg_part_stride = max_pcg;
-    for (int which = 0; which < 3; ++which) {
-        hipError_t pe = pcg_prepare(which, g->nt, &g->occ[which]);
+    {
+        hipError_t pe = use_shape(g, g->shape, 0, 0);
         if (pe != hipSuccess) {
             release(g);
             return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(pe));
@@ -932,6 +971,114 @@ gap_status gap_kernel_stats(gap_grid_t g, int32_t kernel, int64_t* launches, dou
     return GAP_OK;
 }
 
+gap_status gap_get_pcg_config(gap_grid_t g, gap_pcg_config* cfg)
+{
+    if (!g || !cfg) return fail(GAP_EINVAL, "grid and cfg must be non-NULL");
+    cfg->threads = g->shape.NT;
+    cfg->cols_per_thread = g->shape.Q;
+    cfg->wg_per_cu_a = g->wg_a;
+    cfg->wg_per_cu_b = g->wg_b;
+    cfg->occupancy_a = g->occ[0];
+    cfg->occupancy_b = std::min(g->occ[1], g->occ[2]);
+    return GAP_OK;
+}
+
+gap_status gap_set_pcg_config(gap_grid_t g, const gap_pcg_config* cfg)
+{
+    if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    PcgShape sh = pcg_candidates(g->nt)[0];
+    int wa = 0, wb = 0;
+    if (cfg) {
+        sh.NT = cfg->threads;
+        sh.Q = cfg->cols_per_thread;
+        const int cols = sh.NT * sh.Q;
+        if (!shape_known(sh) || cols < g->nt || cols >= 2 * g->nt + 64)
+            return fail(GAP_EINVAL, "shape %d x %d does not fit a ring of %d cells", sh.NT, sh.Q, g->nt);
+        if (pcg_lds_bytes(1, cols) + 2048 > (size_t)g->lds_max)
+            return fail(GAP_EINVAL, "shape %d x %d needs more LDS than a workgroup may use", sh.NT, sh.Q);
+        if (cfg->wg_per_cu_a < 1 || cfg->wg_per_cu_a > 8 || cfg->wg_per_cu_b < 1 || cfg->wg_per_cu_b > 8)
+            return fail(GAP_EINVAL, "wg_per_cu must lie in [1, 8]");
+        wa = cfg->wg_per_cu_a;
+        wb = cfg->wg_per_cu_b;
+    }
+    hipError_t e = use_shape(g, sh, wa, wb);
+    if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
+    return GAP_OK;
+}
+
+gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32_t iterations, gap_pcg_config* best,
+                        double* us_per_iteration, void* stream)
+{
+    if (!g || !o || !p) return fail(GAP_EINVAL, "grid, opts and p must be non-NULL");
+    if (iterations < 2 || iterations > 10000) return fail(GAP_EINVAL, "iterations must lie in [2, 10000]");
+    gap_status vs = validate_opts(o);
+    if (vs != GAP_OK) return vs;
+    if (!g->assembled) return fail(GAP_ESTATE, "gap_tune_pcg before assemble_joint_system");
+    hipStream_t st = (hipStream_t)stream;
+    // a fixed number of iterations, no stopping test, plain launches, one block
+    gap_solver_opts t = *o;
+    t.eps = 1e-300;
+    t.max_iter = iterations;
+    t.check_every = iterations;
+    t.graph = 0;
+    t.warm_start = 0;
+    t.strategy = GAP_STRATEGY_SYNC;
+    const bool timing = g->timing;
+    g->timing = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    gap_status result = GAP_OK;
+    for (auto& e : ev)
+        if (result == GAP_OK && hipEventCreate(&e) != hipSuccess) result = fail(GAP_EDEVICE, "hipEventCreate failed");
+    gap_pcg_config win{};
+    double win_us = 0.0;
+    bool have = false;
+    for (const PcgShape sh : pcg_candidates(g->nt)) {
+        if (result != GAP_OK) break;
+        if (pcg_lds_bytes(1, sh.NT * sh.Q) + 2048 > (size_t)g->lds_max) continue;
+        int occ[3];
+        bool ok = true;
+        for (int which = 0; which < 3 && ok; ++which) ok = pcg_prepare(sh, which, g->nt, &occ[which]) == hipSuccess;
+        if (!ok) continue;
+        const int ob = std::min(occ[1], occ[2]);
+        for (int wa = 1; wa <= occ[0] && result == GAP_OK; ++wa) {
+            for (int wb = 1; wb <= ob && result == GAP_OK; ++wb) {
+                if (use_shape(g, sh, wa, wb) != hipSuccess) {
+                    result = fail(GAP_EDEVICE, "preparing the PCG kernels");
+                    break;
+                }
+                double us = 0.0;
+                for (int rep = 0; rep < 2 && result == GAP_OK; ++rep) {   // first run: warm-up
+                    if (hipEventRecord(ev[0], st) != hipSuccess) result = fail(GAP_EDEVICE, "hipEventRecord failed");
+                    gap_status s = solve_joint_pcg(g, &t, p, nullptr, stream);
+                    if (s != GAP_OK && s != GAP_ENOCONV) result = s;
+                    if (result == GAP_OK && (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess))
+                        result = fail(GAP_EDEVICE, "timing a tuning run failed");
+                    float ms = 0.f;
+                    if (result == GAP_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+                        result = fail(GAP_EDEVICE, "hipEventElapsedTime failed");
+                    us = 1e3 * ms / iterations;
+                }
+                if (result == GAP_OK && (!have || us < win_us)) {
+                    have = true;
+                    win_us = us;
+                    gap_get_pcg_config(g, &win);
+                }
+            }
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    g->timing = timing;
+    if (result != GAP_OK) return result;
+    if (!have) return fail(GAP_EDEVICE, "no kernel shape could be prepared");
+    gap_status ss = gap_set_pcg_config(g, &win);
+    if (ss != GAP_OK) return ss;
+    gap_get_pcg_config(g, &win);
+    if (best) *best = win;
+    if (us_per_iteration) *us_per_iteration = win_us;
+    return GAP_OK;
+}
+
 gap_status gap_read_system(gap_grid_t g, int32_t k, double* kx, double* kz, double* S, void* stream)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
@@ -974,6 +1121,7 @@ struct gap_batch_s {
     int* init_work = nullptr;
     size_t init_cap = 0;
     int occ_a = 1, occ_b = 1, cus = 256;
+    PcgShape shape = pcg_candidates(2048)[0];            // the shape of the largest ring
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
     int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0;
@@ -1055,10 +1203,10 @@ gap_status gap_batch_create(gap_batch_t* out)
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess && hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         b->cus = 256;
-    if (e == hipSuccess) e = pcg_prepare(0, kBatchShape, &b->occ_a);
+    if (e == hipSuccess) e = pcg_prepare(b->shape, 0, kBatchShape, &b->occ_a);
     int occ_b = 1, occ_i = 1;
-    if (e == hipSuccess) e = pcg_prepare(1, kBatchShape, &occ_b);
-    if (e == hipSuccess) e = pcg_prepare(2, kBatchShape, &occ_i);
+    if (e == hipSuccess) e = pcg_prepare(b->shape, 1, kBatchShape, &occ_b);
+    if (e == hipSuccess) e = pcg_prepare(b->shape, 2, kBatchShape, &occ_i);
     if (e != hipSuccess) {
         batch_release(b);
         return fail(GAP_EDEVICE, "creating the batch: %s", hipGetErrorString(e));
@@ -1120,7 +1268,7 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     gap_status es = ensure_ints(&b->init_work, &b->init_cap, tb.size());
     if (es != GAP_OK) return es;
     HIPCHK(hipMemcpyAsync(b->init_work, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    hipError_t le = launch_pcg(2, kBatchShape, b->reqs_dev, b->init_work, (int)tb.size(), st);
+    hipError_t le = launch_pcg(b->shape, 2, kBatchShape, b->reqs_dev, b->init_work, (int)tb.size(), st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
     HIPCHK(hipStreamSynchronize(st));
 
@@ -1167,7 +1315,7 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
                 if (b->exec) (void)hipGraphExecDestroy(b->exec);
                 b->exec = nullptr;
                 if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-                hipError_t ce = capture_block(b->cap_stream, iterations, kBatchShape, b->reqs_dev, wa, b->blocks_a, wb,
+                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, kBatchShape, b->reqs_dev, wa, b->blocks_a, wb,
                                               b->blocks_b, &b->exec);
                 if (ce != hipSuccess) {
                     b->exec = nullptr;
@@ -1181,8 +1329,8 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
             HIPCHK(hipGraphLaunch(b->exec, st));
         } else {
             for (int it = 0; it < iterations; ++it) {
-                hipError_t le = launch_pcg(0, kBatchShape, b->reqs_dev, wa, b->blocks_a, st);
-                if (le == hipSuccess) le = launch_pcg(1, kBatchShape, b->reqs_dev, wb, b->blocks_b, st);
+                hipError_t le = launch_pcg(b->shape, 0, kBatchShape, b->reqs_dev, wa, b->blocks_a, st);
+                if (le == hipSuccess) le = launch_pcg(b->shape, 1, kBatchShape, b->reqs_dev, wb, b->blocks_b, st);
                 if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a batch iteration: %s", hipGetErrorString(le));
             }
         }

@@ -63,6 +63,15 @@ class gap_solve_info(ctypes.Structure):
                 ("rel_residual_cond", ctypes.c_double * GAP_MAX_COND)]
 
 
+class gap_pcg_config(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("cols_per_thread", ctypes.c_int32),
+                ("wg_per_cu_a", ctypes.c_int32), ("wg_per_cu_b", ctypes.c_int32),
+                ("occupancy_a", ctypes.c_int32), ("occupancy_b", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class GapLibraryMissing(RuntimeError):
     pass
 
@@ -98,6 +107,10 @@ _SIGNATURES = {
     "gap_batch_poll": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "gap_batch_remove": [_P, ctypes.c_int32, ctypes.POINTER(gap_solve_info), _P],
     "gap_kernel_timing": [_P, ctypes.c_int32],
+    "gap_get_pcg_config": [_P, ctypes.POINTER(gap_pcg_config)],
+    "gap_set_pcg_config": [_P, ctypes.POINTER(gap_pcg_config)],
+    "gap_tune_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.POINTER(gap_pcg_config),
+                     ctypes.POINTER(ctypes.c_double), _P],
     "gap_kernel_stats": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
 }
 
@@ -228,6 +241,27 @@ def gap_kernel_stats(handle, kernel):
     ms = ctypes.c_double(0.0)
     _check(load().gap_kernel_stats(handle, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def gap_get_pcg_config(handle):
+    cfg = gap_pcg_config()
+    _check(load().gap_get_pcg_config(handle, ctypes.byref(cfg)))
+    return cfg
+
+
+def gap_set_pcg_config(handle, cfg=None):
+    """cfg: a gap_pcg_config, or None for the default configuration."""
+    _check(load().gap_set_pcg_config(handle, ctypes.byref(cfg) if cfg is not None else None))
+
+
+def gap_tune_pcg(handle, opts, p_ptr, iterations, stream=None):
+    """Autotune the PCG kernel configuration; returns (gap_pcg_config, us per iteration).
+    Overwrites the device field at p_ptr."""
+    cfg = gap_pcg_config()
+    us = ctypes.c_double(0.0)
+    _check(load().gap_tune_pcg(handle, ctypes.byref(opts), ctypes.c_void_p(int(p_ptr)), int(iterations),
+                               ctypes.byref(cfg), ctypes.byref(us), _stream(stream)))
+    return cfg, us.value
 
 
 def gap_grid_bytes(geom, max_cond):

@@ -85,6 +85,30 @@ class JointGapSolver:
         st, info = G.solve_joint_pcg(self.handle, opts, self.p.data_ptr(), _stream(self.device), raise_on_error)
         return self.pressure(), info
 
+    def tune(self, opts=None, iterations=20, **kw):
+        """Autotune the PCG kernel shape and row chunking on the assembled system; the choice
+        stays on the handle.  Overwrites the pressure field.  Returns (config dict, us per
+        iteration)."""
+        opts = opts or self.options(**kw)
+        cfg, us = G.gap_tune_pcg(self.handle, opts, self.p.data_ptr(), iterations, _stream(self.device))
+        return cfg.as_dict(), us
+
+    @property
+    def pcg_config(self):
+        return G.gap_get_pcg_config(self.handle).as_dict()
+
+    def set_pcg_config(self, threads=None, cols_per_thread=None, wg_per_cu_a=None, wg_per_cu_b=None):
+        """Select a PCG kernel configuration; no arguments: the default."""
+        if threads is None:
+            G.gap_set_pcg_config(self.handle, None)
+            return self.pcg_config
+        cur = G.gap_get_pcg_config(self.handle)
+        cfg = G.gap_pcg_config(threads, cols_per_thread,
+                               cur.wg_per_cu_a if wg_per_cu_a is None else wg_per_cu_a,
+                               cur.wg_per_cu_b if wg_per_cu_b is None else wg_per_cu_b, 0, 0)
+        G.gap_set_pcg_config(self.handle, cfg)
+        return self.pcg_config
+
     def pressure(self):
         return self.p[: self.n_cond * self.n].view(self.n_cond, self.n_axial, self.n_theta)
 

@@ -1,0 +1,88 @@
+"""GPU parity at the full size of the joint textured workload: 2048 x 1024 cells, 9 conditions,
+160 dimples, seed 0, eps 1e-10, in the launch configuration the benchmark times (autotuned).
+
+The oracle cannot assemble or factor this system here in reasonable time, so the check is
+  * the assembled entries at sampled cells (random cells, both Dirichlet rows, both wrap
+    columns) against the oracle's cell-by-cell assembly;
+  * the true residual ||S - A p|| / ||S|| of each condition, with A built by the oracle's
+    stencil_matrix from those (spot-checked) face conductances, computed here in FP64;
+  * the forces of three conditions (base, an eccentricity and a rate perturbation) from the
+    oracle's force integral applied to the GPU pressure.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import gap_of, texture_of
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
+
+ENTRY_TOL = 1e-12     # face conductances, relative per entry (see the small-grid assembly test)
+S_TOL = 1e-11         # source, relative to the largest sampled |S|
+RES_TOL = 1e-9        # true residual per condition; the solve stops at ||r_G|| / ||S_G|| <= 1e-10
+F_TOL = 1e-8
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def sample_cells(nt, nz, rng, count=3000):
+    i = rng.integers(0, nt, count)
+    j = rng.integers(0, nz, count)
+    edge_i = np.concatenate([np.arange(0, nt, 97), [0, nt - 1] * 8, rng.integers(0, nt, 32)])
+    edge_j = np.concatenate([np.zeros(len(range(0, nt, 97)), int), [0, 0, nz - 1, nz - 1, 5, 500, nz - 2, 1] * 2,
+                             np.full(32, nz - 1)])
+    col_j = rng.integers(0, nz, 64)
+    col_i = np.tile([0, nt - 1], 32)
+    return np.concatenate([i, edge_i, col_i]), np.concatenate([j, edge_j, col_j])
+
+
+def test_joint_textured_2048x1024_full_size():
+    case = synth.make_case("joint_textured_2048x1024", 0)
+    log(f"case: {case.label}, 9 conditions, full size")
+    gap, tex = gap_of(case), texture_of(case)
+    nt, nz = case.n_theta, case.n_axial
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    opts = s.options(omega=case.omega, eps=case.eps)
+    cfg, _ = s.tune(opts, iterations=20)
+    log(f"  launch configuration {cfg}")
+    p, info = s.solve(opts)
+    F = s.integrate().cpu().numpy()
+    p = p.reshape(9, -1).cpu().numpy()
+    log(f"  iterations {info.iterations}, recurrence residual {info.rel_residual:.2e}")
+    assert info.rel_residual <= case.eps
+
+    rng = np.random.default_rng(20251106)
+    I, J = sample_cells(nt, nz, rng)
+    conds = oracle.conditions(case.e, case.edot, case.delta)
+    for k, (ek, edk) in enumerate(conds):
+        kx, kz, S = [t.cpu().numpy() for t in s.read_system(k)]
+        kx, kz, S = kx.reshape(nz, nt), kz.reshape(nz + 1, nt), S.reshape(nz, nt)
+        kx_r, kzs_r, kzn_r, S_r = oracle.cell_values(gap, ek, edk, I, J, tex)
+        ex = np.max(np.abs(kx[J, I] - kx_r) / np.abs(kx_r))
+        ez = max(np.max(np.abs(kz[J, I] - kzs_r) / np.abs(kzs_r)), np.max(np.abs(kz[J + 1, I] - kzn_r) / np.abs(kzn_r)))
+        es = np.max(np.abs(S[J, I] - S_r)) / np.max(np.abs(S_r))
+        A = oracle.stencil_matrix(gap, kx, kz)
+        Sf = S.ravel()
+        res = np.linalg.norm(Sf - A @ p[k]) / np.linalg.norm(Sf)
+        log(f"  condition {k}: sampled kx {ex:.1e} kz {ez:.1e} S {es:.1e}; true residual {res:.2e}")
+        assert ex <= ENTRY_TOL and ez <= ENTRY_TOL and es <= S_TOL
+        assert res <= RES_TOL
+
+    for k in (0, 2, 6):
+        F_r = oracle.forces_for_condition(gap, conds[k][0], p[k], tex)
+        err = max(np.linalg.norm(F[k, :2] - F_r[:2]) / np.linalg.norm(F_r[:2]),
+                  np.linalg.norm(F[k, 2:] - F_r[2:]) / np.linalg.norm(F_r[2:]))
+        log(f"  condition {k}: forces {err:.1e}")
+        assert err <= F_TOL
+    s.close()

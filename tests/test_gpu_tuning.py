@@ -1,0 +1,126 @@
+"""GPU parity of every PCG kernel configuration (workgroup shape x row chunking) and of the
+autotuner's choice, through the C ABI, against the CPU oracle; configuration validation; and
+the launch count of a solve that stops at max_iter."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import gap_of, texture_of
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2511_06824_amd import gapsolve as G  # noqa: E402
+from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
+
+P_TOL, F_TOL = 1e-9, 1e-8
+EPS = 1e-13
+
+# ring sizes and the candidate shapes (threads, columns per thread) the library lists for them
+SHAPES = {300: [(512, 1), (256, 2)], 1000: [(512, 2), (1024, 1), (256, 4)], 2048: [(512, 4), (1024, 2)]}
+CASES = [(300, 23, 9), (1000, 9, 9), (2048, 5, 1)]
+
+_ref = {}
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def reference(nt, nz, n_cond):
+    key = (nt, nz, n_cond)
+    if key not in _ref:
+        case = synth.textured_case(nt, nz, 11)
+        gap, tex = gap_of(case), texture_of(case)
+        ps, Fs = [], []
+        for ek, edk in oracle.conditions(case.e, case.edot, case.delta)[:n_cond]:
+            F, p = oracle.condition_forces(gap, ek, edk, tex)
+            ps.append(p)
+            Fs.append(F)
+        _ref[key] = (case, np.array(ps), np.array(Fs))
+    return _ref[key]
+
+
+def check(s, case, n_cond, p_ref, F_ref):
+    p, info = s.solve(omega=case.omega, eps=EPS)
+    F = s.integrate().cpu().numpy()
+    p = p.reshape(n_cond, -1).cpu().numpy()
+    perr = max(np.linalg.norm(p[k] - p_ref[k]) / np.linalg.norm(p_ref[k]) for k in range(n_cond))
+    ferr = max(max(np.linalg.norm(F[k, :2] - F_ref[k, :2]) / np.linalg.norm(F_ref[k, :2]),
+                   np.linalg.norm(F[k, 2:] - F_ref[k, 2:]) / np.linalg.norm(F_ref[k, 2:])) for k in range(n_cond))
+    return perr, ferr, info
+
+
+@pytest.mark.parametrize("nt,nz,n_cond", CASES, ids=[f"{a}x{b}x{c}" for a, b, c in CASES])
+def test_every_configuration_matches_oracle(nt, nz, n_cond):
+    case, p_ref, F_ref = reference(nt, nz, n_cond)
+    s = JointGapSolver.from_case(case, max_cond=9 if n_cond == 9 else 1)
+    s.assemble(case.e, case.edot, case.delta, n_cond)
+    assert (s.pcg_config["threads"], s.pcg_config["cols_per_thread"]) == SHAPES[nt][0]
+    for NT, Q in SHAPES[nt]:
+        occ = s.set_pcg_config(NT, Q, 1, 1)
+        for wa, wb in sorted({(1, 1), (occ["occupancy_a"], occ["occupancy_b"]), (1, occ["occupancy_b"])}):
+            cfg = s.set_pcg_config(NT, Q, wa, wb)
+            log(f"case: {case.label} x{n_cond}, config {cfg}")
+            perr, ferr, info = check(s, case, n_cond, p_ref, F_ref)
+            log(f"  iterations {info.iterations}, pressure {perr:.2e}, forces {ferr:.2e}")
+            assert perr <= P_TOL and ferr <= F_TOL
+    s.close()
+
+
+def test_autotuner_choice_is_valid_and_matches_oracle():
+    case, p_ref, F_ref = reference(300, 23, 9)
+    log(f"case: {case.label}, autotuner")
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    cfg, us = s.tune(iterations=10, omega=case.omega)
+    log(f"  tuned {cfg}, {us:.1f} us per iteration")
+    assert (cfg["threads"], cfg["cols_per_thread"]) in SHAPES[300]
+    assert 1 <= cfg["wg_per_cu_a"] <= cfg["occupancy_a"] and 1 <= cfg["wg_per_cu_b"] <= cfg["occupancy_b"]
+    assert us > 0.0 and s.pcg_config == cfg
+    perr, ferr, _ = check(s, case, 9, p_ref, F_ref)   # the system survives tuning unchanged
+    assert perr <= P_TOL and ferr <= F_TOL
+    assert (s.set_pcg_config()["threads"], s.pcg_config["cols_per_thread"]) == SHAPES[300][0]
+    s.close()
+
+
+def test_configuration_validation():
+    case = synth.smooth_case(300, 8, 0)
+    log(f"case: {case.label}, configuration validation")
+    s = JointGapSolver.from_case(case, max_cond=1)
+    for NT, Q, wa, wb in [(64, 1, 1, 1), (1024, 2, 1, 1), (512, 3, 1, 1), (384, 1, 1, 1), (512, 1, 0, 1),
+                          (512, 1, 1, 9)]:
+        with pytest.raises(G.GapError) as ei:
+            s.set_pcg_config(NT, Q, wa, wb)
+        assert ei.value.status == G.GAP_EINVAL
+    s.assemble(case.e, case.edot, None, 1)
+    with pytest.raises(G.GapError) as ei:
+        G.gap_tune_pcg(s.handle, s.options(), s.p.data_ptr(), 1)
+    assert ei.value.status == G.GAP_EINVAL
+    s.close()
+
+
+def test_iteration_limited_solve_launches_no_idle_block():
+    """max_iter = 40 with blocks of 16: 16 + 16 iterations, then the 8 remaining and the
+    closing A launch; no block of idle launches."""
+    case = synth.smooth_case(128, 64, 2)
+    log(f"case: {case.label}, max_iter 40, check_every 16")
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    G.gap_kernel_timing(s.handle, 1)
+    _, info = s.solve(omega=1.8, eps=1e-300, max_iter=40, check_every=16, raise_on_error=False)
+    na, _ = G.gap_kernel_stats(s.handle, G.GAP_KERNEL_PCG_A)
+    nb, _ = G.gap_kernel_stats(s.handle, G.GAP_KERNEL_PCG_B)
+    G.gap_kernel_timing(s.handle, 0)
+    assert info.iterations == 40 and info.status == G.GAP_ENOCONV
+    assert (na, nb) == (41, 40)
+    # the same iterate as an uninterrupted run of 40 iterations in one block
+    p1 = s.p.clone()
+    s.solve(omega=1.8, eps=1e-300, max_iter=40, check_every=40, raise_on_error=False)
+    assert torch.equal(p1, s.p)
+    s.close()

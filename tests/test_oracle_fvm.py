@@ -203,3 +203,20 @@ def test_conditions_and_shared_operators():
     A3, S3 = oracle.assemble(gap, *conds[3])
     assert abs(AG[3 * n:4 * n, 3 * n:4 * n] - A3).max() == 0
     assert np.array_equal(SG[3 * n:4 * n], S3)
+
+
+def test_cell_values_equal_full_assembly_everywhere():
+    """The cell-by-cell entries (used to spot-check grids too large to assemble) are the
+    full-array entries, bitwise, at every cell of a textured grid including both Dirichlet
+    rows and both wrap columns."""
+    case = synth.textured_case(40, 17, 3)
+    gap = gap_of(case)
+    tex = texture_of(case)
+    kx_r, kz_r = oracle.face_conductances(gap, case.e, tex)
+    S_r = oracle.source(gap, case.e, case.edot, tex)
+    J, I = np.meshgrid(np.arange(gap.n_axial), np.arange(gap.n_theta), indexing="ij")
+    kx, kz_s, kz_n, S = oracle.cell_values(gap, case.e, case.edot, I, J, tex)
+    assert np.array_equal(kx, kx_r)
+    assert np.array_equal(kz_s, kz_r[:-1])
+    assert np.array_equal(kz_n, kz_r[1:])
+    assert np.array_equal(S, S_r)
