@@ -199,6 +199,23 @@ gap_status jacobian_fd(gap_grid_t grid, const double *F, double *J, void *stream
 gap_status jacobian_adjoint(gap_grid_t grid, const gap_solver_opts *opts, const double *p0, int32_t cavitation,
                             double p_cav, const double *w, double *J, gap_solve_info *info, void *stream);
 
+/* Base solve and adjoint solves together (no cavitation): the adjoint right-hand sides
+ * df_i/dp do not depend on p0 when no clamp is applied, so A p0 = S_0 and the adjoint
+ * systems A lambda_i = df_i/dp (all on the operator of condition 0) run as one joint solve of
+ * 1 + 4 systems (w NULL) or 1 + 1 systems (w non-NULL), each with its own recurrence and its
+ * own stopping test (per-condition scalars, asynchronized test, Eq 3.10), followed by the
+ * sensitivity pass of jacobian_adjoint.
+ *   p0     device, n doubles, output: the pressure of condition 0 of the last assembly
+ *   w, J   as in jacobian_adjoint
+ *   opts   omega, eps, precond, max_iter, check_every, graph; eps applies to each system
+ *   info   host, may be NULL: iterations; rel_residual_cond[0] is the base system's,
+ *          [1..] the adjoint systems'
+ * Needs max_cond >= 5 (w NULL) or >= 2 (w non-NULL).  Only condition 0 of the assembly is
+ * used (assembling 1 condition suffices).  Synchronizes stream.  Errors: GAP_EINVAL,
+ * GAP_ESTATE, GAP_ENOCONV, GAP_ENONFINITE, GAP_ENOMEM, GAP_EDEVICE. */
+gap_status solve_with_adjoint(gap_grid_t grid, const gap_solver_opts *opts, double *p0, const double *w, double *J,
+                              gap_solve_info *info, void *stream);
+
 /* Copy the assembled system of condition k to caller device buffers (inspection and
  * testing): kx (n doubles, east-face conductances h^3/(12 mu) dz/dx), kz
  * ((n_axial + 1) * n_theta doubles, axial-face conductances h^3/(12 mu) dx/dz, doubled on
@@ -295,6 +312,11 @@ gap_status gap_batch_add(gap_batch_t batch, gap_grid_t grid, const gap_solver_op
  * number of requests that have finished (converged or stopped).  Synchronizes stream.
  * Errors: GAP_EINVAL, GAP_EDEVICE. */
 gap_status gap_batch_step(gap_batch_t batch, int32_t iterations, int32_t use_graph, int32_t *n_done, void *stream);
+
+/* Hold (hold != 0) or release a request: a held request keeps its Krylov state and device
+ * record but is left out of the launches of gap_batch_step until released, so a scheduler
+ * can choose which requests advance in each step.  Errors: GAP_EINVAL (unknown id). */
+gap_status gap_batch_hold(gap_batch_t batch, int32_t id, int32_t hold);
 
 /* Ids of the finished requests (as of the last step): up to cap ids into ids (may be NULL),
  * the total count into *count.  Errors: GAP_EINVAL. */

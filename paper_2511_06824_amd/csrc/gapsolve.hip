@@ -514,6 +514,18 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     return GAP_OK;
 }
 
+// Adjoint buffers: right-hand sides and solutions of up to 5 systems (a base system and 4
+// adjoint systems), and the sensitivity partials.
+gap_status ensure_adjoint(gap_grid_t g)
+{
+    if (g->adj_rhs) return GAP_OK;
+    const ChunkMap cm1 = make_chunks(g->nz, 1);
+    gap_status s1 = dmalloc(&g->adj_rhs, 5 * g->n);
+    if (s1 == GAP_OK) s1 = dmalloc(&g->adj_lam, 5 * g->n);
+    if (s1 == GAP_OK) s1 = dmalloc(&g->adj_part, 32 * (size_t)cm1.total);
+    return s1;
+}
+
 // Switch the handle to kernel shape sh; wg_a / wg_b: workgroups per CU the row chunking
 // targets (0: as many as fit, i.e. the occupancy).
 hipError_t use_shape(gap_grid_t g, PcgShape sh, int wg_a, int wg_b)
@@ -870,12 +882,8 @@ gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double
     if (ps != GAP_OK) return ps;
     const size_t n = g->n;
     const ChunkMap cm1 = make_chunks(g->nz, 1);
-    if (!g->adj_rhs) {
-        gap_status s1 = dmalloc(&g->adj_rhs, 4 * n);
-        if (s1 == GAP_OK) s1 = dmalloc(&g->adj_lam, 4 * n);
-        if (s1 == GAP_OK) s1 = dmalloc(&g->adj_part, 32 * (size_t)cm1.total);
-        if (s1 != GAP_OK) return s1;
-    }
+    gap_status as = ensure_adjoint(g);
+    if (as != GAP_OK) return as;
     const double w0 = w ? w[0] : 0.0, w1 = w ? w[1] : 0.0, w2 = w ? w[2] : 0.0, w3 = w ? w[3] : 0.0;
     hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)((n + GAP_BLOCK - 1) / GAP_BLOCK)), dim3(GAP_BLOCK), 0, st, g->gd,
                        g->cd, g->tables(), p0, cavitation, p_cav, w ? 1 : 0, w0, w1, w2, w3, g->adj_rhs);
@@ -913,6 +921,74 @@ gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double
     hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm1, w ? 8 : 32,
                        (const double*)g->adj_part, J);
     HIPLAUNCHCHK("k_adjoint_finalize");
+    HIPCHK(hipStreamSynchronize(st));
+    return GAP_OK;
+}
+
+gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0, const double* w, double* J,
+                              gap_solve_info* info, void* stream)
+{
+    if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    if (!p0 || !J) return fail(GAP_EINVAL, "p0 and J must be non-NULL");
+    gap_status vs = validate_opts(o);
+    if (vs != GAP_OK) return vs;
+    if (!g->assembled) return fail(GAP_ESTATE, "solve_with_adjoint before assemble_joint_system");
+    if (w)
+        for (int i = 0; i < 4; ++i)
+            if (!is_finite(w[i])) return fail(GAP_EINVAL, "w must be finite");
+    const int n_rhs = w ? 1 : 4;
+    const int n_sys = 1 + n_rhs;
+    if (n_sys > g->max_cond)
+        return fail(GAP_EINVAL, "the joint base + adjoint solve of %d systems needs a handle created for at least %d "
+                                "conditions", n_sys, n_sys);
+    hipStream_t st = (hipStream_t)stream;
+    gap_status ps = prepare_precond(g, o, st);
+    if (ps != GAP_OK) return ps;
+    const size_t n = g->n;
+    const ChunkMap cm1 = make_chunks(g->nz, 1);
+    gap_status as = ensure_adjoint(g);
+    if (as != GAP_OK) return as;
+    const double w0 = w ? w[0] : 0.0, w1 = w ? w[1] : 0.0, w2 = w ? w[2] : 0.0, w3 = w ? w[3] : 0.0;
+    // right-hand sides: S of condition 0, then df_i/dp (no clamp: independent of p0)
+    HIPCHK(hipMemcpyAsync(g->adj_rhs, g->S, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3((unsigned)((n + GAP_BLOCK - 1) / GAP_BLOCK)), dim3(GAP_BLOCK), 0, st, g->gd,
+                       g->cd, g->tables(), (const double*)nullptr, (int)GAP_CAVITATION_NONE, 0.0, w ? 1 : 0, w0, w1, w2,
+                       w3, g->adj_rhs + n);
+    HIPLAUNCHCHK("k_adjoint_rhs");
+
+    gap_solver_opts oa = *o;
+    oa.scalars = GAP_SCALARS_PER_COND;
+    oa.strategy = GAP_STRATEGY_ASYNC;
+    oa.warm_start = 0;
+    PcgDev a{};
+    a.kx = g->kx;
+    a.kz = g->kz;
+    a.minv = g->minv;
+    a.S = g->adj_rhs;
+    a.p = g->adj_lam;
+    for (int c = 0; c < GAP_MAXC; ++c) a.op[c] = 0;
+    a.n_cond = n_sys;
+    a.per_cond = 1;
+    a.async = 1;
+    a.warm = 0;
+    gap_status rs = run_pcg(g, a, &oa, st);
+    if (rs != GAP_OK) return rs;
+    gap_status fs = finish_solve(g, n_sys, info);
+    if (fs != GAP_OK) return fs;
+
+    const double* lam = g->adj_lam + n;
+    if (w)
+        hipLaunchKernelGGL((k_adjoint_sens<1>), dim3(cm1.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm1, g->tables(),
+                           (const double*)g->adj_lam, lam, (int)GAP_CAVITATION_NONE, 0.0, w0, w1, w2, w3, g->adj_part);
+    else
+        hipLaunchKernelGGL((k_adjoint_sens<4>), dim3(cm1.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm1, g->tables(),
+                           (const double*)g->adj_lam, lam, (int)GAP_CAVITATION_NONE, 0.0, 0.0, 0.0, 0.0, 0.0,
+                           g->adj_part);
+    HIPLAUNCHCHK("k_adjoint_sens");
+    hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm1, w ? 8 : 32,
+                       (const double*)g->adj_part, J);
+    HIPLAUNCHCHK("k_adjoint_finalize");
+    HIPCHK(hipMemcpyAsync(p0, g->adj_lam, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     return GAP_OK;
 }
@@ -1110,6 +1186,7 @@ struct gap_batch_s {
         int id = 0, slot = 0;
         gap_grid_t g = nullptr;
         bool done = false;
+        bool held = false;                                   // excluded from the launches until released
     };
     std::vector<Req> reqs;
     PcgDev *reqs_dev = nullptr, *reqs_host = nullptr;        // slot-indexed request records
@@ -1290,7 +1367,7 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
     if (b->dirty) {
         std::vector<std::vector<int>> ga, gb;
         for (const auto& r : b->reqs) {
-            if (r.done) continue;
+            if (r.done || r.held) continue;
             const PcgDev& a = b->reqs_host[r.slot];
             pcg_groups(r.slot, a.chunks_a, a.n_cond, a.op, ga);
             pcg_groups(r.slot, a.chunks_b, a.n_cond, a.op, gb);
@@ -1350,6 +1427,20 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
     }
     if (n_done) *n_done = done;
     return GAP_OK;
+}
+
+gap_status gap_batch_hold(gap_batch_t b, int32_t id, int32_t hold)
+{
+    if (!b) return fail(GAP_EINVAL, "batch is NULL");
+    for (auto& r : b->reqs)
+        if (r.id == id) {
+            if (r.held != (hold != 0)) {
+                r.held = hold != 0;
+                b->dirty = true;
+            }
+            return GAP_OK;
+        }
+    return fail(GAP_EINVAL, "no request %d in the batch", id);
 }
 
 gap_status gap_batch_poll(gap_batch_t b, int32_t* ids, int32_t cap, int32_t* count)

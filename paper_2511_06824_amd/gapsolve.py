@@ -99,12 +99,14 @@ _SIGNATURES = {
     "gap_read_system": [_P, ctypes.c_int32, _P, _P, _P, _P],
     "jacobian_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.c_double, _D8, _P,
                          ctypes.POINTER(gap_solve_info), _P],
+    "solve_with_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, _D8, _P, ctypes.POINTER(gap_solve_info), _P],
     "gap_grid_bytes": [ctypes.POINTER(gap_geom), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
     "gap_batch_create": [ctypes.POINTER(_P)],
     "gap_batch_destroy": [_P],
     "gap_batch_add": [_P, _P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(ctypes.c_int32), _P],
     "gap_batch_step": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
     "gap_batch_poll": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "gap_batch_hold": [_P, ctypes.c_int32, ctypes.c_int32],
     "gap_batch_remove": [_P, ctypes.c_int32, ctypes.POINTER(gap_solve_info), _P],
     "gap_kernel_timing": [_P, ctypes.c_int32],
     "gap_get_pcg_config": [_P, ctypes.POINTER(gap_pcg_config)],
@@ -225,6 +227,15 @@ def jacobian_adjoint(handle, opts, p0_ptr, cavitation, p_cav, w, J_ptr, stream=N
     return info
 
 
+def solve_with_adjoint(handle, opts, p0_ptr, w, J_ptr, stream=None):
+    """Base solve of condition 0 and its adjoint solves as one joint solve (no cavitation);
+    p0 (n values) and J (4 x 8, or 8 with weights w) are written.  Returns gap_solve_info."""
+    info = gap_solve_info()
+    _check(load().solve_with_adjoint(handle, ctypes.byref(opts), ctypes.c_void_p(int(p0_ptr)), _darr(w, 4),
+                                     ctypes.c_void_p(int(J_ptr)), ctypes.byref(info), _stream(stream)), info)
+    return info
+
+
 def gap_read_system(handle, k, kx_ptr, kz_ptr, S_ptr, stream=None):
     _check(load().gap_read_system(handle, int(k), ctypes.c_void_p(int(kx_ptr or 0)),
                                   ctypes.c_void_p(int(kz_ptr or 0)), ctypes.c_void_p(int(S_ptr or 0)),
@@ -291,6 +302,10 @@ def gap_batch_step(batch, iterations, use_graph=True, stream=None):
     nd = ctypes.c_int32(0)
     _check(load().gap_batch_step(batch, int(iterations), int(bool(use_graph)), ctypes.byref(nd), _stream(stream)))
     return nd.value
+
+
+def gap_batch_hold(batch, bid, hold):
+    _check(load().gap_batch_hold(batch, int(bid), int(bool(hold))))
 
 
 def gap_batch_poll(batch, cap=128):

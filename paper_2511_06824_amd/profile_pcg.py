@@ -1,7 +1,7 @@
 """Profiling driver: a short joint solve on the 2048 x 1024 textured workload plus a plain
 device copy of known size, for hardware-counter runs (rocprofv3 --pmc / --kernel-trace).
 
-    python3 paper_2511_06824_amd/profile_pcg.py [--iterations N] [--copy-mib M]
+    python3 paper_2511_06824_amd/profile_pcg.py [--iterations N] [--copy-mib M] [--no-tune]
 
 The copy (torch's elementwise copy kernel, M MiB read and M MiB written) calibrates what
 the FETCH_SIZE / WRITE_SIZE counters read per byte actually moved.
@@ -19,6 +19,7 @@ def main():
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="joint_textured_2048x1024")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
 
     import torch
@@ -37,6 +38,9 @@ def main():
     case = synth.make_case(args.workload, 0)
     s = JointGapSolver.from_case(case, max_cond=9, device=dev)
     s.assemble(case.e, case.edot, case.delta, 9)
+    if not args.no_tune:
+        cfg, _ = s.tune(iterations=20, omega=case.omega)      # the configuration the benchmark times
+        print(f"profile: PCG kernel configuration {cfg}", flush=True)
     _, info = s.solve(omega=case.omega, eps=1e-30, max_iter=args.iterations, check_every=args.iterations,
                       raise_on_error=False)
     s.integrate()

@@ -7,6 +7,12 @@ by a block of PCG iterations with one launch per kernel per iteration (gap_batch
 HIP library).  Finished requests are integrated (forces, FD Jacobian), their memory is
 released and the next queued requests are admitted.  Latency = completion - arrival.
 
+Scheduling inside the batch: without a work cap every admitted request advances in every
+step (processor sharing).  With ``work_cap`` (condition-DOFs per step), each step advances
+the admitted requests oldest first while their summed size fits the cap (the oldest one
+always advances) and holds the rest on the device (``gap_batch_hold``): large requests then
+run one after another at full bandwidth while small ones fill what the cap leaves.
+
 The admission and scheduling logic (``AdmissionController``, ``GapServer``) is independent
 of the device: ``BatchBackend`` drives the HIP library, tests may substitute a fake backend
 with its own clock.
@@ -99,6 +105,23 @@ class BatchBackend:
     def footprint(self, case):
         return self.Solver.device_bytes(case.n_theta, case.n_axial, 9)
 
+    @staticmethod
+    def work(case):
+        """Per-iteration size of a request: condition-DOFs."""
+        return 9 * case.n_theta * case.n_axial
+
+    def active(self):
+        return [req for _, req, _ in self.live.values()]
+
+    def select(self, chosen):
+        """Advance only the requests in `chosen` in the next steps; hold the others."""
+        keep = {id(r) for r in chosen}
+        for bid, (s, req, _) in self.live.items():
+            held = id(req) not in keep
+            if held != req.meta.get("held", False):
+                self.G.gap_batch_hold(self.batch, bid, held)
+                req.meta["held"] = held
+
     def start(self, req):
         case = req.case
         s = self.Solver.from_case(case, max_cond=9, device=self.device)
@@ -138,10 +161,21 @@ class BatchBackend:
 class GapServer:
     """Event loop: admit by arrival order and budget, step the batch, retire finished work."""
 
-    def __init__(self, backend, budget_bytes, clock=None):
+    def __init__(self, backend, budget_bytes, clock=None, work_cap=None):
         self.backend = backend
         self.admission = AdmissionController(budget_bytes)
         self.clock = clock or WallClock()
+        self.work_cap = work_cap
+
+    def _schedule(self):
+        """Oldest first while the summed work fits the cap; the oldest always advances."""
+        chosen, total = [], 0
+        for r in sorted(self.backend.active(), key=lambda q: (q.arrival, q.rid)):
+            w = self.backend.work(r.case)
+            if not chosen or total + w <= self.work_cap:
+                chosen.append(r)
+                total += w
+        self.backend.select(chosen)
 
     def run(self, requests: List[Request]):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -164,6 +198,8 @@ class GapServer:
                 if pending:
                     self.clock.sleep_until(pending[0].arrival)
                 continue
+            if self.work_cap is not None:
+                self._schedule()
             for r in self.backend.step():
                 r.finished = self.clock.now()
                 self.admission.release(r.nbytes)

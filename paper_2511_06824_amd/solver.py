@@ -133,6 +133,16 @@ class JointGapSolver:
         out = self.J_adj[:8].clone() if w is not None else self.J_adj.view(4, 8).clone()
         return out, info
 
+    def solve_with_adjoint(self, opts=None, w=None, **kw):
+        """Solve condition 0 of the assembly together with its adjoint systems (no cavitation):
+        returns (pressure of condition 0, 4 x 8 Jacobian or w^T J, gap_solve_info).  The
+        pressure lands in the first block of the handle's field."""
+        opts = opts if opts is not None else self.options(**kw)
+        info = G.solve_with_adjoint(self.handle, opts, self.p.data_ptr(), w, self.J_adj.data_ptr(),
+                                    _stream(self.device))
+        out = self.J_adj[:8].clone() if w is not None else self.J_adj.view(4, 8).clone()
+        return self.p[:self.n].view(self.n_axial, self.n_theta), out, info
+
     def read_system(self, k):
         kx = torch.empty(self.n, dtype=torch.float64, device=self.device)
         kz = torch.empty(self.n + self.n_theta, dtype=torch.float64, device=self.device)

@@ -57,6 +57,39 @@ def test_adjoint_matches_complex_step(case):
     assert err <= ADJ_TOL
 
 
+@pytest.mark.parametrize("case", [synth.textured_case(32, 16, 0), synth.textured_case(67, 33, 3)],
+                         ids=["tex32x16", "tex67x33"])
+def test_joint_base_and_adjoint_solve(case):
+    """solve_with_adjoint: the base pressure and the 4 adjoint fields in one joint solve."""
+    log(f"case: {case.label}, joint base + adjoint solve")
+    gap, tex = gap_of(case), texture_of(case)
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, None, 1)
+    opts = s.options(omega=case.omega, eps=1e-13)
+    p0, J, info = s.solve_with_adjoint(opts)
+    J = J.cpu().numpy()
+    ref = oracle.jacobian_complex_step(gap, case.e, case.edot, tex)
+    err = block_err(J, ref)
+    F_ref, p_ref = oracle.condition_forces(gap, case.e, case.edot, tex)
+    perr = np.linalg.norm(p0.cpu().numpy().ravel() - p_ref) / np.linalg.norm(p_ref)
+    log(f"  iterations {info.iterations}, Jacobian {err:.2e}, pressure {perr:.2e}")
+    assert err <= ADJ_TOL and perr <= 1e-9
+    assert info.n_cond == 5 and all(info.rel_residual_cond[k] <= 1e-13 for k in range(5))
+    F = s.integrate().cpu().numpy()[0]
+    assert np.linalg.norm(F - F_ref) <= 1e-8 * np.linalg.norm(F_ref)
+    w = [0.7, 2.0, -40.0, 15.0]
+    _, v, info2 = s.solve_with_adjoint(opts, w=w)
+    assert info2.n_cond == 2
+    assert np.linalg.norm(v.cpu().numpy() - np.asarray(w) @ J) <= 1e-9 * np.linalg.norm(np.asarray(w) @ J)
+    s.close()
+    s1 = JointGapSolver.from_case(case, max_cond=1)
+    s1.assemble(case.e, case.edot, None, 1)
+    with pytest.raises(G.GapError) as ei:
+        s1.solve_with_adjoint(opts, w=w)
+    assert ei.value.status == G.GAP_EINVAL
+    s1.close()
+
+
 def test_vjp_equals_weighted_full_jacobian():
     case = synth.textured_case(96, 48, 4)
     log(f"case: {case.label}, vjp")
@@ -138,6 +171,10 @@ def test_adjoint_against_fd_jacobians_1024x512_textured():
     gap2 = max(np.linalg.norm(blocks(J_fwd2)[k] - b_adj[k]) / np.linalg.norm(b_adj[k]) for k in (0, 2))
     log(f"  forward-FD gap {gap1:.2e}, at delta/2 {gap2:.2e}; adjoint iterations {info.iterations}")
     assert 1.6 < gap1 / gap2 < 2.4
+    # the joint base + adjoint solve gives the same Jacobian
+    s.assemble(case.e, case.edot, None, 1)
+    _, J_joint, _ = s.solve_with_adjoint(opts)
+    assert block_err(J_joint.cpu().numpy(), J_adj) <= 1e-6
     s.close()
 
 

@@ -103,3 +103,54 @@ def test_server_drains_a_poisson_stream():
     stats = latency_stats(done)
     log(f"  p50 {stats['p50_s'] * 1e3:.1f} ms, p99 {stats['p99_s'] * 1e3:.1f} ms")
     assert all(np.all(np.isfinite(r.F)) and np.all(np.isfinite(r.J)) for r in done)
+
+
+def test_held_request_keeps_its_state_and_result():
+    """A held request does not advance; released, it finishes bitwise as when run alone."""
+    log("case: batch hold and release")
+    cases = [synth.smooth_case(128, 64, 7), synth.textured_case(96, 48, 8)]
+    alone = batch_solve([cases[1]])[0]
+    b = G.gap_batch_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    solvers, ids = [], []
+    for c in cases:
+        s = JointGapSolver.from_case(c, max_cond=9)
+        s.assemble(c.e, c.edot, c.delta, 9)
+        opts = s.options(omega=c.omega, eps=c.eps)
+        ids.append(G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream))
+        solvers.append(s)
+    G.gap_batch_hold(b, ids[1], 1)
+    for _ in range(3):
+        G.gap_batch_step(b, 8, True, stream)
+    p_held = solvers[1].pressure().clone()
+    G.gap_batch_step(b, 8, True, stream)
+    assert torch.equal(p_held, solvers[1].pressure())        # no launch touched it
+    G.gap_batch_hold(b, ids[1], 0)
+    result = None
+    while result is None:
+        G.gap_batch_step(b, 8, True, stream)
+        for bid in G.gap_batch_poll(b):
+            st, info = G.gap_batch_remove(b, bid, stream)
+            if bid == ids[1]:
+                result = (solvers[1].pressure().cpu().numpy().copy(), info.iterations)
+    assert result[1] == alone[1] and np.array_equal(result[0], alone[0])
+    with pytest.raises(G.GapError):
+        G.gap_batch_hold(b, 12345, 1)
+    for s in solvers:
+        s.close()
+    G.gap_batch_destroy(b)
+
+
+def test_server_with_work_cap_drains_a_mixed_stream():
+    log("case: served stream with a work cap")
+    reqs = []
+    sizes = [(256, 128), (64, 32), (256, 128), (128, 64), (64, 32)]
+    for k, (nt, nz) in enumerate(sizes):
+        reqs.append(Request(rid=k, case=synth.smooth_case(nt, nz, 20 + k), arrival=0.001 * k))
+    be = BatchBackend(iterations_per_step=16)
+    cap = be.work(reqs[0].case) + be.work(reqs[1].case)        # one 256x128 plus a small one
+    done = GapServer(be, budget_bytes=10 * be.footprint(reqs[0].case), work_cap=cap).run(reqs)
+    be.close()
+    assert sorted(r.rid for r in done) == list(range(5)) and all(r.status == G.GAP_OK for r in done)
+    by = {r.rid: r for r in done}
+    assert by[0].finished <= by[2].finished                    # the two large ones in order

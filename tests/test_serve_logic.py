@@ -39,8 +39,10 @@ class FakeBackend:
     def step(self):
         self.clock.t += self.step_time
         out = []
+        sel = getattr(self, "selected", None)
         for item in self.live:
-            item[1] -= 1
+            if sel is None or item[0].rid in sel:
+                item[1] -= 1
         for item in [x for x in self.live if x[1] <= 0]:
             self.live.remove(item)
             out.append(item[0])
@@ -49,10 +51,20 @@ class FakeBackend:
     def idle(self):
         return not self.live
 
+    @staticmethod
+    def work(case):
+        return case.fake_work
 
-def req(rid, arrival, nbytes, steps, nt=64, nz=32):
-    return Request(rid=rid, case=SimpleNamespace(fake_bytes=nbytes, fake_steps=steps, n_theta=nt, n_axial=nz),
-                   arrival=arrival)
+    def active(self):
+        return [x[0] for x in self.live]
+
+    def select(self, chosen):
+        self.selected = {r.rid for r in chosen}
+
+
+def req(rid, arrival, nbytes, steps, nt=64, nz=32, work=1):
+    return Request(rid=rid, case=SimpleNamespace(fake_bytes=nbytes, fake_steps=steps, n_theta=nt, n_axial=nz,
+                                                 fake_work=work), arrival=arrival)
 
 
 def test_admission_controller_budget_and_slots():
@@ -98,3 +110,25 @@ def test_request_larger_than_budget_is_rejected():
     srv = GapServer(FakeBackend(clock), budget_bytes=10, clock=clock)
     with pytest.raises(ValueError):
         srv.run([req(0, 0.0, 11, 1)])
+
+
+def test_work_cap_runs_large_requests_in_order_and_small_ones_beside_them():
+    """Cap 5: two large requests (work 4) run one after the other; small ones (work 1)
+    advance beside whichever large one runs."""
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = GapServer(be, budget_bytes=1000, clock=clock, work_cap=5)
+    rs = [req(0, 0.0, 10, 4, work=4), req(1, 0.0, 10, 4, work=4), req(2, 0.5, 10, 2, work=1)]
+    done = {r.rid: r for r in srv.run(rs)}
+    assert done[0].finished == 4.0                 # the oldest large request is never held
+    assert done[2].finished == 3.0                 # the small one advanced beside it
+    assert done[1].finished == 8.0                 # the second large one waited, then ran alone
+
+
+def test_without_a_cap_all_admitted_requests_share_each_step():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = GapServer(be, budget_bytes=1000, clock=clock)
+    rs = [req(0, 0.0, 10, 4, work=4), req(1, 0.0, 10, 4, work=4)]
+    done = {r.rid: r for r in srv.run(rs)}
+    assert done[0].finished == done[1].finished == 4.0
