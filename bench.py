@@ -152,6 +152,53 @@ def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.8, 1.2)):
             "hbm_budget_bytes": budget, "runs": runs}
 
 
+def run_dynamics(torch, G, JointGapSolver, dev, steps=12):
+    """GMAF step V on the joint smooth 512 x 256 gap: 12 one-degree time steps of the synthetic
+    pump (600 rpm, swashplate 10 degrees, inlet pressure ramping into delivery), each solved to
+    equilibrium by Picard iterations of Eq 2.12 (FD Jacobian, warm-started joint solves), and
+    the same with the conventional scheme of Eq 2.20-2.22."""
+    import numpy as np
+    import synth
+    from paper_2511_06824_amd.dynamics import PumpKinematics, simulate
+    case = synth.make_case("joint_smooth_512x256", 0)
+    kin = PumpKinematics()
+    s = JointGapSolver.from_case(case, max_cond=9, device=dev)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    s.tune(iterations=20, omega=case.omega)
+    out = {"workload": "joint_smooth_512x256", "time_steps": steps, "dt_s": 0.1 / 360, "rpm": kin.rpm}
+    for name, scheme in (("general", G.GAP_SCHEME_GENERAL), ("conventional", G.GAP_SCHEME_CONVENTIONAL)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        traj = simulate(s, kin, steps, 0.1 / 360, case.delta, np.zeros(4), np.zeros(4), tol=1e-6, max_picard=12,
+                        scheme=scheme, U=kin.omega * case.R)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"ms_per_time_step": round(1e3 * dt / steps, 2),
+                     "picard_per_time_step": round(sum(r["picard"] for r in traj) / steps, 2),
+                     "pcg_iterations_per_time_step": round(sum(sum(r["pcg_iterations"]) for r in traj) / steps, 1),
+                     "max_final_residual": max(r["residual"] for r in traj),
+                     "final_eccentricity_over_c": round(float(np.max(np.abs(traj[-1]["e"]))) / case.c, 4)}
+    s.close()
+    print(f"bench: dynamics {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def run_precond_study(JointGapSolver, dev):
+    """Jacobi, ASSOR I and ASSOR II over omega = 0.1 + 0.18 i on the joint smooth 512 x 256
+    system (9 conditions), tuned kernels, eps 1e-10."""
+    import synth
+    from paper_2511_06824_amd.study import precond_study, summarize
+    case = synth.make_case("joint_smooth_512x256", 0)
+    s = JointGapSolver.from_case(case, max_cond=9, device=dev)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    s.tune(iterations=20, omega=case.omega)
+    rows = precond_study(s, eps=case.eps)
+    s.close()
+    summ = summarize(rows)
+    print(f"bench: preconditioner study {summ}", file=sys.stderr, flush=True)
+    return {"workload": "joint_smooth_512x256", "eps": case.eps, "summary": summ, "rows": rows}
+
+
 def run_adjoint_vs_fd(torch, JointGapSolver, dev):
     """Cost of the 4 x 8 Jacobian on the 1024 x 512 textured workload: the 9-condition
     forward-difference solve against one base solve plus the 4 adjoint solves."""
@@ -217,6 +264,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default PCG kernel configuration")
+    ap.add_argument("--no-study", action="store_true", help="skip the preconditioner / omega study")
+    ap.add_argument("--no-dynamics", action="store_true", help="skip the general-iteration time steps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
@@ -310,6 +359,14 @@ def main():
     if not args.no_adjoint:
         adjoint = run_adjoint_vs_fd(torch, JointGapSolver, dev)
 
+    study = None
+    if not args.no_study:
+        study = run_precond_study(JointGapSolver, dev)
+
+    dyn = None
+    if not args.no_dynamics:
+        dyn = run_dynamics(torch, G, JointGapSolver, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(case, int(round(mean_iters)), n_cond)
@@ -328,7 +385,7 @@ def main():
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
-        "roofline": roofline, "plain_baseline": plain, "serving": serving, "adjoint_vs_fd": adjoint,
+        "roofline": roofline, "plain_baseline": plain, "serving": serving, "adjoint_vs_fd": adjoint, "precond_study": study, "dynamics": dyn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

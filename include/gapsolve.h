@@ -216,6 +216,47 @@ gap_status jacobian_adjoint(gap_grid_t grid, const gap_solver_opts *opts, const 
 gap_status solve_with_adjoint(gap_grid_t grid, const gap_solver_opts *opts, double *p0, const double *w, double *J,
                               gap_solve_info *info, void *stream);
 
+/* ---- GMAF step V (Sec 2.3): one general iteration of the piston equilibrium
+ * F = F_E + F_I + F_O = 0 (Eq 2.10), F = (Fx, Fy, Mx, My) (Eq 2.11), at a new time point.
+ * F_O is the oil-film force of the base condition (steps I-III), F_E an external load and
+ * F_I = -mass (edot - edot_prev) / dt the inertia force of a constant 4 x 4 mass matrix on the
+ * backward-difference acceleration.  The eccentricities follow e = e_prev + dt edot, so an
+ * update keeps de = dt d(edot).  Eq 2.12 then reads
+ *   GAP_SCHEME_GENERAL:       (F_,edot + dt F_,e) d(edot) = -F      (both Jacobians)
+ *   GAP_SCHEME_CONVENTIONAL:  F_,edot d(edot) = -F                   (Eq 2.20-2.22)
+ * with F_,e = dF_O/de and F_,edot = dF_O/dedot - mass / dt.  The oil-film Jacobian comes from
+ * the 9-condition joint solve and Eq 2.13-2.14 (GAP_JACOBIAN_FD; needs a 9-condition handle
+ * and delta) or from the joint base + adjoint solve (GAP_JACOBIAN_ADJOINT; no cavitation;
+ * needs max_cond >= 5; delta may be NULL). */
+enum { GAP_SCHEME_GENERAL = 0, GAP_SCHEME_CONVENTIONAL = 1 };
+enum { GAP_JACOBIAN_FD = 0, GAP_JACOBIAN_ADJOINT = 1 };
+typedef struct {
+    double dt;              /* time step (s), > 0 */
+    double edot_prev[4];    /* rates at the previous time point (m/s) */
+    double F_ext[4];        /* external load F_E (N, N, N m, N m) */
+    double mass[16];        /* row-major 4 x 4 mass matrix (kg, kg m^2 / m as the rows need) */
+    int32_t scheme;         /* GAP_SCHEME_* */
+    int32_t jacobian;       /* GAP_JACOBIAN_* */
+} gap_step_params;
+
+/* One step from (e, edot) (host, 4 each; overwritten with the updated state):
+ *   p      device, 9 n doubles (FD) or n doubles (adjoint): the pressure field, also the
+ *          initial guess when opts->warm_start is set (FD only)
+ *   F      host, 4 doubles, output: the residual F at the input state
+ *   J      host, 32 doubles or NULL, output: the oil-film Jacobian used (layout of jacobian_fd)
+ *   info   host or NULL: the PCG solve of this step
+ * Synchronizes stream.  Errors: GAP_EINVAL, GAP_ECONTACT, GAP_ENOCONV, GAP_ENONFINITE
+ * (also a singular update matrix), GAP_ENOMEM, GAP_EDEVICE. */
+gap_status general_iteration_step(gap_grid_t grid, const gap_solver_opts *opts, const gap_step_params *prm,
+                                  const double delta[8], double *p, double e[4], double edot[4], double F[4],
+                                  double *J, gap_solve_info *info, void *stream);
+
+/* Operating point of the gap (pump kinematics, time-varying pressures): circumferential and
+ * axial sliding speeds U, V (m/s) and the Dirichlet pressures p_in (z = 0) and p_out (z = L)
+ * (Pa).  Takes effect at the next assemble_joint_system (the handle returns to the state
+ * "not assembled").  Errors: GAP_EINVAL (NULL grid, non-finite value). */
+gap_status set_operating_point(gap_grid_t grid, double U, double V, double p_in, double p_out);
+
 /* Copy the assembled system of condition k to caller device buffers (inspection and
  * testing): kx (n doubles, east-face conductances h^3/(12 mu) dz/dx), kz
  * ((n_axial + 1) * n_theta doubles, axial-face conductances h^3/(12 mu) dx/dz, doubled on

@@ -23,6 +23,8 @@ What it computes (paper: arXiv 2511.06824):
 * ``forces``    pressure + viscous-shear force and moment integrals (Sec 2.4-III).
 * ``jacobian``  forward differences of Eq 2.13-2.14, central differences, and
                 an exact complex-step derivative.
+* ``dynamics``  one general-iteration step of the equilibrium F_E + F_I + F_O = 0
+                (Eq 2.10, 2.12; the conventional scheme of Eq 2.20-2.22).
 
 The paper does not state the Reynolds equation, the shear formula, the force
 definitions or a cavitation rule; the readings taken here are listed in each
@@ -37,6 +39,7 @@ from .pcg import pcg, pcg_blocks, jacobi_precond, assor1_precond, assor2_precond
 from .forces import effective_pressure, force_moment, forces_for_condition
 from .jacobian import (solve_condition, condition_forces, jacobian_fd, jacobian_central,
                        jacobian_complex_step)
+from . import dynamics
 
 __all__ = [
     "Gap", "cell_centers", "film", "film_naive", "film_rate", "dimple_texture", "no_texture",
@@ -45,5 +48,5 @@ __all__ = [
     "pcg", "pcg_blocks", "jacobi_precond", "assor1_precond", "assor2_precond", "assor2_explicit",
     "effective_pressure", "force_moment", "forces_for_condition",
     "solve_condition", "condition_forces", "jacobian_fd", "jacobian_central",
-    "jacobian_complex_step",
+    "jacobian_complex_step", "dynamics",
 ]

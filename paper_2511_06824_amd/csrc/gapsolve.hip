@@ -253,6 +253,7 @@ struct gap_grid_s {
     PcgDev *req_dev = nullptr, *req_host = nullptr;          // the request record of this handle's launches
     double *adj_rhs = nullptr, *adj_lam = nullptr;           // adjoint right-hand sides and solutions
     double *adj_part = nullptr;                              // sensitivity partials
+    double *step_buf = nullptr;                              // general iteration: F (9 x 4) and J (4 x 8)
     int cus = 256;                                           // compute units of the device
     PcgShape shape{};                                        // PCG kernel shape in use
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
@@ -295,7 +296,7 @@ namespace {
 void release(gap_grid_t g)
 {
     double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->partial,
-                      g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part};
+                      g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part, g->step_buf};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& gr : g->graphs)
@@ -990,6 +991,105 @@ gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0
     HIPLAUNCHCHK("k_adjoint_finalize");
     HIPCHK(hipMemcpyAsync(p0, g->adj_lam, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
+    return GAP_OK;
+}
+
+gap_status set_operating_point(gap_grid_t g, double U, double V, double p_in, double p_out)
+{
+    if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    if (!is_finite(U) || !is_finite(V) || !is_finite(p_in) || !is_finite(p_out))
+        return fail(GAP_EINVAL, "U, V, p_in and p_out must be finite");
+    g->geom.U = g->gd.U = U;
+    g->geom.V = g->gd.V = V;
+    g->geom.p_in = g->gd.p_in = p_in;
+    g->geom.p_out = g->gd.p_out = p_out;
+    g->assembled = false;
+    return GAP_OK;
+}
+
+gap_status general_iteration_step(gap_grid_t g, const gap_solver_opts* o, const gap_step_params* prm,
+                                  const double* delta, double* p, double* e, double* edot, double* F, double* J,
+                                  gap_solve_info* info, void* stream)
+{
+    if (!g || !o || !prm || !p || !e || !edot || !F) return fail(GAP_EINVAL, "grid, opts, prm, p, e, edot and F must be non-NULL");
+    if (!is_finite(prm->dt) || !(prm->dt > 0.0)) return fail(GAP_EINVAL, "dt must be finite and > 0");
+    for (int k = 0; k < 4; ++k)
+        if (!is_finite(prm->edot_prev[k]) || !is_finite(prm->F_ext[k])) return fail(GAP_EINVAL, "edot_prev and F_ext must be finite");
+    for (int k = 0; k < 16; ++k)
+        if (!is_finite(prm->mass[k])) return fail(GAP_EINVAL, "mass must be finite");
+    if (prm->scheme != GAP_SCHEME_GENERAL && prm->scheme != GAP_SCHEME_CONVENTIONAL) return fail(GAP_EINVAL, "unknown scheme");
+    if (prm->jacobian != GAP_JACOBIAN_FD && prm->jacobian != GAP_JACOBIAN_ADJOINT) return fail(GAP_EINVAL, "unknown jacobian");
+    if (prm->jacobian == GAP_JACOBIAN_FD && (g->max_cond != GAP_MAX_COND || !delta))
+        return fail(GAP_EINVAL, "the FD Jacobian needs a 9-condition handle and delta");
+    hipStream_t st = (hipStream_t)stream;
+    if (!g->step_buf) {
+        gap_status s1 = dmalloc(&g->step_buf, 36 + 32);
+        if (s1 != GAP_OK) return s1;
+    }
+    double* F_dev = g->step_buf;
+    double* J_dev = g->step_buf + 36;
+    gap_status s1;
+    if (prm->jacobian == GAP_JACOBIAN_FD) {
+        s1 = assemble_joint_system(g, e, edot, delta, GAP_MAX_COND, stream);
+        if (s1 == GAP_OK) s1 = solve_joint_pcg(g, o, p, info, stream);
+        if (s1 == GAP_OK) s1 = integrate_force_moment(g, p, GAP_CAVITATION_NONE, 0.0, F_dev, stream);
+        if (s1 == GAP_OK) s1 = jacobian_fd(g, F_dev, J_dev, stream);
+    } else {
+        s1 = assemble_joint_system(g, e, edot, nullptr, 1, stream);
+        if (s1 == GAP_OK) s1 = solve_with_adjoint(g, o, p, nullptr, J_dev, info, stream);
+        if (s1 == GAP_OK) s1 = integrate_force_moment(g, p, GAP_CAVITATION_NONE, 0.0, F_dev, stream);
+    }
+    if (s1 != GAP_OK) return s1;
+    double Fo[4], Jo[32];
+    HIPCHK(hipMemcpyAsync(Fo, F_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(Jo, J_dev, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // residual F = F_E + F_I + F_O and the update matrix (Eq 2.12 or Eq 2.20)
+    const double dt = prm->dt;
+    const double* M = prm->mass;
+    double R[4], K[4][4];
+    for (int i = 0; i < 4; ++i) {
+        double fi = 0.0;
+        for (int k = 0; k < 4; ++k) fi -= M[4 * i + k] * (edot[k] - prm->edot_prev[k]);
+        R[i] = prm->F_ext[i] + fi / dt + Fo[i];
+        for (int k = 0; k < 4; ++k) {
+            K[i][k] = Jo[8 * i + 4 + k] - M[4 * i + k] / dt;
+            if (prm->scheme == GAP_SCHEME_GENERAL) K[i][k] += dt * Jo[8 * i + k];
+        }
+    }
+    for (int i = 0; i < 4; ++i) F[i] = R[i];
+    if (J)
+        for (int k = 0; k < 32; ++k) J[k] = Jo[k];
+    // K d(edot) = -R by Gaussian elimination with partial pivoting
+    double b[4] = {-R[0], -R[1], -R[2], -R[3]};
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (std::fabs(K[r][c]) > std::fabs(K[piv][c])) piv = r;
+        if (!(std::fabs(K[piv][c]) > 0.0) || !is_finite(K[piv][c]))
+            return fail(GAP_ENONFINITE, "the update matrix of the general iteration is singular");
+        if (piv != c) {
+            for (int k = 0; k < 4; ++k) std::swap(K[c][k], K[piv][k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < 4; ++r) {
+            const double f = K[r][c] / K[c][c];
+            for (int k = c; k < 4; ++k) K[r][k] -= f * K[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    double d_edot[4];
+    for (int r = 3; r >= 0; --r) {
+        double v = b[r];
+        for (int k = r + 1; k < 4; ++k) v -= K[r][k] * d_edot[k];
+        d_edot[r] = v / K[r][r];
+    }
+    for (int k = 0; k < 4; ++k)
+        if (!is_finite(d_edot[k])) return fail(GAP_ENONFINITE, "non-finite update of the general iteration");
+    for (int k = 0; k < 4; ++k) {
+        e[k] += dt * d_edot[k];
+        edot[k] += d_edot[k];
+    }
     return GAP_OK;
 }
 

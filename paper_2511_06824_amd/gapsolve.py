@@ -72,6 +72,15 @@ class gap_pcg_config(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class gap_step_params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("edot_prev", ctypes.c_double * 4), ("F_ext", ctypes.c_double * 4),
+                ("mass", ctypes.c_double * 16), ("scheme", ctypes.c_int32), ("jacobian", ctypes.c_int32)]
+
+
+GAP_SCHEME_GENERAL, GAP_SCHEME_CONVENTIONAL = 0, 1
+GAP_JACOBIAN_FD, GAP_JACOBIAN_ADJOINT = 0, 1
+
+
 class GapLibraryMissing(RuntimeError):
     pass
 
@@ -100,6 +109,9 @@ _SIGNATURES = {
     "jacobian_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.c_double, _D8, _P,
                          ctypes.POINTER(gap_solve_info), _P],
     "solve_with_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, _D8, _P, ctypes.POINTER(gap_solve_info), _P],
+    "general_iteration_step": [_P, ctypes.POINTER(gap_solver_opts), ctypes.POINTER(gap_step_params), _D8, _P, _D8, _D8,
+                               _D8, _D8, ctypes.POINTER(gap_solve_info), _P],
+    "set_operating_point": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "gap_grid_bytes": [ctypes.POINTER(gap_geom), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
     "gap_batch_create": [ctypes.POINTER(_P)],
     "gap_batch_destroy": [_P],
@@ -234,6 +246,24 @@ def solve_with_adjoint(handle, opts, p0_ptr, w, J_ptr, stream=None):
     _check(load().solve_with_adjoint(handle, ctypes.byref(opts), ctypes.c_void_p(int(p0_ptr)), _darr(w, 4),
                                      ctypes.c_void_p(int(J_ptr)), ctypes.byref(info), _stream(stream)), info)
     return info
+
+
+def general_iteration_step(handle, opts, prm, delta, p_ptr, e, edot, stream=None):
+    """One general iteration (GMAF step V).  e, edot: 4 values each (not modified).
+    Returns (e_new, edot_new, residual F at the input state, oil-film J (4 x 8), info)."""
+    e_arr = (ctypes.c_double * 4)(*[float(x) for x in e])
+    ed_arr = (ctypes.c_double * 4)(*[float(x) for x in edot])
+    F = (ctypes.c_double * 4)()
+    J = (ctypes.c_double * 32)()
+    info = gap_solve_info()
+    _check(load().general_iteration_step(handle, ctypes.byref(opts), ctypes.byref(prm), _darr(delta, 8),
+                                         ctypes.c_void_p(int(p_ptr)), e_arr, ed_arr, F, J, ctypes.byref(info),
+                                         _stream(stream)), info)
+    return list(e_arr), list(ed_arr), list(F), [list(J[8 * i:8 * i + 8]) for i in range(4)], info
+
+
+def set_operating_point(handle, U, V, p_in, p_out):
+    _check(load().set_operating_point(handle, float(U), float(V), float(p_in), float(p_out)))
 
 
 def gap_read_system(handle, k, kx_ptr, kz_ptr, S_ptr, stream=None):

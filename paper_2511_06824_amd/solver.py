@@ -85,6 +85,21 @@ class JointGapSolver:
         st, info = G.solve_joint_pcg(self.handle, opts, self.p.data_ptr(), _stream(self.device), raise_on_error)
         return self.pressure(), info
 
+    def set_operating_point(self, U, V, p_in, p_out):
+        """Sliding speeds and end pressures for the next assembly (pump kinematics)."""
+        G.set_operating_point(self.handle, U, V, p_in, p_out)
+        self.geom.U, self.geom.V, self.geom.p_in, self.geom.p_out = float(U), float(V), float(p_in), float(p_out)
+
+    def general_iteration_step(self, e, edot, delta, dt, edot_prev, F_ext, mass, opts=None,
+                               scheme=G.GAP_SCHEME_GENERAL, jacobian=G.GAP_JACOBIAN_FD):
+        """One general iteration of the piston equilibrium (GMAF step V); returns
+        (e_new, edot_new, residual F, oil-film Jacobian, gap_solve_info)."""
+        from .dynamics import step_params
+        opts = opts if opts is not None else self.options()
+        prm = step_params(dt, edot_prev, F_ext, mass, scheme, jacobian)
+        return G.general_iteration_step(self.handle, opts, prm, delta, self.p.data_ptr(), e, edot,
+                                        _stream(self.device))
+
     def tune(self, opts=None, iterations=20, **kw):
         """Autotune the PCG kernel shape and row chunking on the assembled system; the choice
         stays on the handle.  Overwrites the pressure field.  Returns (config dict, us per

@@ -141,6 +141,21 @@ def test_iteration_counts_follow_oracle_pcg(precond, name):
     assert np.linalg.norm(p.ravel() - pG) / np.linalg.norm(pG) < 1e-8
 
 
+@pytest.mark.parametrize("name,precond", [("assor2", G.GAP_PRECOND_ASSOR2), ("assor1", G.GAP_PRECOND_ASSOR1)])
+@pytest.mark.parametrize("omega", [0.1, 0.46, 1.0, 1.54, 1.9])
+def test_omega_sweep_iteration_counts_follow_oracle(name, precond, omega):
+    """The relaxation-factor study (omega = 0.1 + 0.18 i): the GPU recurrence follows the
+    oracle's Table 1 PCG with the same preconditioner at every omega."""
+    case = synth.smooth_case(64, 32, 3)
+    log(f"case: {case.label}, 9 conditions, {name}, omega {omega}")
+    AG, SG = oracle.assemble_joint(gap_of(case), case.e, case.edot, case.delta)
+    M = (oracle.assor2_precond if name == "assor2" else oracle.assor1_precond)(AG, omega)
+    pG, it_ref, _ = oracle.pcg(AG, SG, M, 1e-10, 100000)
+    p, F, J, info = gpu_case(case, 9, eps=1e-10, precond=precond, omega=omega)
+    assert abs(info.iterations - it_ref) <= 2, (info.iterations, it_ref)
+    assert np.linalg.norm(p.ravel() - pG) / np.linalg.norm(pG) < 1e-8
+
+
 def test_per_condition_scalars_reach_same_solution():
     case = synth.smooth_case(128, 64, 4)
     log(f"case: {case.label}, 9 conditions, per-condition scalars")
