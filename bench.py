@@ -93,7 +93,8 @@ def _round(d):
 def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.8, 1.2)):
     """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
     128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server (HBM-budget
-    admission, continuous batching, work cap of 1.25 joint 2048x1024 systems per step) is
+    admission, continuous batching, smallest request first under a work cap of one joint
+    2048x1024 system per step) is
     measured first with all requests queued at t = 0 (its capacity); then arrivals run at
     each load x that capacity, against the same requests solved one at a time in arrival
     order as joint solves, and (at the first load) as plain one-condition-at-a-time solves."""
@@ -108,7 +109,7 @@ def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.8, 1.2)):
 
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    work_cap = int(1.25 * 9 * 2048 * 1024)
+    work_cap = 9 * 2048 * 1024               # one joint 2048 x 1024 system per step
 
     def batched(reqs):
         be = BatchBackend(iterations_per_step=16)
@@ -310,6 +311,17 @@ def main():
     graph_solves_per_s = args.steps / (time.perf_counter() - tg0)
     print(f"bench: graph-replayed steps {graph_solves_per_s:.4f} solves/s", file=sys.stderr, flush=True)
 
+    # the other scalar reading: 9 recurrences (per-condition alpha, beta), one synchronized stop
+    opts_pc = solver.options(omega=case.omega, eps=case.eps, scalars=G.GAP_SCALARS_PER_COND)
+    solver.step(case.e, case.edot, case.delta, opts_pc)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    _, _, info_pc = solver.step(case.e, case.edot, case.delta, opts_pc)
+    torch.cuda.synchronize()
+    per_cond = {"solves_per_s": round(1.0 / (time.perf_counter() - tp0), 5), "iterations": info_pc.iterations,
+                "scalars": "per condition, synchronized stopping test (Eq 3.9)"}
+    print(f"bench: per-condition scalars {per_cond}", file=sys.stderr, flush=True)
+
     stream = torch.cuda.current_stream(dev)
     G.gap_kernel_timing(solver.handle, 1)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
@@ -381,7 +393,7 @@ def main():
                    "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "seed": args.seed},
         "gdof_iter_per_s": round(gdof, 3), "iterations": mean_iters,
         "graph_solves_per_s": round(graph_solves_per_s, 5),
-        "pcg_config": solver.pcg_config, "tune": tune,
+        "pcg_config": solver.pcg_config, "tune": tune, "per_condition_scalars": per_cond,
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},

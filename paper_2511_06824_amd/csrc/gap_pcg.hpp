@@ -212,16 +212,21 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
     const int t = threadIdx.x;
 
     // registers: u of rows s-1, s, s+1; face conductances of faces s, s+1; kx of row s at
-    // the own and at the western column (periodic); and the loads of the next row step,
-    // issued one step ahead.  The western kx is a second load of the same cache lines.
+    // the own and at the western column (periodic; a second load of the same cache lines).
+    // The loads of the next PF row steps are in flight in the stages: stage k holds row step
+    // s + 1 + k (kx of that row, its northern face, z and u_prev of the row after it).  Two
+    // steps ahead where registers allow: a row step of this kernel moves little data, so one
+    // step of lead does not cover the memory latency.
+    constexpr int PF = (Q <= 2) ? 2 : 1;
     double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], kwc[Q];
-    double nz_[Q], nu_[Q], nkx[Q], nkw[Q], nkz[Q];
+    double pz[PF][Q], pu[PF][Q], pkx[PF][Q], pkw[PF][Q], pkz[PF][Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
         const int dw = i ? -1 : nt - 1;
         um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = kwc[q] = 0.0;
-        nz_[q] = nu_[q] = nkx[q] = nkw[q] = nkz[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) pz[k][q] = pu[k][q] = pkx[k][q] = pkw[k][q] = pkz[k][q] = 0.0;
         if (i < nt) {
             if (j0 > 0) {
                 const size_t g = (size_t)(j0 - 1) * nt + i;
@@ -239,23 +244,49 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
             }
         }
     }
-    double acc = 0.0;
-    for (int s = j0; s < j1; ++s) {
-        const int buf = s & 1;
-        // issue the loads of the next row step (row s + 2 of u, row s + 1 of kx, face s + 2)
+    // prologue: stages 0 .. PF-2 receive row steps j0+1 .. j0+PF-1
+#pragma unroll
+    for (int k = 0; k < PF - 1; ++k) {
+        const int r = j0 + 1 + k;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = t + q * NT;
-            if (i < nt && s + 1 < j1) {
-                const size_t g1 = (size_t)(s + 1) * nt + i;
-                nkx[q] = kx[g1];
-                nkw[q] = kx[g1 + (i ? -1 : nt - 1)];
-                nkz[q] = kz[g1 + nt];
-                if (s + 2 < nz) {
-                    nz_[q] = zc[g1 + nt];
-                    if (!first) nu_[q] = ui[g1 + nt];
+            if (i < nt && r < j1) {
+                const size_t g1 = (size_t)r * nt + i;
+                pkx[k][q] = kx[g1];
+                pkw[k][q] = kx[g1 + (i ? -1 : nt - 1)];
+                pkz[k][q] = kz[g1 + nt];
+                if (r + 1 < nz) {
+                    pz[k][q] = zc[g1 + nt];
+                    if (!first) pu[k][q] = ui[g1 + nt];
                 }
             }
+        }
+    }
+    double acc = 0.0;
+    for (int s = j0; s < j1; ++s) {
+        const int buf = s & 1;
+        // issue the loads of row step s + PF into the last stage
+        {
+            const int r = s + PF;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int i = t + q * NT;
+                if (i < nt && r < j1) {
+                    const size_t g1 = (size_t)r * nt + i;
+                    pkx[PF - 1][q] = kx[g1];
+                    pkw[PF - 1][q] = kx[g1 + (i ? -1 : nt - 1)];
+                    pkz[PF - 1][q] = kz[g1 + nt];
+                    if (r + 1 < nz) {
+                        pz[PF - 1][q] = zc[g1 + nt];
+                        if (!first) pu[PF - 1][q] = ui[g1 + nt];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
             if (i < nt) su[buf * nt + i] = uc[q];
         }
         __syncthreads();
@@ -274,15 +305,24 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
                 uo[(size_t)s * nt + i] = uc[q];
             }
         }
+        // advance one row: the current state takes stage 0 (row step s + 1), the stages shift
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             um[q] = uc[q];
             uc[q] = up[q];
             kzS[q] = kzN[q];
-            kzN[q] = nkz[q];
-            kxc[q] = nkx[q];
-            kwc[q] = nkw[q];
-            up[q] = (s + 2 < nz) ? (first ? nz_[q] : nz_[q] + beta * nu_[q]) : 0.0;
+            kzN[q] = pkz[0][q];
+            kxc[q] = pkx[0][q];
+            kwc[q] = pkw[0][q];
+            up[q] = (s + 2 < nz) ? (first ? pz[0][q] : pz[0][q] + beta * pu[0][q]) : 0.0;
+#pragma unroll
+            for (int k = 0; k + 1 < PF; ++k) {
+                pz[k][q] = pz[k + 1][q];
+                pu[k][q] = pu[k + 1][q];
+                pkx[k][q] = pkx[k + 1][q];
+                pkw[k][q] = pkw[k + 1][q];
+                pkz[k][q] = pkz[k + 1][q];
+            }
         }
     }
     double v1[1] = {acc};

@@ -87,7 +87,7 @@ std::vector<PcgShape> pcg_candidates(int nt)
     if (nt <= 256) return {{256, 1}, {128, 2}};
     if (nt <= 512) return {{512, 1}, {256, 2}};
     if (nt <= 1024) return {{512, 2}, {1024, 1}, {256, 4}};
-    return {{512, 4}, {1024, 2}};        // n_theta <= 2048 (validated at create)
+    return {{1024, 2}, {512, 4}};        // n_theta <= 2048 (validated at create)
 }
 
 // Dynamic LDS of the A kernel (u row, double-buffered) and of the B kernels (u and y rows,

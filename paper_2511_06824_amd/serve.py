@@ -9,9 +9,13 @@ released and the next queued requests are admitted.  Latency = completion - arri
 
 Scheduling inside the batch: without a work cap every admitted request advances in every
 step (processor sharing).  With ``work_cap`` (condition-DOFs per step), each step advances
-the admitted requests oldest first while their summed size fits the cap (the oldest one
-always advances) and holds the rest on the device (``gap_batch_hold``): large requests then
-run one after another at full bandwidth while small ones fill what the cap leaves.
+admitted requests in the order of ``order`` while their summed size fits the cap (the first
+one always advances) and holds the rest on the device (``gap_batch_hold``):
+  * "smallest" (default): smallest request first, then arrival.  Small requests, which
+    cannot fill the GPU alone, advance together; a request as large as the cap runs alone at
+    full bandwidth and yields to small requests while they are present.
+  * "oldest": arrival order; large requests run one after another and small ones fill what
+    the cap leaves beside them.
 
 The admission and scheduling logic (``AdmissionController``, ``GapServer``) is independent
 of the device: ``BatchBackend`` drives the HIP library, tests may substitute a fake backend
@@ -161,16 +165,24 @@ class BatchBackend:
 class GapServer:
     """Event loop: admit by arrival order and budget, step the batch, retire finished work."""
 
-    def __init__(self, backend, budget_bytes, clock=None, work_cap=None):
+    def __init__(self, backend, budget_bytes, clock=None, work_cap=None, order="smallest"):
+        if order not in ("smallest", "oldest"):
+            raise ValueError(f"unknown order {order!r}")
         self.backend = backend
         self.admission = AdmissionController(budget_bytes)
         self.clock = clock or WallClock()
         self.work_cap = work_cap
+        self.order = order
 
     def _schedule(self):
-        """Oldest first while the summed work fits the cap; the oldest always advances."""
+        """Requests in scheduling order while the summed work fits the cap; the first always
+        advances."""
+        if self.order == "smallest":
+            key = lambda q: (self.backend.work(q.case), q.arrival, q.rid)
+        else:
+            key = lambda q: (q.arrival, q.rid)
         chosen, total = [], 0
-        for r in sorted(self.backend.active(), key=lambda q: (q.arrival, q.rid)):
+        for r in sorted(self.backend.active(), key=key):
             w = self.backend.work(r.case)
             if not chosen or total + w <= self.work_cap:
                 chosen.append(r)

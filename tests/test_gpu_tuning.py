@@ -22,7 +22,7 @@ P_TOL, F_TOL = 1e-9, 1e-8
 EPS = 1e-13
 
 # ring sizes and the candidate shapes (threads, columns per thread) the library lists for them
-SHAPES = {300: [(512, 1), (256, 2)], 1000: [(512, 2), (1024, 1), (256, 4)], 2048: [(512, 4), (1024, 2)]}
+SHAPES = {300: [(512, 1), (256, 2)], 1000: [(512, 2), (1024, 1), (256, 4)], 2048: [(1024, 2), (512, 4)]}
 CASES = [(300, 23, 9), (1000, 9, 9), (2048, 5, 1)]
 
 _ref = {}

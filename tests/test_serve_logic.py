@@ -117,7 +117,7 @@ def test_work_cap_runs_large_requests_in_order_and_small_ones_beside_them():
     advance beside whichever large one runs."""
     clock = FakeClock()
     be = FakeBackend(clock)
-    srv = GapServer(be, budget_bytes=1000, clock=clock, work_cap=5)
+    srv = GapServer(be, budget_bytes=1000, clock=clock, work_cap=5, order="oldest")
     rs = [req(0, 0.0, 10, 4, work=4), req(1, 0.0, 10, 4, work=4), req(2, 0.5, 10, 2, work=1)]
     done = {r.rid: r for r in srv.run(rs)}
     assert done[0].finished == 4.0                 # the oldest large request is never held
@@ -132,3 +132,18 @@ def test_without_a_cap_all_admitted_requests_share_each_step():
     rs = [req(0, 0.0, 10, 4, work=4), req(1, 0.0, 10, 4, work=4)]
     done = {r.rid: r for r in srv.run(rs)}
     assert done[0].finished == done[1].finished == 4.0
+
+
+def test_smallest_first_lets_small_requests_pass_a_large_one():
+    """Cap 4 (one large request): the large request yields while small ones are present;
+    small ones advance together."""
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    srv = GapServer(be, budget_bytes=1000, clock=clock, work_cap=4)
+    rs = [req(0, 0.0, 10, 5, work=4), req(1, 1.5, 10, 2, work=1), req(2, 1.5, 10, 2, work=1)]
+    done = {r.rid: r for r in srv.run(rs)}
+    # t=0..2: the large one alone (3 steps left); t=2..4: the two small ones together; then it resumes
+    assert done[1].finished == done[2].finished == 4.0
+    assert done[0].finished == 7.0
+    with pytest.raises(ValueError):
+        GapServer(be, budget_bytes=1, clock=clock, order="random")
