@@ -14,6 +14,13 @@
 // (east wrap of the last column in L, west wrap of the first column in L^T) stay inside one
 // workgroup.  The chunk of rows [j0, j1) reads one or two halo rows on each side.
 //
+// Cache hints: the u stores of A, and the p loads and z stores of B, are non-temporal.  Those
+// streams are not re-read within a launch, and keeping them out of L2 and the Infinity Cache
+// leaves both to what is re-read (the operator rows shared by conditions, the halo rows, the
+// vectors the next kernel reads first).  On the 2048 x 1024 joint workload this subset
+// measured fastest of the combinations of hints on the five vector streams (iteration -2 %,
+// B -3 %).
+//
 // Scalars: every workgroup reduces the per-chunk partial sums it needs at its start, in a
 // fixed order, so all workgroups of a launch derive identical alpha / beta / stopping
 // decisions without atomics or an extra launch; workgroup 0 publishes the host-visible
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
                 if (s > 0) v -= kzS[q] * um[q];
                 if (s < nz - 1) v -= kzN[q] * up[q];
                 acc += uc[q] * v;
-                uo[(size_t)s * nt + i] = uc[q];
+                __builtin_nontemporal_store(uc[q], &uo[(size_t)s * nt + i]);
             }
         }
         // advance one row: the current state takes stage 0 (row step s + 1), the stages shift
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
             kxc[q] = kx[g];
             kwc[q] = kx[g + (i ? -1 : nt - 1)];
             rc[q] = rin[g];
-            if (!INIT && s_begin >= j0) pc[q] = pp[g];
+            if (!INIT && s_begin >= j0) pc[q] = __builtin_nontemporal_load(&pp[g]);
         }
     }
     double acc_rz = 0.0, acc_rr = 0.0, acc_ss = 0.0;
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
                     nkw[q] = kx[g1 + (i ? -1 : nt - 1)];
                     nkz[q] = kz[g1 + nt];
                     nr[q] = rin[g1];
-                    np[q] = (!INIT && s + 1 >= j0 && s + 1 < j1) ? pp[g1] : 0.0;
+                    np[q] = (!INIT && s + 1 >= j0 && s + 1 < j1) ? __builtin_nontemporal_load(&pp[g1]) : 0.0;
                 }
             }
         }
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
                         if (i < nt - 1) hi += kxprev[q] * svp[i + 1];
                         if (i == 0) hi += kxwrap_prev * svp[nt - 1];
                         const double zv = scale * (vprev[q] + om * dinvprev[q] * hi);
-                        zz[(size_t)(s - 1) * nt + i] = zv;
+                        __builtin_nontemporal_store(zv, &zz[(size_t)(s - 1) * nt + i]);
                         acc_rz += rpprev[q] * zv;
                     }
                     yprev[q] = y[q];
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
                 if (i < nt - 1) hi += kxprev[q] * svp[i + 1];
                 if (i == 0) hi += kxwrap_prev * svp[nt - 1];
                 const double zv = scale * (vprev[q] + om * dinvprev[q] * hi);
-                zz[(size_t)(nz - 1) * nt + i] = zv;
+                __builtin_nontemporal_store(zv, &zz[(size_t)(nz - 1) * nt + i]);
                 acc_rz += rpprev[q] * zv;
             }
         }
