@@ -33,16 +33,17 @@ def kernel_bytes(n, n_cond, n_op):
 
 
 def run_cpu_baseline(case, iterations_gpu, n_cond):
-    """Oracle on a bounded sample: condition 0 of the same input, assembly + 20 PCG
-    iterations (Table 1, ASSOR II) + force integral, scaled to n_cond conditions and the
-    GPU's iteration count.  The oracle is plain NumPy/SciPy on one core."""
+    """Oracle on a bounded sample: condition 0 of the same input, assembly + 200 PCG
+    iterations (Table 1, ASSOR II) + force integral (about 10-15 s on one core), scaled to
+    n_cond conditions and the GPU's iteration count.  The oracle is plain NumPy/SciPy on one
+    core."""
     import numpy as np
     import oracle
     gap = oracle.Gap(case.R, case.c, case.L, case.mu, case.U, case.V, case.p_in, case.p_out,
                      case.n_theta, case.n_axial)
     tex = oracle.dimple_texture(case.R, case.dimple_theta, case.dimple_z, case.dimple_radius,
                                 case.dimple_depth) if case.n_dimples else oracle.no_texture
-    sample_iters = 20
+    sample_iters = 200
     t0 = time.perf_counter()
     A, S = oracle.assemble(gap, case.e, case.edot, tex)
     t1 = time.perf_counter()
@@ -419,7 +420,7 @@ def plain_solve(case, JointGapSolver, dev, tune=True, handle=None):
             ed[k - 5] += case.delta[k - 1]
         conds.append((e, ed))
     s1 = handle or JointGapSolver.from_case(case, max_cond=1, device=dev)
-    opts = s1.options(omega=case.omega, eps=case.eps, check_every=1)
+    opts = s1.options(omega=case.omega, eps=case.eps, check_every=1, graph=False)
     if tune:
         s1.assemble(conds[0][0], conds[0][1], None, 1)
         s1.tune(opts, iterations=20)

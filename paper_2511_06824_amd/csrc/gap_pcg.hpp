@@ -154,10 +154,84 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
     if (a.sc->done) return;
     const int j0 = kc * a.rows_a, j1 = min(j0 + a.rows_a, a.nz), slot = c * a.chunks_a + kc;
     const bool writer = (c == 0 && kc == 0);   // publishes the request's device record
+    // A condition frozen by the asynchronized test stays frozen: skip it before any load
+    // (the mask of the previous iteration; the writer always runs)
+    if (a.async && !writer && !((a.sc->active_b >> c) & 1)) return;
     const int j = a.sc->iter_a;
     const int nt = a.nt, nz = a.nz;
     const size_t n = (size_t)nt * nz;
 
+    // ---- rows of the chunk: operands of the first rows (issued before the scalars) -----
+    extern __shared__ double lds[];
+    double* su = lds;             // [2][nt]  u of the current row, by row parity
+    const int op = a.op[c];
+    const double* kx = a.kx + (size_t)op * n;
+    const double* kz = a.kz + (size_t)op * (n + nt);
+    const double* zc = a.z + (size_t)c * n;
+    const double* ui = a.u[(j + 1) & 1] + (size_t)c * n;
+    double* uo = a.u[j & 1] + (size_t)c * n;
+    const bool first = (j == 0);
+    const int t = threadIdx.x;
+
+    // registers: u of rows s-1, s, s+1; face conductances of faces s, s+1; kx of row s at
+    // the own and at the western column (periodic; a second load of the same cache lines).
+    // The loads of the next PF row steps are in flight in the stages: stage k holds row step
+    // s + 1 + k (kx of that row, its northern face, z and u_prev of the row after it).  Two
+    // steps ahead where registers allow: a row step of this kernel moves little data, so one
+    // step of lead does not cover the memory latency.
+    constexpr int PF = (Q <= 2) ? 2 : 1;
+    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], kwc[Q];
+    double pz[PF][Q], pu[PF][Q], pkx[PF][Q], pkw[PF][Q], pkz[PF][Q];
+    // the loads of the first rows do not depend on the scalars: they are issued before the
+    // reduction below and combined with beta after it (um/uc/up hold z, um_/uc_/up_ u_prev)
+    double um_[Q], uc_[Q], up_[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = t + q * NT;
+        const int dw = i ? -1 : nt - 1;
+        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = kwc[q] = 0.0;
+        um_[q] = uc_[q] = up_[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) pz[k][q] = pu[k][q] = pkx[k][q] = pkw[k][q] = pkz[k][q] = 0.0;
+        if (i < nt) {
+            if (j0 > 0) {
+                const size_t g = (size_t)(j0 - 1) * nt + i;
+                um[q] = zc[g];
+                if (!first) um_[q] = ui[g];
+            }
+            size_t g = (size_t)j0 * nt + i;
+            uc[q] = zc[g];
+            if (!first) uc_[q] = ui[g];
+            kzS[q] = kz[g];
+            kxc[q] = kx[g];
+            kwc[q] = kx[g + dw];
+            g += nt;
+            kzN[q] = kz[g];
+            if (j0 + 1 < nz) {
+                up[q] = zc[g];
+                if (!first) up_[q] = ui[g];
+            }
+        }
+    }
+    // prologue: stages 0 .. PF-2 receive row steps j0+1 .. j0+PF-1
+#pragma unroll
+    for (int k = 0; k < PF - 1; ++k) {
+        const int r = j0 + 1 + k;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            if (i < nt && r < j1) {
+                const size_t g1 = (size_t)r * nt + i;
+                pkx[k][q] = kx[g1];
+                pkw[k][q] = kx[g1 + (i ? -1 : nt - 1)];
+                pkz[k][q] = kz[g1 + nt];
+                if (r + 1 < nz) {
+                    pz[k][q] = zc[g1 + nt];
+                    if (!first) pu[k][q] = ui[g1 + nt];
+                }
+            }
+        }
+    }
     // ---- scalars: beta_{j-1} = d_j / d_{j-1}, stopping test on ||r_j|| -----------------
     __shared__ double sums[4][GAP_MAXC];
     {
@@ -206,68 +280,13 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
     }
     if (stop || !(active & (1u << c))) return;
 
-    // ---- march over the rows of the chunk ----------------------------------------------
-    extern __shared__ double lds[];
-    double* su = lds;             // [2][nt]  u of the current row, by row parity
-    const int op = a.op[c];
-    const double* kx = a.kx + (size_t)op * n;
-    const double* kz = a.kz + (size_t)op * (n + nt);
-    const double* zc = a.z + (size_t)c * n;
-    const double* ui = a.u[(j + 1) & 1] + (size_t)c * n;
-    double* uo = a.u[j & 1] + (size_t)c * n;
-    const bool first = (j == 0);
-    const int t = threadIdx.x;
-
-    // registers: u of rows s-1, s, s+1; face conductances of faces s, s+1; kx of row s at
-    // the own and at the western column (periodic; a second load of the same cache lines).
-    // The loads of the next PF row steps are in flight in the stages: stage k holds row step
-    // s + 1 + k (kx of that row, its northern face, z and u_prev of the row after it).  Two
-    // steps ahead where registers allow: a row step of this kernel moves little data, so one
-    // step of lead does not cover the memory latency.
-    constexpr int PF = (Q <= 2) ? 2 : 1;
-    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kxc[Q], kwc[Q];
-    double pz[PF][Q], pu[PF][Q], pkx[PF][Q], pkw[PF][Q], pkz[PF][Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = t + q * NT;
-        const int dw = i ? -1 : nt - 1;
-        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kxc[q] = kwc[q] = 0.0;
-#pragma unroll
-        for (int k = 0; k < PF; ++k) pz[k][q] = pu[k][q] = pkx[k][q] = pkw[k][q] = pkz[k][q] = 0.0;
-        if (i < nt) {
-            if (j0 > 0) {
-                const size_t g = (size_t)(j0 - 1) * nt + i;
-                um[q] = first ? zc[g] : zc[g] + beta * ui[g];
-            }
-            size_t g = (size_t)j0 * nt + i;
-            uc[q] = first ? zc[g] : zc[g] + beta * ui[g];
-            kzS[q] = kz[g];
-            kxc[q] = kx[g];
-            kwc[q] = kx[g + dw];
-            g += nt;
-            kzN[q] = kz[g];
-            if (j0 + 1 < nz) {
-                up[q] = first ? zc[g] : zc[g] + beta * ui[g];
-            }
-        }
-    }
-    // prologue: stages 0 .. PF-2 receive row steps j0+1 .. j0+PF-1
-#pragma unroll
-    for (int k = 0; k < PF - 1; ++k) {
-        const int r = j0 + 1 + k;
+    // u = z + beta u_prev on the first rows
+    if (!first) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int i = t + q * NT;
-            if (i < nt && r < j1) {
-                const size_t g1 = (size_t)r * nt + i;
-                pkx[k][q] = kx[g1];
-                pkw[k][q] = kx[g1 + (i ? -1 : nt - 1)];
-                pkz[k][q] = kz[g1 + nt];
-                if (r + 1 < nz) {
-                    pz[k][q] = zc[g1 + nt];
-                    if (!first) pu[k][q] = ui[g1 + nt];
-                }
-            }
+            um[q] += beta * um_[q];
+            uc[q] += beta * uc_[q];
+            up[q] += beta * up_[q];
         }
     }
     double acc = 0.0;
@@ -348,46 +367,13 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
     if (!INIT && a.sc->done) return;
     const int j0 = kc * a.rows_b, j1 = min(j0 + a.rows_b, a.nz), slot = c * a.chunks_b + kc;
     const bool writer = (c == 0 && kc == 0);   // publishes the request's device record
+    if (!INIT && !writer && !((a.sc->active_b >> c) & 1)) return;   // frozen condition
     const int j = INIT ? -1 : a.sc->iter_b;
     const int nt = a.nt, nz = a.nz;
     const size_t n = (size_t)nt * nz;
 
-    // ---- scalars: alpha_j = d_j / (u_j^T A u_j) ------------------------------------------
-    double alpha = 1.0;
-    if (!INIT) {
-        __shared__ double sums[2][GAP_MAXC];
-        const double* src[2] = {a.part_rz[j & 1], a.part_uau};
-        const int cnt[2] = {a.chunks_b, a.chunks_a};
-        cond_sums<NT, 2>(a.n_cond, cnt, src, sums);
-        const unsigned active = (unsigned)a.sc->active_b;
-        double num = 0.0, den = 0.0;
-        bool bad = false;
-        for (int k = 0; k < a.n_cond; ++k) {
-            if (!(active & (1u << k))) continue;
-            num += sums[0][k];
-            den += sums[1][k];
-            if (a.per_cond) bad |= !finite_d(sums[0][k] / sums[1][k]);
-        }
-        if (!a.per_cond) bad |= !finite_d(num / den);
-        alpha = a.per_cond ? sums[0][c] / sums[1][c] : num / den;
-        if (bad) {
-            if (writer && threadIdx.x == 0) {
-                a.sc->status = -4;
-                a.sc->done = 1;
-            }
-            return;
-        }
-        if (writer && threadIdx.x == 0) a.sc->iter_a = j + 1;
-        if (!(active & (1u << c))) return;
-    } else if (writer && threadIdx.x == 0) {
-        a.sc->iter_a = 0;
-        a.sc->iter_b = 0;
-        a.sc->done = 0;
-        a.sc->status = 0;
-        a.sc->iterations = 0;
-        a.sc->active_b = (1 << a.n_cond) - 1;
-    }
-
+    // ---- operands of the first rows: they do not depend on alpha and are issued before the
+    // reduction of the scalars ------------------------------------------------------------
     const bool spmv = !INIT || a.warm;
     const bool assor = (a.precond == 2);
     const int op = a.op[c];
@@ -441,6 +427,42 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
             if (!INIT && s_begin >= j0) pc[q] = __builtin_nontemporal_load(&pp[g]);
         }
     }
+    // ---- scalars: alpha_j = d_j / (u_j^T A u_j) ------------------------------------------
+    double alpha = 1.0;
+    if (!INIT) {
+        __shared__ double sums[2][GAP_MAXC];
+        const double* src[2] = {a.part_rz[j & 1], a.part_uau};
+        const int cnt[2] = {a.chunks_b, a.chunks_a};
+        cond_sums<NT, 2>(a.n_cond, cnt, src, sums);
+        const unsigned active = (unsigned)a.sc->active_b;
+        double num = 0.0, den = 0.0;
+        bool bad = false;
+        for (int k = 0; k < a.n_cond; ++k) {
+            if (!(active & (1u << k))) continue;
+            num += sums[0][k];
+            den += sums[1][k];
+            if (a.per_cond) bad |= !finite_d(sums[0][k] / sums[1][k]);
+        }
+        if (!a.per_cond) bad |= !finite_d(num / den);
+        alpha = a.per_cond ? sums[0][c] / sums[1][c] : num / den;
+        if (bad) {
+            if (writer && threadIdx.x == 0) {
+                a.sc->status = -4;
+                a.sc->done = 1;
+            }
+            return;
+        }
+        if (writer && threadIdx.x == 0) a.sc->iter_a = j + 1;
+        if (!(active & (1u << c))) return;
+    } else if (writer && threadIdx.x == 0) {
+        a.sc->iter_a = 0;
+        a.sc->iter_b = 0;
+        a.sc->done = 0;
+        a.sc->status = 0;
+        a.sc->iterations = 0;
+        a.sc->active_b = (1 << a.n_cond) - 1;
+    }
+
     double acc_rz = 0.0, acc_rr = 0.0, acc_ss = 0.0;
 
     for (int s = s_begin; s <= s_last; ++s) {

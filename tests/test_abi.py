@@ -31,7 +31,10 @@ def lib():
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
     assert {"create_gap_grid", "destroy_gap_grid", "assemble_joint_system", "solve_joint_pcg",
-            "integrate_force_moment", "jacobian_fd", "gap_last_error"} <= set(names)
+            "integrate_force_moment", "jacobian_fd", "jacobian_adjoint", "solve_with_adjoint",
+            "general_iteration_step", "set_operating_point", "gap_tune_pcg", "gap_get_pcg_config",
+            "gap_set_pcg_config", "gap_batch_create", "gap_batch_add", "gap_batch_step", "gap_batch_hold",
+            "gap_batch_poll", "gap_batch_remove", "gap_last_error"} <= set(names)
     for name in names:
         assert hasattr(lib, name), name
 
@@ -96,3 +99,22 @@ def test_create_rejects_out_of_range_dimples():
         with pytest.raises(G.GapError) as ei:
             G.create_gap_grid(good_geom(), G.make_dimples([th], [z], [a], [1e-5]), 9)
         assert ei.value.status == G.GAP_EINVAL
+
+
+def test_new_entry_points_reject_null_handles(lib):
+    """Argument checks that run before any device call."""
+    P = ctypes.c_void_p
+    assert lib.set_operating_point(None, 1.0, 0.0, 1e6, 1e5) == G.GAP_EINVAL
+    assert lib.gap_batch_hold(None, 1, 1) == G.GAP_EINVAL
+    assert lib.gap_get_pcg_config(None, None) == G.GAP_EINVAL
+    assert lib.gap_set_pcg_config(None, None) == G.GAP_EINVAL
+    opts = G.gap_default_opts()
+    J = (ctypes.c_double * 32)()
+    assert lib.solve_with_adjoint(None, ctypes.byref(opts), P(8), None, J, None, None) == G.GAP_EINVAL
+    assert lib.gap_tune_pcg(None, ctypes.byref(opts), P(8), 20, None, None, None) == G.GAP_EINVAL
+    prm = G.gap_step_params()
+    e = (ctypes.c_double * 4)()
+    F = (ctypes.c_double * 4)()
+    assert lib.general_iteration_step(None, ctypes.byref(opts), ctypes.byref(prm), None, P(8), e, e, F, None, None,
+                                      None) == G.GAP_EINVAL
+    assert "non-NULL" in G.gap_last_error() or "NULL" in G.gap_last_error()
