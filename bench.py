@@ -361,6 +361,16 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dominant), "kernel": dominant,
                 "bytes_per_launch": nbytes[dominant], "avg_launch_us": round(stats[dominant]["avg_us"], 2)}
 
+    # the whole PCG iteration (A + B launches): algorithmic bytes over the summed launch times
+    it_bytes = sum(nbytes[k] for k in stats if k in nbytes)
+    it_us = sum(stats[k]["avg_us"] for k in stats if k in nbytes)
+    it_achieved = it_bytes / (it_us * 1e-6) / 1e9
+    roofline_iteration = {"bound": "hbm", "achieved": round(it_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(it_achieved / HBM_PEAK_GBS, 4), "bytes_per_iteration": it_bytes,
+                          "us_per_iteration": round(it_us, 2),
+                          "traffic": (sum(recorded_traffic(k) or 0 for k in stats if k in nbytes)
+                                      if all(recorded_traffic(k) for k in stats if k in nbytes) else None)}
+
     plain = None
     if not args.no_plain:
         plain = run_plain(case, G, JointGapSolver, dev, tune=not args.no_tune)
@@ -398,7 +408,7 @@ def main():
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
-        "roofline": roofline, "plain_baseline": plain, "serving": serving, "adjoint_vs_fd": adjoint, "precond_study": study, "dynamics": dyn,
+        "roofline": roofline, "roofline_iteration": roofline_iteration, "plain_baseline": plain, "serving": serving, "adjoint_vs_fd": adjoint, "precond_study": study, "dynamics": dyn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

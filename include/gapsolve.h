@@ -285,16 +285,19 @@ gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, 
  * A workgroup of `threads` threads owns whole rings of one condition (thread t handles the
  * columns t, t + threads, ...; threads * cols_per_thread >= n_theta) and marches over a
  * chunk of rows; the rows of every condition are cut into chunks so that one launch places
- * wg_per_cu x (compute units) workgroups.  occupancy_a / occupancy_b report how many
- * workgroups of the A and B kernels fit on one CU with this shape (output only).  Results
- * depend on the configuration only through the summation order of the reductions. */
+ * wg_per_cu x (compute units) workgroups.  The A kernel (steps 9, 3 of Table 1) and the B
+ * kernels (steps 4-8, and the initial residual) are configured separately.  occupancy_*
+ * report how many workgroups of the kernel fit on one CU with its shape (output only).
+ * Results depend on the configuration only through the summation order of the reductions. */
 typedef struct {
-    int32_t threads;          /* 64, 128, 256, 512 or 1024 */
-    int32_t cols_per_thread;  /* 1, 2 or 4 */
-    int32_t wg_per_cu_a;      /* row chunking target of the A kernel, >= 1 */
-    int32_t wg_per_cu_b;      /* row chunking target of the B kernels, >= 1 */
-    int32_t occupancy_a;      /* output: A workgroups that fit on one CU */
-    int32_t occupancy_b;      /* output: B workgroups that fit on one CU */
+    int32_t threads_a;          /* A: 64, 128, 256, 512 or 1024 */
+    int32_t cols_per_thread_a;  /* A: 1, 2 or 4 */
+    int32_t wg_per_cu_a;        /* A: row chunking target, >= 1 */
+    int32_t occupancy_a;        /* output: A workgroups that fit on one CU */
+    int32_t threads_b;          /* B: as for A */
+    int32_t cols_per_thread_b;
+    int32_t wg_per_cu_b;
+    int32_t occupancy_b;        /* output */
 } gap_pcg_config;
 
 /* Read the configuration the next solve_joint_pcg of this handle uses.
@@ -302,20 +305,21 @@ typedef struct {
 gap_status gap_get_pcg_config(gap_grid_t grid, gap_pcg_config *cfg);
 
 /* Select a configuration (cfg NULL: the default, the first candidate shape for n_theta with
- * as many workgroups per CU as fit).  Accepted shapes: threads x cols_per_thread one of
- * 64x1, 128x1, 128x2, 256x1, 256x2, 256x4, 512x1, 512x2, 512x4, 1024x1, 1024x2 with
- * n_theta <= threads * cols_per_thread < 2 n_theta + 64; wg_per_cu in [1, 8].
- * Errors: GAP_EINVAL (unsupported shape or range), GAP_EDEVICE. */
+ * as many workgroups per CU as fit, for both kernels).  Accepted shapes: threads x
+ * cols_per_thread one of 64x1, 128x1, 128x2, 256x1, 256x2, 256x4, 512x1, 512x2, 512x4,
+ * 1024x1, 1024x2 with n_theta <= threads * cols_per_thread < 2 n_theta + 64; wg_per_cu in
+ * [1, 8].  Errors: GAP_EINVAL (unsupported shape or range), GAP_EDEVICE. */
 gap_status gap_set_pcg_config(gap_grid_t grid, const gap_pcg_config *cfg);
 
 /* Autotuner: time `iterations` PCG iterations of the assembled system (options of opts, run
  * from p = 0 without a stopping test) for every candidate shape of n_theta and every
- * wg_per_cu up to that shape's occupancy, keep the fastest on the handle and return it in
- * best (may be NULL) with its device time per iteration in us (may be NULL).  Overwrites p
- * (caller device memory, n_cond * n doubles) and the handle's Krylov state; call
- * solve_joint_pcg afterwards.  Stream-ordered on stream, synchronizes it.
- * Errors: GAP_EINVAL (NULL grid/opts/p, iterations outside [2, 10000]), GAP_ESTATE (nothing
- * assembled), GAP_EDEVICE. */
+ * wg_per_cu up to that shape's occupancy, with HIP events around each kernel launch; keep,
+ * for A and for B separately, the fastest configuration (the default unless another is at
+ * least 1 % faster), and return it in best (may be NULL) with the device time per iteration
+ * of the chosen pair in us (may be NULL).  Overwrites p (caller device memory, n_cond * n
+ * doubles) and the handle's Krylov state; call solve_joint_pcg afterwards.  Stream-ordered on
+ * stream, synchronizes it; resets the counters of gap_kernel_stats.  Errors: GAP_EINVAL (NULL
+ * grid/opts/p, iterations outside [2, 10000]), GAP_ESTATE (nothing assembled), GAP_EDEVICE. */
 gap_status gap_tune_pcg(gap_grid_t grid, const gap_solver_opts *opts, double *p, int32_t iterations,
                         gap_pcg_config *best, double *us_per_iteration, void *stream);
 

@@ -14,12 +14,13 @@
 // (east wrap of the last column in L, west wrap of the first column in L^T) stay inside one
 // workgroup.  The chunk of rows [j0, j1) reads one or two halo rows on each side.
 //
-// Cache hints: the u stores of A, and the p loads and z stores of B, are non-temporal.  Those
-// streams are not re-read within a launch, and keeping them out of L2 and the Infinity Cache
-// leaves both to what is re-read (the operator rows shared by conditions, the halo rows, the
-// vectors the next kernel reads first).  On the 2048 x 1024 joint workload this subset
-// measured fastest of the combinations of hints on the five vector streams (iteration -2 %,
-// B -3 %).
+// Cache hints: the row-by-row z and u_prev loads and the u stores of A, and the p loads and z
+// stores of B, are non-temporal.  Those streams are not re-read within a launch (the first
+// rows of a chunk, which neighbouring chunks also read as halo, keep normal loads), and
+// keeping them out of L2 and the Infinity Cache leaves both to what is re-read: the operator
+// rows shared by conditions and the halo rows.  On the 2048 x 1024 joint workload this subset
+// measured fastest of the combinations tried (iteration 379 -> 347 us together with the
+// early first-row loads).
 //
 // Scalars: every workgroup reduces the per-chunk partial sums it needs at its start, in a
 // fixed order, so all workgroups of a launch derive identical alpha / beta / stopping
@@ -304,8 +305,8 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
                     pkw[PF - 1][q] = kx[g1 + (i ? -1 : nt - 1)];
                     pkz[PF - 1][q] = kz[g1 + nt];
                     if (r + 1 < nz) {
-                        pz[PF - 1][q] = zc[g1 + nt];
-                        if (!first) pu[PF - 1][q] = ui[g1 + nt];
+                        pz[PF - 1][q] = __builtin_nontemporal_load(&zc[g1 + nt]);
+                        if (!first) pu[PF - 1][q] = __builtin_nontemporal_load(&ui[g1 + nt]);
                     }
                 }
             }

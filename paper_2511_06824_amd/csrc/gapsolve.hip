@@ -200,7 +200,8 @@ hipError_t launch_pcg(PcgShape sh, int which, int lds_nt, const PcgDev* reqs, co
 }
 
 // Capture `iters` iterations (A, B launch pairs) into a graph.
-hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh, int lds_nt, const PcgDev* reqs, const int* work_a,
+hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh_a, PcgShape sh_b, int lds_nt, const PcgDev* reqs,
+                         const int* work_a,
                          int blocks_a, const int* work_b, int blocks_b, hipGraphExec_t* exec)
 {
     hipGraph_t graph = nullptr;
@@ -208,8 +209,8 @@ hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh, int lds_nt, co
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int it = 0; it < iters && le == hipSuccess; ++it) {
-        le = launch_pcg(sh, 0, lds_nt, reqs, work_a, blocks_a, cap);
-        if (le == hipSuccess) le = launch_pcg(sh, 1, lds_nt, reqs, work_b, blocks_b, cap);
+        le = launch_pcg(sh_a, 0, lds_nt, reqs, work_a, blocks_a, cap);
+        if (le == hipSuccess) le = launch_pcg(sh_b, 1, lds_nt, reqs, work_b, blocks_b, cap);
     }
     e = hipStreamEndCapture(cap, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -255,7 +256,7 @@ struct gap_grid_s {
     double *adj_part = nullptr;                              // sensitivity partials
     double *step_buf = nullptr;                              // general iteration: F (9 x 4) and J (4 x 8)
     int cus = 256;                                           // compute units of the device
-    PcgShape shape{};                                        // PCG kernel shape in use
+    PcgShape shape_a{}, shape_b{};                           // PCG kernel shapes in use (A; B and init)
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
     int wg_a = 1, wg_b = 1;                                  // workgroups per CU the row chunking targets
     int lds_max = 65536;                                     // bytes of LDS one workgroup may use
@@ -401,7 +402,7 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
 
     // schedule tables for this (kernel shape, n_cond, chunk counts, operator map); graphs are
     // cached by table, so the shape belongs to the key
-    std::vector<int> key = {g->shape.NT, g->shape.Q, a.n_cond, a.chunks_a, a.chunks_b};
+    std::vector<int> key = {g->shape_a.NT, g->shape_a.Q, g->shape_b.NT, g->shape_b.Q, a.n_cond, a.chunks_a, a.chunks_b};
     for (int c = 0; c < a.n_cond; ++c) key.push_back(a.op[c]);
     gap_grid_s::Sched* sch = nullptr;
     for (auto& e : g->scheds)
@@ -440,7 +441,7 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     *g->req_host = a;
     HIPCHK(hipMemcpyAsync(g->req_dev, g->req_host, sizeof(PcgDev), hipMemcpyHostToDevice, st));
 
-    hipError_t le = launch_pcg(g->shape, 2, g->nt, g->req_dev, work_b, sch->blocks_b, st);
+    hipError_t le = launch_pcg(g->shape_b, 2, g->nt, g->req_dev, work_b, sch->blocks_b, st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
 
     // One block = check_every iterations (A, B launch pairs); after each block the host reads
@@ -449,12 +450,12 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     auto enqueue_block = [&](hipStream_t s, int iters, bool closing) -> hipError_t {
         for (int it = 0; it < iters + (closing ? 1 : 0); ++it) {
             timing_mark(g, GAP_KERNEL_PCG_A, true, s);
-            hipError_t e1 = launch_pcg(g->shape, 0, g->nt, g->req_dev, work_a, sch->blocks_a, s);
+            hipError_t e1 = launch_pcg(g->shape_a, 0, g->nt, g->req_dev, work_a, sch->blocks_a, s);
             timing_mark(g, GAP_KERNEL_PCG_A, false, s);
             if (e1 != hipSuccess) return e1;
             if (it == iters) break;
             timing_mark(g, GAP_KERNEL_PCG_B, true, s);
-            e1 = launch_pcg(g->shape, 1, g->nt, g->req_dev, work_b, sch->blocks_b, s);
+            e1 = launch_pcg(g->shape_b, 1, g->nt, g->req_dev, work_b, sch->blocks_b, s);
             timing_mark(g, GAP_KERNEL_PCG_B, false, s);
             if (e1 != hipSuccess) return e1;
         }
@@ -470,7 +471,7 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
             if (gr.block == check_every && gr.table == sch->table) exec = gr.exec;
         if (!exec) {
             if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            hipError_t ce = capture_block(g->cap_stream, check_every, g->shape, g->nt, g->req_dev, work_a, sch->blocks_a, work_b,
+            hipError_t ce = capture_block(g->cap_stream, check_every, g->shape_a, g->shape_b, g->nt, g->req_dev, work_a, sch->blocks_a, work_b,
                                           sch->blocks_b, &exec);
             if (ce != hipSuccess) return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce));
             if (g->graphs.size() >= 4) {
@@ -527,16 +528,17 @@ gap_status ensure_adjoint(gap_grid_t g)
     return s1;
 }
 
-// Switch the handle to kernel shape sh; wg_a / wg_b: workgroups per CU the row chunking
-// targets (0: as many as fit, i.e. the occupancy).
-hipError_t use_shape(gap_grid_t g, PcgShape sh, int wg_a, int wg_b)
+// Switch the handle to kernel shapes sa (A) and sb (B, init); wg_a / wg_b: workgroups per
+// CU the row chunking targets (0: as many as fit, i.e. the occupancy).
+hipError_t use_shape(gap_grid_t g, PcgShape sa, PcgShape sb, int wg_a, int wg_b)
 {
     int occ[3];
     for (int which = 0; which < 3; ++which) {
-        hipError_t e = pcg_prepare(sh, which, g->nt, &occ[which]);
+        hipError_t e = pcg_prepare(which == 0 ? sa : sb, which, g->nt, &occ[which]);
         if (e != hipSuccess) return e;
     }
-    g->shape = sh;
+    g->shape_a = sa;
+    g->shape_b = sb;
     for (int k = 0; k < 3; ++k) g->occ[k] = occ[k];
     g->wg_a = wg_a > 0 ? wg_a : occ[0];
     g->wg_b = wg_b > 0 ? wg_b : std::min(occ[1], occ[2]);
@@ -701,8 +703,8 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
             g->lds_max = lds;
-        g->shape = pcg_candidates(g->nt)[0];
-        const size_t need = pcg_lds_bytes(1, g->shape.NT * g->shape.Q) + 2048;
+        g->shape_a = g->shape_b = pcg_candidates(g->nt)[0];
+        const size_t need = pcg_lds_bytes(1, g->shape_b.NT * g->shape_b.Q) + 2048;
         if (need > (size_t)g->lds_max) {
             release(g);
             return fail(GAP_EINVAL, "n_theta = %d needs %zu bytes of LDS per workgroup, the device allows %d",
@@ -713,7 +715,7 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     const size_t max_pcg = (size_t)max_cond * g->nz;
     g->pcg_part_stride = max_pcg;
     {
-        hipError_t pe = use_shape(g, g->shape, 0, 0);
+        hipError_t pe = use_shape(g, g->shape_a, g->shape_b, 0, 0);
         if (pe != hipSuccess) {
             release(g);
             return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(pe));
@@ -1150,34 +1152,68 @@ gap_status gap_kernel_stats(gap_grid_t g, int32_t kernel, int64_t* launches, dou
 gap_status gap_get_pcg_config(gap_grid_t g, gap_pcg_config* cfg)
 {
     if (!g || !cfg) return fail(GAP_EINVAL, "grid and cfg must be non-NULL");
-    cfg->threads = g->shape.NT;
-    cfg->cols_per_thread = g->shape.Q;
+    cfg->threads_a = g->shape_a.NT;
+    cfg->cols_per_thread_a = g->shape_a.Q;
     cfg->wg_per_cu_a = g->wg_a;
-    cfg->wg_per_cu_b = g->wg_b;
     cfg->occupancy_a = g->occ[0];
+    cfg->threads_b = g->shape_b.NT;
+    cfg->cols_per_thread_b = g->shape_b.Q;
+    cfg->wg_per_cu_b = g->wg_b;
     cfg->occupancy_b = std::min(g->occ[1], g->occ[2]);
     return GAP_OK;
 }
 
+namespace {
+
+gap_status check_shape(gap_grid_t g, PcgShape sh)
+{
+    const int cols = sh.NT * sh.Q;
+    if (!shape_known(sh) || cols < g->nt || cols >= 2 * g->nt + 64)
+        return fail(GAP_EINVAL, "shape %d x %d does not fit a ring of %d cells", sh.NT, sh.Q, g->nt);
+    if (pcg_lds_bytes(1, cols) + 2048 > (size_t)g->lds_max)
+        return fail(GAP_EINVAL, "shape %d x %d needs more LDS than a workgroup may use", sh.NT, sh.Q);
+    return GAP_OK;
+}
+
+// One timed run of the tuner: average device us per launch of A and of B.
+gap_status tune_run(gap_grid_t g, const gap_solver_opts* t, double* p, void* stream, double* us_a, double* us_b)
+{
+    for (int k = 0; k < GAP_KERNEL_COUNT; ++k) {
+        g->launches[k] = 0;
+        g->total_ms[k] = 0.0;
+    }
+    g->timing = true;
+    gap_status s = solve_joint_pcg(g, t, p, nullptr, stream);
+    g->timing = false;
+    if (s != GAP_OK && s != GAP_ENOCONV) return s;
+    if (!g->launches[GAP_KERNEL_PCG_A] || !g->launches[GAP_KERNEL_PCG_B])
+        return fail(GAP_EDEVICE, "the tuning run recorded no launches");
+    *us_a = 1e3 * g->total_ms[GAP_KERNEL_PCG_A] / (double)g->launches[GAP_KERNEL_PCG_A];
+    *us_b = 1e3 * g->total_ms[GAP_KERNEL_PCG_B] / (double)g->launches[GAP_KERNEL_PCG_B];
+    return GAP_OK;
+}
+
+}  // namespace
+
 gap_status gap_set_pcg_config(gap_grid_t g, const gap_pcg_config* cfg)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
-    PcgShape sh = pcg_candidates(g->nt)[0];
+    PcgShape sa = pcg_candidates(g->nt)[0], sb = sa;
     int wa = 0, wb = 0;
     if (cfg) {
-        sh.NT = cfg->threads;
-        sh.Q = cfg->cols_per_thread;
-        const int cols = sh.NT * sh.Q;
-        if (!shape_known(sh) || cols < g->nt || cols >= 2 * g->nt + 64)
-            return fail(GAP_EINVAL, "shape %d x %d does not fit a ring of %d cells", sh.NT, sh.Q, g->nt);
-        if (pcg_lds_bytes(1, cols) + 2048 > (size_t)g->lds_max)
-            return fail(GAP_EINVAL, "shape %d x %d needs more LDS than a workgroup may use", sh.NT, sh.Q);
+        sa.NT = cfg->threads_a;
+        sa.Q = cfg->cols_per_thread_a;
+        sb.NT = cfg->threads_b;
+        sb.Q = cfg->cols_per_thread_b;
+        gap_status cs = check_shape(g, sa);
+        if (cs == GAP_OK) cs = check_shape(g, sb);
+        if (cs != GAP_OK) return cs;
         if (cfg->wg_per_cu_a < 1 || cfg->wg_per_cu_a > 8 || cfg->wg_per_cu_b < 1 || cfg->wg_per_cu_b > 8)
             return fail(GAP_EINVAL, "wg_per_cu must lie in [1, 8]");
         wa = cfg->wg_per_cu_a;
         wb = cfg->wg_per_cu_b;
     }
-    hipError_t e = use_shape(g, sh, wa, wb);
+    hipError_t e = use_shape(g, sa, sb, wa, wb);
     if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
     return GAP_OK;
 }
@@ -1190,8 +1226,7 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     gap_status vs = validate_opts(o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "gap_tune_pcg before assemble_joint_system");
-    hipStream_t st = (hipStream_t)stream;
-    // a fixed number of iterations, no stopping test, plain launches, one block
+    // a fixed number of iterations, no stopping test, plain launches timed by events
     gap_solver_opts t = *o;
     t.eps = 1e-300;
     t.max_iter = iterations;
@@ -1200,14 +1235,14 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     t.warm_start = 0;
     t.strategy = GAP_STRATEGY_SYNC;
     const bool timing = g->timing;
-    g->timing = false;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct Pick {
+        PcgShape sh;
+        int wg = 0;
+        double us = 0.0;
+        bool have = false;
+    } pa, pb, da, db;   // best and default, per kernel
+    const PcgShape def = pcg_candidates(g->nt)[0];
     gap_status result = GAP_OK;
-    for (auto& e : ev)
-        if (result == GAP_OK && hipEventCreate(&e) != hipSuccess) result = fail(GAP_EDEVICE, "hipEventCreate failed");
-    gap_pcg_config win{};
-    double win_us = 0.0;
-    bool have = false;
     for (const PcgShape sh : pcg_candidates(g->nt)) {
         if (result != GAP_OK) break;
         if (pcg_lds_bytes(1, sh.NT * sh.Q) + 2048 > (size_t)g->lds_max) continue;
@@ -1216,42 +1251,40 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
         for (int which = 0; which < 3 && ok; ++which) ok = pcg_prepare(sh, which, g->nt, &occ[which]) == hipSuccess;
         if (!ok) continue;
         const int ob = std::min(occ[1], occ[2]);
-        for (int wa = 1; wa <= occ[0] && result == GAP_OK; ++wa) {
-            for (int wb = 1; wb <= ob && result == GAP_OK; ++wb) {
-                if (use_shape(g, sh, wa, wb) != hipSuccess) {
-                    result = fail(GAP_EDEVICE, "preparing the PCG kernels");
-                    break;
-                }
-                double us = 0.0;
-                for (int rep = 0; rep < 2 && result == GAP_OK; ++rep) {   // first run: warm-up
-                    if (hipEventRecord(ev[0], st) != hipSuccess) result = fail(GAP_EDEVICE, "hipEventRecord failed");
-                    gap_status s = solve_joint_pcg(g, &t, p, nullptr, stream);
-                    if (s != GAP_OK && s != GAP_ENOCONV) result = s;
-                    if (result == GAP_OK && (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess))
-                        result = fail(GAP_EDEVICE, "timing a tuning run failed");
-                    float ms = 0.f;
-                    if (result == GAP_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
-                        result = fail(GAP_EDEVICE, "hipEventElapsedTime failed");
-                    us = 1e3 * ms / iterations;
-                }
-                if (result == GAP_OK && (!have || us < win_us)) {
-                    have = true;
-                    win_us = us;
-                    gap_get_pcg_config(g, &win);
-                }
+        // A and B are timed in the same runs; wg_per_cu of A and of B advance together
+        for (int w = 1; w <= std::max(occ[0], ob) && result == GAP_OK; ++w) {
+            const int wa = std::min(w, occ[0]), wb = std::min(w, ob);
+            if (use_shape(g, sh, sh, wa, wb) != hipSuccess) {
+                result = fail(GAP_EDEVICE, "preparing the PCG kernels");
+                break;
             }
+            double ua = 0.0, ub = 0.0, ta = 0.0, tb = 0.0;
+            result = tune_run(g, &t, p, stream, &ua, &ub);                       // warm-up
+            for (int rep = 0; rep < 2 && result == GAP_OK; ++rep) {
+                result = tune_run(g, &t, p, stream, &ua, &ub);
+                ta = rep ? std::min(ta, ua) : ua;
+                tb = rep ? std::min(tb, ub) : ub;
+            }
+            if (result != GAP_OK) break;
+            if (!pa.have || ta < pa.us) pa = {sh, wa, ta, true};
+            if (!pb.have || tb < pb.us) pb = {sh, wb, tb, true};
+            const bool is_def = sh.NT == def.NT && sh.Q == def.Q;
+            if (is_def && wa == occ[0]) da = {sh, wa, ta, true};
+            if (is_def && wb == ob) db = {sh, wb, tb, true};
         }
     }
-    for (auto& e : ev)
-        if (e) (void)hipEventDestroy(e);
     g->timing = timing;
     if (result != GAP_OK) return result;
-    if (!have) return fail(GAP_EDEVICE, "no kernel shape could be prepared");
-    gap_status ss = gap_set_pcg_config(g, &win);
-    if (ss != GAP_OK) return ss;
+    if (!pa.have || !pb.have) return fail(GAP_EDEVICE, "no kernel shape could be prepared");
+    // keep the default unless the best is at least 1 % faster (stable choice on near-ties)
+    if (da.have && da.us <= 1.01 * pa.us) pa = da;
+    if (db.have && db.us <= 1.01 * pb.us) pb = db;
+    hipError_t e = use_shape(g, pa.sh, pb.sh, pa.wg, pb.wg);
+    if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
+    gap_pcg_config win{};
     gap_get_pcg_config(g, &win);
     if (best) *best = win;
-    if (us_per_iteration) *us_per_iteration = win_us;
+    if (us_per_iteration) *us_per_iteration = pa.us + pb.us;
     return GAP_OK;
 }
 
@@ -1492,7 +1525,7 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
                 if (b->exec) (void)hipGraphExecDestroy(b->exec);
                 b->exec = nullptr;
                 if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, kBatchShape, b->reqs_dev, wa, b->blocks_a, wb,
+                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, b->shape, kBatchShape, b->reqs_dev, wa, b->blocks_a, wb,
                                               b->blocks_b, &b->exec);
                 if (ce != hipSuccess) {
                     b->exec = nullptr;

@@ -64,9 +64,10 @@ class gap_solve_info(ctypes.Structure):
 
 
 class gap_pcg_config(ctypes.Structure):
-    _fields_ = [("threads", ctypes.c_int32), ("cols_per_thread", ctypes.c_int32),
-                ("wg_per_cu_a", ctypes.c_int32), ("wg_per_cu_b", ctypes.c_int32),
-                ("occupancy_a", ctypes.c_int32), ("occupancy_b", ctypes.c_int32)]
+    _fields_ = [("threads_a", ctypes.c_int32), ("cols_per_thread_a", ctypes.c_int32),
+                ("wg_per_cu_a", ctypes.c_int32), ("occupancy_a", ctypes.c_int32),
+                ("threads_b", ctypes.c_int32), ("cols_per_thread_b", ctypes.c_int32),
+                ("wg_per_cu_b", ctypes.c_int32), ("occupancy_b", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

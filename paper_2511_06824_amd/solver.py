@@ -112,15 +112,21 @@ class JointGapSolver:
     def pcg_config(self):
         return G.gap_get_pcg_config(self.handle).as_dict()
 
-    def set_pcg_config(self, threads=None, cols_per_thread=None, wg_per_cu_a=None, wg_per_cu_b=None):
-        """Select a PCG kernel configuration; no arguments: the default."""
+    def set_pcg_config(self, threads=None, cols_per_thread=None, wg_per_cu_a=None, wg_per_cu_b=None,
+                       threads_b=None, cols_per_thread_b=None):
+        """Select the PCG kernel configuration: shape (threads x columns per thread) of A, and of
+        B when threads_b / cols_per_thread_b are given (else the same); no arguments: the
+        default."""
         if threads is None:
             G.gap_set_pcg_config(self.handle, None)
             return self.pcg_config
         cur = G.gap_get_pcg_config(self.handle)
-        cfg = G.gap_pcg_config(threads, cols_per_thread,
-                               cur.wg_per_cu_a if wg_per_cu_a is None else wg_per_cu_a,
-                               cur.wg_per_cu_b if wg_per_cu_b is None else wg_per_cu_b, 0, 0)
+        cfg = G.gap_pcg_config()
+        cfg.threads_a, cfg.cols_per_thread_a = int(threads), int(cols_per_thread)
+        cfg.threads_b = int(threads if threads_b is None else threads_b)
+        cfg.cols_per_thread_b = int(cols_per_thread if cols_per_thread_b is None else cols_per_thread_b)
+        cfg.wg_per_cu_a = cur.wg_per_cu_a if wg_per_cu_a is None else int(wg_per_cu_a)
+        cfg.wg_per_cu_b = cur.wg_per_cu_b if wg_per_cu_b is None else int(wg_per_cu_b)
         G.gap_set_pcg_config(self.handle, cfg)
         return self.pcg_config
 

@@ -61,15 +61,21 @@ def test_every_configuration_matches_oracle(nt, nz, n_cond):
     case, p_ref, F_ref = reference(nt, nz, n_cond)
     s = JointGapSolver.from_case(case, max_cond=9 if n_cond == 9 else 1)
     s.assemble(case.e, case.edot, case.delta, n_cond)
-    assert (s.pcg_config["threads"], s.pcg_config["cols_per_thread"]) == SHAPES[nt][0]
+    cfg0 = s.pcg_config
+    assert (cfg0["threads_a"], cfg0["cols_per_thread_a"]) == SHAPES[nt][0]
+    assert (cfg0["threads_b"], cfg0["cols_per_thread_b"]) == SHAPES[nt][0]
+    configs = []
     for NT, Q in SHAPES[nt]:
         occ = s.set_pcg_config(NT, Q, 1, 1)
         for wa, wb in sorted({(1, 1), (occ["occupancy_a"], occ["occupancy_b"]), (1, occ["occupancy_b"])}):
-            cfg = s.set_pcg_config(NT, Q, wa, wb)
-            log(f"case: {case.label} x{n_cond}, config {cfg}")
-            perr, ferr, info = check(s, case, n_cond, p_ref, F_ref)
-            log(f"  iterations {info.iterations}, pressure {perr:.2e}, forces {ferr:.2e}")
-            assert perr <= P_TOL and ferr <= F_TOL
+            configs.append(((NT, Q), (NT, Q), wa, wb))
+    configs.append((SHAPES[nt][-1], SHAPES[nt][0], 1, 1))          # A and B with different shapes
+    for (NA, QA), (NB, QB), wa, wb in configs:
+        cfg = s.set_pcg_config(NA, QA, wa, wb, threads_b=NB, cols_per_thread_b=QB)
+        log(f"case: {case.label} x{n_cond}, config {cfg}")
+        perr, ferr, info = check(s, case, n_cond, p_ref, F_ref)
+        log(f"  iterations {info.iterations}, pressure {perr:.2e}, forces {ferr:.2e}")
+        assert perr <= P_TOL and ferr <= F_TOL
     s.close()
 
 
@@ -80,12 +86,14 @@ def test_autotuner_choice_is_valid_and_matches_oracle():
     s.assemble(case.e, case.edot, case.delta, 9)
     cfg, us = s.tune(iterations=10, omega=case.omega)
     log(f"  tuned {cfg}, {us:.1f} us per iteration")
-    assert (cfg["threads"], cfg["cols_per_thread"]) in SHAPES[300]
+    assert (cfg["threads_a"], cfg["cols_per_thread_a"]) in SHAPES[300]
+    assert (cfg["threads_b"], cfg["cols_per_thread_b"]) in SHAPES[300]
     assert 1 <= cfg["wg_per_cu_a"] <= cfg["occupancy_a"] and 1 <= cfg["wg_per_cu_b"] <= cfg["occupancy_b"]
     assert us > 0.0 and s.pcg_config == cfg
     perr, ferr, _ = check(s, case, 9, p_ref, F_ref)   # the system survives tuning unchanged
     assert perr <= P_TOL and ferr <= F_TOL
-    assert (s.set_pcg_config()["threads"], s.pcg_config["cols_per_thread"]) == SHAPES[300][0]
+    d = s.set_pcg_config()
+    assert (d["threads_a"], d["cols_per_thread_a"]) == SHAPES[300][0] == (d["threads_b"], d["cols_per_thread_b"])
     s.close()
 
 
@@ -98,6 +106,9 @@ def test_configuration_validation():
         with pytest.raises(G.GapError) as ei:
             s.set_pcg_config(NT, Q, wa, wb)
         assert ei.value.status == G.GAP_EINVAL
+    with pytest.raises(G.GapError) as ei:
+        s.set_pcg_config(512, 1, 1, 1, threads_b=64, cols_per_thread_b=1)     # B shape too small
+    assert ei.value.status == G.GAP_EINVAL
     s.assemble(case.e, case.edot, None, 1)
     with pytest.raises(G.GapError) as ei:
         G.gap_tune_pcg(s.handle, s.options(), s.p.data_ptr(), 1)
