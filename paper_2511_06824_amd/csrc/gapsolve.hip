@@ -95,10 +95,18 @@ std::vector<PcgShape> pcg_candidates(int nt)
 size_t pcg_lds_bytes(int which, int nt) { return (size_t)(which == 0 ? 2 : 4) * nt * sizeof(double); }
 
 // Row chunks per condition: as many workgroups as the device holds at once (occupancy x CUs),
-// so that one launch runs in a single round.
-void pcg_chunks(int nz, int n_cond, int slots, int& chunks, int& rows)
+// so that one launch runs in a single round; but at least kMinChunkCells cells per chunk and
+// at most kMaxChunks workgroups per request.  Every workgroup reduces all chunk partials of
+// its request at its start (work ~ NQ x chunks^2 per launch), and a chunk of a row or two is
+// mostly halo: narrow rings (small n_theta) would otherwise get thousands of one-row chunks.
+constexpr int kMinChunkCells = 1024;
+constexpr int kMaxChunks = 1024;
+
+void pcg_chunks(int nz, int nt, int n_cond, int slots, int& chunks, int& rows)
 {
-    int per = slots / n_cond;
+    int per = std::min(slots, kMaxChunks) / n_cond;
+    const int min_rows = (kMinChunkCells + nt - 1) / nt;
+    per = std::min(per, std::max(1, nz / min_rows));
     if (per < 1) per = 1;
     if (per > nz) per = nz;
     rows = (nz + per - 1) / per;
@@ -397,8 +405,8 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
 {
     const int check_every = o->check_every ? o->check_every : 32;
     fill_pcg(g, a, o);
-    pcg_chunks(g->nz, a.n_cond, g->wg_a * g->cus, a.chunks_a, a.rows_a);
-    pcg_chunks(g->nz, a.n_cond, g->wg_b * g->cus, a.chunks_b, a.rows_b);
+    pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_a * g->cus, a.chunks_a, a.rows_a);
+    pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_b * g->cus, a.chunks_b, a.rows_b);
 
     // schedule tables for this (kernel shape, n_cond, chunk counts, operator map); graphs are
     // cached by table, so the shape belongs to the key
@@ -1466,8 +1474,8 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     fill_pcg(g, a, o);
     // chunking depends only on the request and the batch kernel shape, so a request gets
     // the same reduction order (bitwise the same result) alone and in any mix
-    pcg_chunks(g->nz, a.n_cond, b->occ_a * b->cus, a.chunks_a, a.rows_a);
-    pcg_chunks(g->nz, a.n_cond, b->occ_b * b->cus, a.chunks_b, a.rows_b);
+    pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_a * b->cus, a.chunks_a, a.rows_a);
+    pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_b * b->cus, a.chunks_b, a.rows_b);
     HIPCHK(hipStreamSynchronize(st));
     b->reqs_host[slot] = a;
     HIPCHK(hipMemcpyAsync(b->reqs_dev + slot, b->reqs_host + slot, sizeof(PcgDev), hipMemcpyHostToDevice, st));

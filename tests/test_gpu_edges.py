@@ -1,0 +1,77 @@
+"""GPU edge cases through the C ABI: closed-form degenerate solutions, the largest axial size,
+an empty batch."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import gap_of
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2511_06824_amd import gapsolve as G  # noqa: E402
+from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("ecc,U", [((0.0, 0.0, 0.0, 0.0), 2.0), ((6e-6, -3e-6, 6e-6, -3e-6), 0.0)],
+                         ids=["concentric", "parallel-offset"])
+def test_linear_axial_profile_closed_form(ecc, U):
+    """A film independent of z without wedge or squeeze: the discrete solution is exactly
+    p = p_in + (p_out - p_in) z / L (cell centres, Dirichlet faces half a cell away)."""
+    case = synth.smooth_case(96, 40, 0)
+    log(f"case: linear axial profile, e = {ecc}, U = {U}")
+    s = JointGapSolver(case.R, case.c, case.L, case.mu, U, 0.0, case.p_in, case.p_out, 96, 40, max_cond=1)
+    s.assemble(np.array(ecc), np.zeros(4), None, 1)
+    p, info = s.solve(omega=1.8, eps=1e-13)
+    p = p.reshape(40, 96).cpu().numpy()
+    s.close()
+    z = (np.arange(40) + 0.5) * case.L / 40
+    exact = case.p_in + (case.p_out - case.p_in) * z / case.L
+    err = np.max(np.abs(p - exact[:, None])) / case.p_in
+    log(f"  iterations {info.iterations}, max error {err:.1e} of p_in")
+    assert err <= 1e-9
+
+
+def test_largest_axial_size_follows_the_oracle_recurrence():
+    """n_axial = 65536 (the largest accepted) on a 16-cell ring, one condition: 100 iterations of
+    the GPU recurrence against 100 iterations of the oracle's Table 1 PCG with ASSOR II."""
+    nt, nz = 16, 65536
+    case = synth.smooth_case(nt, nz, 1)
+    log(f"case: {case.label}, 100 PCG iterations against the oracle")
+    gap = gap_of(case)
+    A, S = oracle.assemble(gap, case.e, case.edot)
+    M = oracle.assor2_precond(A, 1.8)
+    p_ref, it_ref, hist = oracle.pcg(A, S, M, 1e-300, 100)
+    s = JointGapSolver.from_case(case, max_cond=1)
+    s.assemble(case.e, case.edot, None, 1)
+    p, info = s.solve(omega=1.8, eps=1e-300, max_iter=100, raise_on_error=False)
+    p = p.reshape(-1).cpu().numpy()
+    kx, kz, Sg = [t.cpu().numpy() for t in s.read_system(0)]
+    s.close()
+    assert info.status == G.GAP_ENOCONV and info.iterations == 100 == it_ref
+    perr = np.linalg.norm(p - p_ref) / np.linalg.norm(p_ref)
+    rerr = abs(info.rel_residual - hist[-1]) / hist[-1]
+    true_rel = np.linalg.norm(Sg.ravel() - oracle.stencil_matrix(gap, kx, kz) @ p) / np.linalg.norm(Sg)
+    log(f"  pressure {perr:.1e}, recurrence residual {info.rel_residual:.3e} vs {hist[-1]:.3e}, true {true_rel:.3e}")
+    assert perr <= 1e-8 and rerr <= 1e-6
+    assert abs(true_rel - info.rel_residual) <= 1e-6 * info.rel_residual
+    np.testing.assert_allclose(Sg.ravel(), S, rtol=1e-11, atol=1e-11 * np.max(np.abs(S)))
+
+
+def test_empty_batch_steps_and_polls():
+    log("case: empty batch")
+    b = G.gap_batch_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    for use_graph in (True, False):
+        G.gap_batch_step(b, 4, use_graph, stream)
+    assert G.gap_batch_poll(b) == []
+    G.gap_batch_destroy(b)
