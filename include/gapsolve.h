@@ -169,6 +169,23 @@ gap_status solve_joint_pcg(gap_grid_t grid, const gap_solver_opts *opts, double 
 gap_status integrate_force_moment(gap_grid_t grid, const double *p, int32_t cavitation,
                                   double p_cav, double *F, void *stream);
 
+/* The forces of integrate_force_moment split into the normal-pressure part and the
+ * viscous-shear part (the paper reports them separately, Sec 4.3), with the axial force and
+ * the torque of the shear: F (device, n_cond x 10 doubles) per condition
+ *   pressure: Fx, Fy, Mx, My;  shear: Fx, Fy, Mx, My, Fz = sum tau_z dA, Mz = sum R tau_theta dA.
+ * The two parts of each of (Fx, Fy, Mx, My) add up to integrate_force_moment's value (up to
+ * summation order).  Arguments and errors as for integrate_force_moment. */
+gap_status integrate_force_moment_split(gap_grid_t grid, const double *p, int32_t cavitation, double p_cav,
+                                        double *F, void *stream);
+
+/* GMAF step II, "update and rebuild pressure field": the full field of every condition with
+ * its boundary rows, out (device, n_cond x (n_axial + 2) x n_theta doubles, theta fastest):
+ * row 0 is p_in (the face z = 0), rows 1 .. n_axial the cell-centre pressure after the
+ * cavitation rule, the last row p_out (z = L).  Arguments and errors as for
+ * integrate_force_moment. */
+gap_status rebuild_pressure_field(gap_grid_t grid, const double *p, int32_t cavitation, double p_cav,
+                                  double *out, void *stream);
+
 /* Step IV (Eq 2.13-2.14): forward-difference double Jacobian from the forces of the 9
  * conditions.  F: device, 9 * 4 doubles from integrate_force_moment.  J: device, 32
  * doubles, row-major 4 x 8, J[i*8 + k] = (F[(k+1)*4 + i] - F[i]) / delta[k], rows

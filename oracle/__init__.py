@@ -36,7 +36,8 @@ from .film import Gap, cell_centers, film, film_naive, film_rate, dimple_texture
 from .fvm import face_conductances, source, cell_values, stencil_matrix, assemble, conditions, assemble_joint
 from .direct import solve_band, solve_dense, sor_solve
 from .pcg import pcg, pcg_blocks, jacobi_precond, assor1_precond, assor2_precond, assor2_explicit
-from .forces import effective_pressure, force_moment, forces_for_condition
+from .forces import (effective_pressure, force_moment, forces_for_condition, force_moment_split,
+                     forces_split_for_condition, rebuild_field)
 from .jacobian import (solve_condition, condition_forces, jacobian_fd, jacobian_central,
                        jacobian_complex_step)
 from . import dynamics
@@ -46,7 +47,8 @@ __all__ = [
     "face_conductances", "source", "cell_values", "stencil_matrix", "assemble", "conditions", "assemble_joint",
     "solve_band", "solve_dense", "sor_solve",
     "pcg", "pcg_blocks", "jacobi_precond", "assor1_precond", "assor2_precond", "assor2_explicit",
-    "effective_pressure", "force_moment", "forces_for_condition",
+    "effective_pressure", "force_moment", "forces_for_condition", "force_moment_split",
+    "forces_split_for_condition", "rebuild_field",
     "solve_condition", "condition_forces", "jacobian_fd", "jacobian_central",
     "jacobian_complex_step", "dynamics",
 ]

@@ -155,8 +155,13 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_diag_precond(GeomDev g, int kind,
 // Fx, Fy, Mx, My per chunk before the factor dA.
 __device__ __forceinline__ double peff(double p, int cav, double pc) { return (cav && p < pc) ? pc : p; }
 
-__global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, ChunkMap cm, TablesDev tb, const double* __restrict__ p_all,
-                         int cav, double p_cav, double* __restrict__ partial)
+// NV = 4: (Fx, Fy, Mx, My) of pressure and shear together.  NV = 10: the pressure part
+// (Fx, Fy, Mx, My), then the shear part (Fx, Fy, Mx, My, Fz, Mz) with the axial force and the
+// torque of the wall shear.
+template <int NV>
+__global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, ChunkMap cm, TablesDev tb,
+                                                      const double* __restrict__ p_all, int cav, double p_cav,
+                                                      double* __restrict__ partial)
 {
     int c, j0, j1;
     chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
@@ -164,7 +169,9 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, Chu
     const size_t n = (size_t)nt * nz;
     const double* p = p_all + (size_t)c * n;
     const double* e = cd.e[c];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
     for (int j = j0; j < j1; ++j) {
         const double zj = (j + 0.5) * g.dz;
         const double zr = zj - 0.5 * g.L;
@@ -182,15 +189,28 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, Chu
             const double h = film_h(g, e, cs, sn, zj, tb.tex_c[gi]);
             const double tt = -0.5 * h * dpdx + g.mu * g.U / h;
             const double tz = -0.5 * h * dpdz + g.mu * g.V / h;
-            acc[0] += -pc * cs - tt * sn;
-            acc[1] += -pc * sn + tt * cs;
-            acc[2] += zr * (pc * sn - tt * cs) + tz * g.R * sn;
-            acc[3] += -zr * (pc * cs + tt * sn) - tz * g.R * cs;
+            if (NV == 4) {
+                acc[0] += -pc * cs - tt * sn;
+                acc[1] += -pc * sn + tt * cs;
+                acc[2] += zr * (pc * sn - tt * cs) + tz * g.R * sn;
+                acc[3] += -zr * (pc * cs + tt * sn) - tz * g.R * cs;
+            } else {
+                acc[0] += -pc * cs;
+                acc[1] += -pc * sn;
+                acc[2] += zr * pc * sn;
+                acc[3] += -zr * pc * cs;
+                acc[4 % NV] += -tt * sn;
+                acc[5 % NV] += tt * cs;
+                acc[6 % NV] += -zr * tt * cs + tz * g.R * sn;
+                acc[7 % NV] += -zr * tt * sn - tz * g.R * cs;
+                acc[8 % NV] += tz;
+                acc[9 % NV] += g.R * tt;
+            }
         }
     }
-    block_sum<4>(acc);
+    block_sum<NV>(acc);
     if (threadIdx.x == 0)
-        for (int q = 0; q < 4; ++q) partial[q * cm.total + blockIdx.x] = acc[q];
+        for (int q = 0; q < NV; ++q) partial[q * cm.total + blockIdx.x] = acc[q];
 }
 
 __device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& cm, int c)
@@ -201,14 +221,33 @@ __device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& c
     return v[0];   // valid in thread 0
 }
 
-__global__ __launch_bounds__(GAP_BLOCK) void k_forces_finalize(ChunkMap cm, int n_cond, double dA, const double* __restrict__ part,
-                                  double* __restrict__ F)
+__global__ __launch_bounds__(GAP_BLOCK) void k_forces_finalize(ChunkMap cm, int n_cond, int nv, double dA,
+                                                               const double* __restrict__ part, double* __restrict__ F)
 {
     for (int c = 0; c < n_cond; ++c)
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < nv; ++q) {
             const double s = cond_sum(part + q * cm.total, cm, c);
-            if (threadIdx.x == 0) F[c * 4 + q] = s * dA;
+            if (threadIdx.x == 0) F[c * nv + q] = s * dA;
         }
+}
+
+// GMAF step II: the full field with its boundary rows, out[c][j][i] for j = 0 .. n_axial + 1
+// (row 0: p_in at z = 0, rows 1 .. n_axial: the cell centres after the cavitation rule, last
+// row: p_out at z = L).
+__global__ __launch_bounds__(GAP_BLOCK) void k_rebuild(GeomDev g, int n_cond, const double* __restrict__ p_all, int cav,
+                                                       double p_cav, double* __restrict__ out)
+{
+    const size_t nt = g.nt, nz = g.nz;
+    const size_t per = (nz + 2) * nt;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per * (size_t)n_cond) return;
+    const size_t c = idx / per, r = idx - c * per;
+    const size_t j = r / nt, i = r - j * nt;
+    double v;
+    if (j == 0) v = g.p_in;
+    else if (j == nz + 1) v = g.p_out;
+    else v = peff(p_all[c * nz * nt + (j - 1) * nt + i], cav, p_cav);
+    out[idx] = v;
 }
 
 // Eq 2.13-2.14: J[i][k] = (F_{k+1,i} - F_{0,i}) / delta_k.

@@ -735,7 +735,7 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     ALLOC(g->u0, max_cond * n);
     ALLOC(g->u1, max_cond * n);
     ALLOC(g->z, max_cond * n);
-    ALLOC(g->partial, 4 * max_chunks);
+    ALLOC(g->partial, 10 * max_chunks);
     ALLOC(g->pcg_part, 5 * max_pcg);
 #undef ALLOC
     if (hipMalloc((void**)&g->sc, sizeof(PcgScalars)) != hipSuccess) {
@@ -1103,22 +1103,62 @@ gap_status general_iteration_step(gap_grid_t g, const gap_solver_opts* o, const 
     return GAP_OK;
 }
 
-gap_status integrate_force_moment(gap_grid_t g, const double* p, int32_t cavitation, double p_cav, double* F,
-                                  void* stream)
+namespace {
+
+gap_status check_integrate(gap_grid_t g, const double* p, const double* out, int32_t cavitation, double p_cav,
+                           const char* what)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
-    if (!p || !F) return fail(GAP_EINVAL, "p and F must be non-NULL");
-    if (!g->assembled) return fail(GAP_ESTATE, "integrate_force_moment before assemble_joint_system");
+    if (!p || !out) return fail(GAP_EINVAL, "p and the output must be non-NULL");
+    if (!g->assembled) return fail(GAP_ESTATE, "%s before assemble_joint_system", what);
     if (cavitation != GAP_CAVITATION_NONE && cavitation != GAP_CAVITATION_CLAMP)
         return fail(GAP_EINVAL, "unknown cavitation mode");
     if (!is_finite(p_cav)) return fail(GAP_EINVAL, "p_cav must be finite");
+    return GAP_OK;
+}
+
+}  // namespace
+
+gap_status integrate_force_moment(gap_grid_t g, const double* p, int32_t cavitation, double p_cav, double* F,
+                                  void* stream)
+{
+    gap_status cs = check_integrate(g, p, F, cavitation, p_cav, "integrate_force_moment");
+    if (cs != GAP_OK) return cs;
     hipStream_t st = (hipStream_t)stream;
     const ChunkMap cm = g->cm;
-    hipLaunchKernelGGL(k_forces, dim3(cm.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm, g->tables(), p, cavitation,
-                       p_cav, g->partial);
-    hipLaunchKernelGGL(k_forces_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm, g->n_cond, g->gd.dx * g->gd.dz,
+    hipLaunchKernelGGL((k_forces<4>), dim3(cm.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm, g->tables(), p,
+                       cavitation, p_cav, g->partial);
+    hipLaunchKernelGGL(k_forces_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm, g->n_cond, 4, g->gd.dx * g->gd.dz,
                        (const double*)g->partial, F);
     HIPLAUNCHCHK("force integration");
+    return GAP_OK;
+}
+
+gap_status integrate_force_moment_split(gap_grid_t g, const double* p, int32_t cavitation, double p_cav, double* F,
+                                        void* stream)
+{
+    gap_status cs = check_integrate(g, p, F, cavitation, p_cav, "integrate_force_moment_split");
+    if (cs != GAP_OK) return cs;
+    hipStream_t st = (hipStream_t)stream;
+    const ChunkMap cm = g->cm;
+    hipLaunchKernelGGL((k_forces<10>), dim3(cm.total), dim3(GAP_BLOCK), 0, st, g->gd, g->cd, cm, g->tables(), p,
+                       cavitation, p_cav, g->partial);
+    hipLaunchKernelGGL(k_forces_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm, g->n_cond, 10, g->gd.dx * g->gd.dz,
+                       (const double*)g->partial, F);
+    HIPLAUNCHCHK("split force integration");
+    return GAP_OK;
+}
+
+gap_status rebuild_pressure_field(gap_grid_t g, const double* p, int32_t cavitation, double p_cav, double* out,
+                                  void* stream)
+{
+    gap_status cs = check_integrate(g, p, out, cavitation, p_cav, "rebuild_pressure_field");
+    if (cs != GAP_OK) return cs;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t total = (size_t)g->n_cond * (g->nz + 2) * g->nt;
+    hipLaunchKernelGGL(k_rebuild, dim3((unsigned)((total + GAP_BLOCK - 1) / GAP_BLOCK)), dim3(GAP_BLOCK), 0, st, g->gd,
+                       g->n_cond, p, cavitation, p_cav, out);
+    HIPLAUNCHCHK("k_rebuild");
     return GAP_OK;
 }
 
@@ -1394,7 +1434,7 @@ gap_status gap_grid_bytes(const gap_geom* geom, int32_t max_cond, int64_t* bytes
     int64_t d = 4 * nt + 2 * n + (nz + 1) * nt;              // tables and texture samples
     d += max_op * n + max_op * (n + nt);                     // face conductances
     d += 6 * (int64_t)max_cond * n;                          // S, r (2), u (2), z
-    d += 4 * (int64_t)std::max(cm1.total, cm9.total);        // force partials
+    d += 10 * (int64_t)std::max(cm1.total, cm9.total);       // force partials
     d += 5 * (int64_t)max_cond * nz;                         // PCG partials
     d += (int64_t)max_cond * n;                              // the caller's pressure field
     *bytes = d * (int64_t)sizeof(double) + 4096;

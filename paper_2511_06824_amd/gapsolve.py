@@ -105,6 +105,8 @@ _SIGNATURES = {
     "assemble_joint_system": [_P, _D8, _D8, _D8, ctypes.c_int32, _P],
     "solve_joint_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(gap_solve_info), _P],
     "integrate_force_moment": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
+    "integrate_force_moment_split": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
+    "rebuild_pressure_field": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
     "jacobian_fd": [_P, _P, _P, _P],
     "gap_read_system": [_P, ctypes.c_int32, _P, _P, _P, _P],
     "jacobian_adjoint": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.c_double, _D8, _P,
@@ -224,6 +226,16 @@ def solve_joint_pcg(handle, opts, p_ptr, stream=None, raise_on_error=True):
 def integrate_force_moment(handle, p_ptr, cavitation, p_cav, F_ptr, stream=None):
     _check(load().integrate_force_moment(handle, ctypes.c_void_p(int(p_ptr)), int(cavitation), float(p_cav),
                                          ctypes.c_void_p(int(F_ptr)), _stream(stream)))
+
+
+def integrate_force_moment_split(handle, p_ptr, cavitation, p_cav, F_ptr, stream=None):
+    _check(load().integrate_force_moment_split(handle, ctypes.c_void_p(int(p_ptr)), int(cavitation), float(p_cav),
+                                               ctypes.c_void_p(int(F_ptr)), _stream(stream)))
+
+
+def rebuild_pressure_field(handle, p_ptr, cavitation, p_cav, out_ptr, stream=None):
+    _check(load().rebuild_pressure_field(handle, ctypes.c_void_p(int(p_ptr)), int(cavitation), float(p_cav),
+                                         ctypes.c_void_p(int(out_ptr)), _stream(stream)))
 
 
 def jacobian_fd(handle, F_ptr, J_ptr, stream=None):

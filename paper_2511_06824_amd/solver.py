@@ -139,6 +139,22 @@ class JointGapSolver:
                                  _stream(self.device))
         return self.F[: self.n_cond * 4].view(self.n_cond, 4)
 
+    def integrate_split(self, cavitation=G.GAP_CAVITATION_NONE, p_cav=0.0, p=None):
+        """Forces split per condition: (n_cond, 10) = pressure (Fx, Fy, Mx, My), shear (Fx, Fy, Mx,
+        My, Fz, Mz)."""
+        src = self.p if p is None else p
+        out = torch.empty(self.n_cond * 10, dtype=torch.float64, device=self.device)
+        G.integrate_force_moment_split(self.handle, src.data_ptr(), cavitation, p_cav, out.data_ptr(),
+                                       _stream(self.device))
+        return out.view(self.n_cond, 10)
+
+    def full_pressure(self, cavitation=G.GAP_CAVITATION_NONE, p_cav=0.0, p=None):
+        """The pressure of every condition with its two boundary rows: (n_cond, n_axial + 2, n_theta)."""
+        src = self.p if p is None else p
+        out = torch.empty(self.n_cond * (self.n_axial + 2) * self.n_theta, dtype=torch.float64, device=self.device)
+        G.rebuild_pressure_field(self.handle, src.data_ptr(), cavitation, p_cav, out.data_ptr(), _stream(self.device))
+        return out.view(self.n_cond, self.n_axial + 2, self.n_theta)
+
     def jacobian_fd(self):
         G.jacobian_fd(self.handle, self.F.data_ptr(), self.J.data_ptr(), _stream(self.device))
         return self.J.view(4, 8)

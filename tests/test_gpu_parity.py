@@ -239,3 +239,31 @@ def test_error_paths():
         s1.jacobian_fd()
     assert ei.value.status == G.GAP_ESTATE
     s1.close()
+
+
+def test_split_forces_and_rebuilt_field():
+    """Pressure / shear split with the axial force and torque, and the full field with its
+    boundary rows, against the oracle (axial sliding V != 0 so that every shear term is on)."""
+    case = synth.textured_case(80, 36, 4)
+    log(f"case: {case.label}, 9 conditions, split forces and rebuilt field")
+    V = 0.15
+    gap, tex = gap_of(case, V=V), texture_of(case)
+    s = JointGapSolver(case.R, case.c, case.L, case.mu, case.U, V, case.p_in, case.p_out, case.n_theta, case.n_axial,
+                       dimples=(case.dimple_theta, case.dimple_z, case.dimple_radius, case.dimple_depth), max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    s.solve(omega=case.omega, eps=EPS_PARITY)
+    Fs = s.integrate_split().cpu().numpy()
+    F = s.integrate().cpu().numpy()
+    full = s.full_pressure().cpu().numpy()
+    full_c = s.full_pressure(G.GAP_CAVITATION_CLAMP, 0.0).cpu().numpy()
+    p_gpu = s.pressure().reshape(9, -1).cpu().numpy()
+    s.close()
+    for k, (ek, edk) in enumerate(oracle.conditions(case.e, case.edot, case.delta)):
+        _, p_ref = oracle.condition_forces(gap, ek, edk, tex)
+        ref = oracle.forces_split_for_condition(gap, ek, p_ref, tex)
+        for sl in (slice(0, 2), slice(2, 4), slice(4, 6), slice(6, 8)):
+            assert np.linalg.norm(Fs[k, sl] - ref[sl]) <= F_TOL * np.linalg.norm(ref[sl]), (k, sl)
+        assert abs(Fs[k, 8] - ref[8]) <= F_TOL * abs(ref[8]) and abs(Fs[k, 9] - ref[9]) <= F_TOL * abs(ref[9])
+        np.testing.assert_allclose(Fs[k, 0:4] + Fs[k, 4:8], F[k], rtol=1e-12, atol=1e-12 * np.abs(F[k]).max())
+        np.testing.assert_array_equal(full[k], oracle.rebuild_field(gap, p_gpu[k]))
+        np.testing.assert_array_equal(full_c[k], oracle.rebuild_field(gap, p_gpu[k], "clamp", 0.0))

@@ -93,3 +93,55 @@ def test_circumferential_gradient_shear():
     expect = -P * np.pi * gap.R * gap.L - 0.5 * h0 * P * np.sin(dth) / dth * np.pi * gap.L
     assert F[1] == pytest.approx(expect, rel=1e-13)
     assert abs(F[1] + P * np.pi * gap.R * gap.L) > 1e3 * 1e-13 * abs(expect)   # term is visible
+
+
+def test_split_couette_torque_and_no_pressure_force():
+    """Concentric gap at uniform pressure with the wall sliding at U: tau_theta = mu U / c,
+    so the torque is R mu U / c times the area 2 pi R L; the pressure part of (Fx, Fy, Mx, My)
+    vanishes and there is no axial shear."""
+    g = oracle.Gap(0.01, 2e-5, 0.04, 0.04, 1.7, 0.0, 3e6, 3e6, 48, 20)
+    p = np.full((20, 48), 3e6)
+    h = np.full((20, 48), g.c)
+    Fs = oracle.force_moment_split(g, p, h)
+    torque = g.R * g.mu * g.U / g.c * 2 * np.pi * g.R * g.L
+    assert abs(Fs[9] - torque) <= 1e-12 * torque
+    assert np.all(np.abs(Fs[:4]) <= 1e-9 * 3e6 * g.R * g.L) and abs(Fs[8]) <= 1e-12 * torque
+    np.testing.assert_allclose(Fs[4:8], 0.0, atol=1e-12 * torque)
+
+
+def test_split_axial_poiseuille_force():
+    """Concentric gap with the linear axial profile (no sliding): dp/dz = (p_out - p_in)/L on
+    every row (the end rows see the Dirichlet face 1.5 dz away), tau_z = -(c/2) dp/dz, so the
+    axial force is -(c/2) (p_out - p_in)/L times 2 pi R L; adding V adds mu V / c per area."""
+    for V in (0.0, 0.3):
+        g = oracle.Gap(0.01, 2e-5, 0.04, 0.04, 0.0, V, 8e6, 1e5, 32, 25)
+        _, z, _, _ = oracle.cell_centers(g)
+        p = np.repeat((g.p_in + (g.p_out - g.p_in) * z / g.L)[:, None], 32, axis=1)
+        Fs = oracle.force_moment_split(g, p, np.full((25, 32), g.c))
+        area = 2 * np.pi * g.R * g.L
+        fz = (-0.5 * g.c * (g.p_out - g.p_in) / g.L + g.mu * V / g.c) * area
+        assert abs(Fs[8] - fz) <= 1e-12 * abs(fz)
+        assert abs(Fs[9]) <= 1e-12 * abs(fz)
+
+
+def test_split_parts_add_up_to_the_total():
+    case = synth.textured_case(40, 18, 2)
+    from conftest import texture_of
+    gap, tex = gap_of(case), texture_of(case)
+    F, p = oracle.condition_forces(gap, case.e, case.edot, tex)
+    Fs = oracle.forces_split_for_condition(gap, case.e, p, tex)
+    np.testing.assert_allclose(Fs[0:4] + Fs[4:8], F, rtol=1e-12, atol=1e-12 * np.max(np.abs(F)))
+
+
+def test_rebuilt_field_is_linear_for_the_linear_profile():
+    """The rebuilt field of the linear axial solution is linear in z through both boundary
+    rows (at z = 0 and z = L, half a cell beyond the end centres)."""
+    g = oracle.Gap(0.01, 2e-5, 0.04, 0.04, 0.0, 0.0, 5e6, 2e5, 16, 10)
+    _, z, _, dz = oracle.cell_centers(g)
+    p = np.repeat((g.p_in + (g.p_out - g.p_in) * z / g.L)[:, None], 16, axis=1)
+    full = oracle.rebuild_field(g, p)
+    zz = np.concatenate([[0.0], z, [g.L]])
+    np.testing.assert_allclose(full, np.repeat((g.p_in + (g.p_out - g.p_in) * zz / g.L)[:, None], 16, axis=1),
+                               rtol=1e-13)
+    clamped = oracle.rebuild_field(g, p - 4e6, cavitation="clamp", p_cav=0.0)
+    assert clamped.min() >= 0.0 and clamped[0, 0] == g.p_in
