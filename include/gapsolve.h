@@ -116,12 +116,16 @@ typedef struct {
 } gap_solver_opts;
 
 /* Result of a solve.  iterations counts completed Table 1 iterations (SpMV + update);
- * rel_residual is the recurrence ||r_G|| / ||S_G|| at exit; rel_residual_cond[k] the
- * same per condition; status repeats the return code. */
+ * rel_residual is the recurrence ||r_G|| / ||S_G|| at exit (the quantity the stopping test
+ * of Eq 3.9 reads); rel_residual_cond[k] the same per condition; true_rel_residual is
+ * ||S_G - A_G p|| / ||S_G|| recomputed from the returned p once at exit (solve_joint_pcg
+ * only; -1 where not computed: batched and adjoint solves); status repeats the return code. */
 typedef struct {
     int32_t iterations, status, n_cond, reserved;
     double rel_residual;
     double rel_residual_cond[GAP_MAX_COND];
+    double true_rel_residual;
+    double true_rel_residual_cond[GAP_MAX_COND];
 } gap_solve_info;
 
 /* Fill *opts with the defaults: omega 1.6, eps 1e-10, max_iter 100000, ASSOR II,

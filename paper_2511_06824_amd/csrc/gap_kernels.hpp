@@ -231,6 +231,45 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_forces_finalize(ChunkMap cm, int 
         }
 }
 
+// ||S - A p||^2 and ||S||^2 per chunk of rows, the true residual of a returned solution.
+__global__ __launch_bounds__(GAP_BLOCK) void k_true_residual(GeomDev g, CondDev cd, ChunkMap cm,
+                                                             const double* __restrict__ kx_all,
+                                                             const double* __restrict__ kz_all,
+                                                             const double* __restrict__ S_all,
+                                                             const double* __restrict__ p_all, double* __restrict__ partial)
+{
+    int c, j0, j1;
+    chunk_rows(cm, g.nz, blockIdx.x, c, j0, j1);
+    const int nt = g.nt, nz = g.nz;
+    const size_t n = (size_t)nt * nz;
+    const int op = cd.op[c];
+    const double* kx = kx_all + (size_t)op * n;
+    const double* kz = kz_all + (size_t)op * (n + nt);
+    const double* S = S_all + (size_t)c * n;
+    const double* p = p_all + (size_t)c * n;
+    double acc[2] = {0.0, 0.0};
+    for (int j = j0; j < j1; ++j) {
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            const size_t gi = (size_t)j * nt + i;
+            const int iw = i ? i - 1 : nt - 1;
+            const int ie = (i + 1 < nt) ? i + 1 : 0;
+            const double kE = kx[gi], kW = kx[(size_t)j * nt + iw];
+            const double kS = kz[gi], kN = kz[gi + nt];
+            double Ap = (((kE + kW) + kS) + kN) * p[gi] - kE * p[(size_t)j * nt + ie] - kW * p[(size_t)j * nt + iw];
+            if (j > 0) Ap -= kS * p[gi - nt];
+            if (j < nz - 1) Ap -= kN * p[gi + nt];
+            const double r = S[gi] - Ap;
+            acc[0] += r * r;
+            acc[1] += S[gi] * S[gi];
+        }
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = acc[0];
+        partial[cm.total + blockIdx.x] = acc[1];
+    }
+}
+
 // GMAF step II: the full field with its boundary rows, out[c][j][i] for j = 0 .. n_axial + 1
 // (row 0: p_in at z = 0, rows 1 .. n_axial: the cell centres after the cavitation rule, last
 // row: p_out at z = L).

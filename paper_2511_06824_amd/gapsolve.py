@@ -60,7 +60,9 @@ class gap_solver_opts(ctypes.Structure):
 class gap_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32), ("n_cond", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("rel_residual_cond", ctypes.c_double * GAP_MAX_COND)]
+                ("rel_residual_cond", ctypes.c_double * GAP_MAX_COND),
+                ("true_rel_residual", ctypes.c_double),
+                ("true_rel_residual_cond", ctypes.c_double * GAP_MAX_COND)]
 
 
 class gap_pcg_config(ctypes.Structure):

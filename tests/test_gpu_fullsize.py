@@ -75,9 +75,11 @@ def test_joint_textured_2048x1024_full_size():
         A = oracle.stencil_matrix(gap, kx, kz)
         Sf = S.ravel()
         res = np.linalg.norm(Sf - A @ p[k]) / np.linalg.norm(Sf)
-        log(f"  condition {k}: sampled kx {ex:.1e} kz {ez:.1e} S {es:.1e}; true residual {res:.2e}")
+        log(f"  condition {k}: sampled kx {ex:.1e} kz {ez:.1e} S {es:.1e}; true residual {res:.2e} "
+            f"(library {info.true_rel_residual_cond[k]:.2e})")
         assert ex <= ENTRY_TOL and ez <= ENTRY_TOL and es <= S_TOL
         assert res <= RES_TOL
+        assert abs(info.true_rel_residual_cond[k] - res) <= 1e-4 * res    # same system, other summation order
 
     for k in (0, 2, 6):
         F_r = oracle.forces_for_condition(gap, conds[k][0], p[k], tex)

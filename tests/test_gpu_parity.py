@@ -267,3 +267,33 @@ def test_split_forces_and_rebuilt_field():
         np.testing.assert_allclose(Fs[k, 0:4] + Fs[k, 4:8], F[k], rtol=1e-12, atol=1e-12 * np.abs(F[k]).max())
         np.testing.assert_array_equal(full[k], oracle.rebuild_field(gap, p_gpu[k]))
         np.testing.assert_array_equal(full_c[k], oracle.rebuild_field(gap, p_gpu[k], "clamp", 0.0))
+
+
+def test_true_residual_reported_at_exit():
+    """The true residual ||S - A p|| / ||S|| the library recomputes at exit, against the same
+    quantity on the CPU: with the library's own assembled system (read back) to 1e-4 (at a
+    residual of 1e-10 the subtraction S - A p cancels, so the summation order alone moves the
+    norm by ~1e-6), and with the oracle's system to 5e-2 (entry differences of 1e-13..1e-12
+    between the two assemblies move a 1e-10 residual by up to ~1e-2)."""
+    case = synth.textured_case(70, 30, 8)
+    log(f"case: {case.label}, true residual at exit")
+    gap, tex = gap_of(case), texture_of(case)
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    p, info = s.solve(omega=case.omega, eps=1e-10)
+    p = p.reshape(9, -1).cpu().numpy()
+    systems = [[t.cpu().numpy() for t in s.read_system(k)] for k in range(9)]
+    s.close()
+    rr = ss = 0.0
+    for k, (ek, edk) in enumerate(oracle.conditions(case.e, case.edot, case.delta)):
+        kx, kz, Sg = systems[k]
+        r = Sg.ravel() - oracle.stencil_matrix(gap, kx, kz) @ p[k]
+        rel = np.linalg.norm(r) / np.linalg.norm(Sg)
+        assert abs(info.true_rel_residual_cond[k] - rel) <= 1e-4 * rel, (k, info.true_rel_residual_cond[k], rel)
+        A, S = oracle.assemble(gap, ek, edk, tex)
+        rel_o = np.linalg.norm(S - A @ p[k]) / np.linalg.norm(S)
+        assert abs(info.true_rel_residual_cond[k] - rel_o) <= 5e-2 * rel_o
+        rr += r @ r
+        ss += Sg.ravel() @ Sg.ravel()
+    assert abs(info.true_rel_residual - np.sqrt(rr / ss)) <= 1e-4 * np.sqrt(rr / ss)
+    assert info.true_rel_residual <= 10 * info.rel_residual      # the recurrence tracks it
