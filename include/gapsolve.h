@@ -366,9 +366,11 @@ gap_status gap_batch_destroy(gap_batch_t batch);
 /* Add a request: `grid` must be assembled (its conditions form the joint system), p is its
  * device solution array (n_cond * n doubles; the initial guess if opts->warm_start), opts as
  * for solve_joint_pcg (check_every and graph are ignored here).  Computes the initial
- * residual on `stream` and returns the request id in *id.  The grid, p and opts must stay
- * unchanged until the request is removed.  Errors: GAP_EINVAL, GAP_ESTATE, GAP_EBUDGET (all
- * 128 slots in use), GAP_ENOMEM, GAP_EDEVICE. */
+ * residual on `stream` and returns the request id in *id.  The grid lends its Krylov
+ * buffers and device record to the batch: until gap_batch_remove, assembling, solving,
+ * tuning, re-configuring or destroying it returns GAP_ESTATE, and p and opts must stay
+ * unchanged.  A grid is in at most one batch (GAP_EINVAL otherwise).  Errors: GAP_EINVAL,
+ * GAP_ESTATE, GAP_EBUDGET (all 128 slots in use), GAP_ENOMEM, GAP_EDEVICE. */
 gap_status gap_batch_add(gap_batch_t batch, gap_grid_t grid, const gap_solver_opts *opts, double *p, int32_t *id,
                          void *stream);
 

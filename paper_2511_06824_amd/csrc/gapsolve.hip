@@ -45,6 +45,13 @@ gap_status fail(gap_status s, const char* fmt, ...)
 
 bool is_finite(double x) { return std::isfinite(x); }
 
+// A handle in a batch lends its Krylov buffers and device record to the batch: no other use
+// until gap_batch_remove.
+#define GAP_NOT_IN_BATCH(g, what)                                                                  \
+    do {                                                                                           \
+        if ((g)->batch) return fail(GAP_ESTATE, "%s on a grid that is in a batch (gap_batch_remove it first)", what); \
+    } while (0)
+
 constexpr int kTargetChunks = 2048;
 constexpr int kMaxThetaCells = 2048;
 constexpr int kMaxAxialCells = 65536;
@@ -263,6 +270,7 @@ struct gap_grid_s {
     double *adj_rhs = nullptr, *adj_lam = nullptr;           // adjoint right-hand sides and solutions
     double *adj_part = nullptr;                              // sensitivity partials
     double *step_buf = nullptr;                              // general iteration: F (9 x 4) and J (4 x 8)
+    gap_batch_s* batch = nullptr;                            // the batch this handle is in (its buffers are lent)
     int cus = 256;                                           // compute units of the device
     PcgShape shape_a{}, shape_b{};                           // PCG kernel shapes in use (A; B and init)
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
@@ -793,6 +801,7 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
 gap_status destroy_gap_grid(gap_grid_t g)
 {
     if (!g) return GAP_OK;
+    GAP_NOT_IN_BATCH(g, "destroy_gap_grid");
     (void)hipDeviceSynchronize();
     release(g);
     return GAP_OK;
@@ -802,6 +811,7 @@ gap_status assemble_joint_system(gap_grid_t g, const double e[4], const double e
                                  int32_t n_cond, void* stream)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "assemble_joint_system");
     if (!e || !edot) return fail(GAP_EINVAL, "e and edot must be non-NULL");
     if (n_cond != 1 && n_cond != GAP_MAX_COND) return fail(GAP_EINVAL, "n_cond must be 1 or 9");
     if (n_cond > g->max_cond) return fail(GAP_EINVAL, "n_cond = %d exceeds max_cond = %d", n_cond, g->max_cond);
@@ -848,6 +858,7 @@ gap_status assemble_joint_system(gap_grid_t g, const double e[4], const double e
 gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, gap_solve_info* info, void* stream)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "solve_joint_pcg");
     if (!p) return fail(GAP_EINVAL, "p is NULL");
     gap_status vs = validate_opts(o);
     if (vs != GAP_OK) return vs;
@@ -902,6 +913,7 @@ gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double
                             const double* w, double* J, gap_solve_info* info, void* stream)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "jacobian_adjoint");
     if (!p0 || !J) return fail(GAP_EINVAL, "p0 and J must be non-NULL");
     gap_status vs = validate_opts(o);
     if (vs != GAP_OK) return vs;
@@ -968,6 +980,7 @@ gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0
                               gap_solve_info* info, void* stream)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "solve_with_adjoint");
     if (!p0 || !J) return fail(GAP_EINVAL, "p0 and J must be non-NULL");
     gap_status vs = validate_opts(o);
     if (vs != GAP_OK) return vs;
@@ -1035,6 +1048,7 @@ gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0
 gap_status set_operating_point(gap_grid_t g, double U, double V, double p_in, double p_out)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "set_operating_point");
     if (!is_finite(U) || !is_finite(V) || !is_finite(p_in) || !is_finite(p_out))
         return fail(GAP_EINVAL, "U, V, p_in and p_out must be finite");
     g->geom.U = g->gd.U = U;
@@ -1050,6 +1064,7 @@ gap_status general_iteration_step(gap_grid_t g, const gap_solver_opts* o, const 
                                   gap_solve_info* info, void* stream)
 {
     if (!g || !o || !prm || !p || !e || !edot || !F) return fail(GAP_EINVAL, "grid, opts, prm, p, e, edot and F must be non-NULL");
+    GAP_NOT_IN_BATCH(g, "general_iteration_step");
     if (!is_finite(prm->dt) || !(prm->dt > 0.0)) return fail(GAP_EINVAL, "dt must be finite and > 0");
     for (int k = 0; k < 4; ++k)
         if (!is_finite(prm->edot_prev[k]) || !is_finite(prm->F_ext[k])) return fail(GAP_EINVAL, "edot_prev and F_ext must be finite");
@@ -1274,6 +1289,7 @@ gap_status tune_run(gap_grid_t g, const gap_solver_opts* t, double* p, void* str
 gap_status gap_set_pcg_config(gap_grid_t g, const gap_pcg_config* cfg)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "gap_set_pcg_config");
     PcgShape sa = pcg_candidates(g->nt)[0], sb = sa;
     int wa = 0, wb = 0;
     if (cfg) {
@@ -1298,6 +1314,7 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
                         double* us_per_iteration, void* stream)
 {
     if (!g || !o || !p) return fail(GAP_EINVAL, "grid, opts and p must be non-NULL");
+    GAP_NOT_IN_BATCH(g, "gap_tune_pcg");
     if (iterations < 2 || iterations > 10000) return fail(GAP_EINVAL, "iterations must lie in [2, 10000]");
     gap_status vs = validate_opts(o);
     if (vs != GAP_OK) return vs;
@@ -1311,6 +1328,8 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     t.warm_start = 0;
     t.strategy = GAP_STRATEGY_SYNC;
     const bool timing = g->timing;
+    const PcgShape orig_a = g->shape_a, orig_b = g->shape_b;    // restored if tuning fails
+    const int orig_wa = g->wg_a, orig_wb = g->wg_b;
     struct Pick {
         PcgShape sh;
         int wg = 0;
@@ -1350,8 +1369,10 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
         }
     }
     g->timing = timing;
-    if (result != GAP_OK) return result;
-    if (!pa.have || !pb.have) return fail(GAP_EDEVICE, "no kernel shape could be prepared");
+    if (result != GAP_OK || !pa.have || !pb.have) {
+        (void)use_shape(g, orig_a, orig_b, orig_wa, orig_wb);
+        return result != GAP_OK ? result : fail(GAP_EDEVICE, "no kernel shape could be prepared");
+    }
     // keep the default unless the best is at least 1 % faster (stable choice on near-ties)
     if (da.have && da.us <= 1.01 * pa.us) pa = da;
     if (db.have && db.us <= 1.01 * pb.us) pb = db;
@@ -1506,6 +1527,7 @@ gap_status gap_batch_destroy(gap_batch_t b)
 {
     if (!b) return GAP_OK;
     (void)hipDeviceSynchronize();
+    for (auto& r : b->reqs) r.g->batch = nullptr;        // the handles are free again
     batch_release(b);
     return GAP_OK;
 }
@@ -1516,8 +1538,7 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     gap_status vs = validate_opts(o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "gap_batch_add needs an assembled grid");
-    for (const auto& r : b->reqs)
-        if (r.g == g) return fail(GAP_EINVAL, "this grid is already in the batch");
+    if (g->batch) return fail(GAP_EINVAL, "this grid is already in a batch");
     int slot = -1;
     std::vector<bool> used(gap_batch_s::kCap, false);
     for (const auto& r : b->reqs) used[r.slot] = true;
@@ -1562,6 +1583,7 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     r.id = b->next_id++;
     r.slot = slot;
     r.g = g;
+    g->batch = b;
     b->reqs.push_back(r);
     b->dirty = true;
     *id = r.id;
@@ -1691,6 +1713,7 @@ gap_status gap_batch_remove(gap_batch_t b, int32_t id, gap_solve_info* info, voi
     std::memset(b->reqs_host + it->slot, 0, sizeof(PcgDev));
     HIPCHK(hipMemcpyAsync(b->reqs_dev + it->slot, b->reqs_host + it->slot, sizeof(PcgDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
+    it->g->batch = nullptr;
     b->reqs.erase(it);
     b->dirty = true;
     return GAP_OK;

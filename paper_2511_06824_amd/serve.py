@@ -156,10 +156,11 @@ class BatchBackend:
         return not self.live
 
     def close(self):
+        self.G.gap_batch_destroy(self.batch)       # releases the grids still in the batch
+        self.batch = None
         for s, _, _ in self.live.values():
             s.close()
         self.live.clear()
-        self.G.gap_batch_destroy(self.batch)
 
 
 class GapServer:

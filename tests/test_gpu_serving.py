@@ -154,3 +154,33 @@ def test_server_with_work_cap_drains_a_mixed_stream():
     assert sorted(r.rid for r in done) == list(range(5)) and all(r.status == G.GAP_OK for r in done)
     by = {r.rid: r for r in done}
     assert by[0].finished <= by[2].finished                    # the two large ones in order
+
+
+def test_a_grid_in_a_batch_is_lent_to_it():
+    """While a grid is in a batch, using it elsewhere is refused (its Krylov buffers and
+    device record belong to the batch); after removal it works again."""
+    log("case: grid lent to a batch")
+    c = synth.smooth_case(64, 32, 9)
+    b = G.gap_batch_create()
+    b2 = G.gap_batch_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    s = JointGapSolver.from_case(c, max_cond=9)
+    s.assemble(c.e, c.edot, c.delta, 9)
+    opts = s.options(omega=c.omega, eps=c.eps)
+    bid = G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
+    for call in (lambda: s.solve(opts), lambda: s.assemble(c.e, c.edot, c.delta, 9), lambda: s.tune(opts),
+                 lambda: s.set_pcg_config(), lambda: G.destroy_gap_grid(s.handle)):
+        with pytest.raises(G.GapError) as ei:
+            call()
+        assert ei.value.status == G.GAP_ESTATE
+    with pytest.raises(G.GapError) as ei:
+        G.gap_batch_add(b2, s.handle, opts, s.p.data_ptr(), stream)
+    assert ei.value.status == G.GAP_EINVAL
+    while not G.gap_batch_poll(b):
+        G.gap_batch_step(b, 16, True, stream)
+    G.gap_batch_remove(b, bid, stream)
+    _, info = s.solve(opts)                                   # free again
+    assert info.status == G.GAP_OK
+    s.close()
+    G.gap_batch_destroy(b)
+    G.gap_batch_destroy(b2)
