@@ -113,7 +113,7 @@ def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.8, 1.2)):
     work_cap = 9 * 2048 * 1024               # one joint 2048 x 1024 system per step
 
     def batched(reqs):
-        be = BatchBackend(iterations_per_step=16)
+        be = BatchBackend(iterations_per_step=32)
         done = GapServer(be, budget_bytes=budget, work_cap=work_cap).run(reqs)
         be.close()
         return done
@@ -208,6 +208,8 @@ def run_adjoint_vs_fd(torch, JointGapSolver, dev):
     case = synth.make_case("adjoint_textured_1024x512", 0)
     s = JointGapSolver.from_case(case, max_cond=9, device=dev)
     opts = s.options(omega=case.omega, eps=case.eps)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    s.tune(opts, iterations=20)                  # one configuration for both paths
 
     def fd():
         s.assemble(case.e, case.edot, case.delta, 9)
@@ -257,7 +259,7 @@ def run_adjoint_vs_fd(torch, JointGapSolver, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="joint_textured_2048x1024")
     ap.add_argument("--seed", type=int, default=0)
@@ -326,10 +328,11 @@ def main():
     stream = torch.cuda.current_stream(dev)
     G.gap_kernel_timing(solver.handle, 1)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    iters, true_rel = [], []
+    iters, true_rel, step_s = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
+        ts = time.perf_counter()
         ev[s][0].record(stream)
         solver.assemble(case.e, case.edot, case.delta, 9)
         ev[s][1].record(stream)
@@ -339,6 +342,8 @@ def main():
         solver.jacobian_fd()
         iters.append(info.iterations)
         true_rel.append(info.true_rel_residual)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
         print(f"bench: step {s} iterations {info.iterations} rel {info.rel_residual:.2e} "
               f"true {info.true_rel_residual:.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -404,6 +409,7 @@ def main():
                    "n_cond": n_cond, "dimples": case.n_dimples, "omega": case.omega, "eps": case.eps,
                    "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "seed": args.seed},
         "gdof_iter_per_s": round(gdof, 3), "iterations": mean_iters,
+        "median_ms_per_step": round(1e3 * sorted(step_s)[len(step_s) // 2], 3),
         "true_rel_residual": max(true_rel),
         "graph_solves_per_s": round(graph_solves_per_s, 5),
         "pcg_config": solver.pcg_config, "tune": tune, "per_condition_scalars": per_cond,

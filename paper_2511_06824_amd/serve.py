@@ -94,7 +94,7 @@ class WallClock:
 class BatchBackend:
     """Drives the HIP library: one JointGapSolver handle per request, one gap_batch."""
 
-    def __init__(self, device="cuda:0", iterations_per_step=16, use_graph=True, keep_pressure=False):
+    def __init__(self, device="cuda:0", iterations_per_step=32, use_graph=True, keep_pressure=False):
         import torch
         from . import gapsolve as G
         from .solver import JointGapSolver
