@@ -27,8 +27,10 @@ HBM_PEAK_GBS = 8000.0
 def kernel_bytes(n, n_cond, n_op):
     """Algorithmic HBM bytes of one launch of each iteration kernel: every vector operand is
     read or written once per condition-DOF; the face conductances (kx, kz: 16 B per
-    operator-DOF) once per distinct operator."""
-    vec = {"k_pcg_a": 3, "k_pcg_b": 6}
+    operator-DOF) once per distinct operator.  k_pcg_a reads z, u_prev and writes u; k_pcg_b
+    reads u, p, r and writes p, r, z; the one-launch k_pcg_f reads z, u_prev, p, r and writes
+    u, p, r, z."""
+    vec = {"k_pcg_a": 3, "k_pcg_b": 6, "k_pcg_f": 8}
     return {k: 8 * v * n * n_cond + 16 * n * n_op for k, v in vec.items()}
 
 
@@ -65,7 +67,7 @@ def kernel_source_digest():
     """sha256 of the PCG kernel sources: counter figures taken for other sources are stale."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("gap_pcg.hpp", "gap_device.hpp"):
+    for f in ("gap_pcg.hpp", "gap_pcg1.hpp", "gap_device.hpp"):
         with open(os.path.join(ROOT, "paper_2511_06824_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -270,6 +272,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default PCG kernel configuration")
     ap.add_argument("--no-study", action="store_true", help="skip the preconditioner / omega study")
     ap.add_argument("--no-dynamics", action="store_true", help="skip the general-iteration time steps")
+    ap.add_argument("--no-two-launch", action="store_true", help="skip the two-launch iteration comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
@@ -324,6 +327,24 @@ def main():
     per_cond = {"solves_per_s": round(1.0 / (time.perf_counter() - tp0), 5), "iterations": info_pc.iterations,
                 "scalars": "per condition, synchronized stopping test (Eq 3.9)"}
     print(f"bench: per-condition scalars {per_cond}", file=sys.stderr, flush=True)
+
+    # the two-launch iteration (Table 1 as printed), tuned on its own, graph-replayed
+    two_launch = None
+    if not args.no_two_launch:
+        opts2 = solver.options(omega=case.omega, eps=case.eps, iteration=G.GAP_ITERATION_TWO_LAUNCH)
+        solver.assemble(case.e, case.edot, case.delta, 9)
+        cfg2, us2 = solver.tune(opts2, iterations=20) if not args.no_tune else (solver.pcg_config, None)
+        solver.step(case.e, case.edot, case.delta, opts2)
+        torch.cuda.synchronize()
+        t20 = time.perf_counter()
+        for _ in range(2):
+            _, _, info2 = solver.step(case.e, case.edot, case.delta, opts2)
+        torch.cuda.synchronize()
+        two_launch = {"graph_solves_per_s": round(2.0 / (time.perf_counter() - t20), 5),
+                      "iterations": info2.iterations, "tuned_us_per_iteration": us2 and round(us2, 2),
+                      "kernels": "k_pcg_a + k_pcg_b",
+                      "config": {k: v for k, v in cfg2.items() if k[-1] in "ab"}}
+        print(f"bench: two-launch iteration {two_launch}", file=sys.stderr, flush=True)
 
     stream = torch.cuda.current_stream(dev)
     G.gap_kernel_timing(solver.handle, 1)
@@ -407,12 +428,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_theta": case.n_theta, "n_axial": case.n_axial,
                    "n_cond": n_cond, "dimples": case.n_dimples, "omega": case.omega, "eps": case.eps,
-                   "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "seed": args.seed},
+                   "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "iteration": "one launch",
+                   "seed": args.seed},
         "gdof_iter_per_s": round(gdof, 3), "iterations": mean_iters,
         "median_ms_per_step": round(1e3 * sorted(step_s)[len(step_s) // 2], 3),
         "true_rel_residual": max(true_rel),
         "graph_solves_per_s": round(graph_solves_per_s, 5),
         "pcg_config": solver.pcg_config, "tune": tune, "per_condition_scalars": per_cond,
+        "two_launch_iteration": two_launch,
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},

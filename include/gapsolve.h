@@ -63,6 +63,7 @@ enum { GAP_PRECOND_JACOBI = 0, GAP_PRECOND_ASSOR1 = 1, GAP_PRECOND_ASSOR2 = 2 };
 enum { GAP_SCALARS_GLOBAL = 0, GAP_SCALARS_PER_COND = 1 };
 enum { GAP_STRATEGY_SYNC = 0, GAP_STRATEGY_ASYNC = 1 };
 enum { GAP_CAVITATION_NONE = 0, GAP_CAVITATION_CLAMP = 1 };
+enum { GAP_ITERATION_TWO_LAUNCH = 0, GAP_ITERATION_ONE_LAUNCH = 1 };
 #define GAP_MAX_COND 9
 
 /* Gap geometry, fluid and boundary data (Eq 2.3; Table 8 lists the paper's pump).
@@ -109,10 +110,18 @@ typedef struct {
  *   check_every  iterations between host reads of the device convergence flag (0: 32);
  *                launches after convergence return at once, so the count is exact
  *   graph        nonzero: each block of check_every iterations is captured once into a
- *                hipGraph and replayed; zero: plain launches                           */
+ *                hipGraph and replayed; zero: plain launches
+ *   iteration    GAP_ITERATION_TWO_LAUNCH: Table 1 as printed, two launches per iteration
+ *                (u and u^T A u; then alpha and the updates).  GAP_ITERATION_ONE_LAUNCH:
+ *                one launch per iteration, with u^T A u = z^T A z + 2 beta z^T A u_prev +
+ *                beta^2 u_prev^T A u_prev from sums the previous launch forms (A is
+ *                symmetric).  The iterates agree up to rounding.  Batched solves
+ *                (gap_batch_*) always use the two-launch iteration.                    */
 typedef struct {
     double omega, eps;
     int32_t max_iter, precond, neumann, scalars, warm_start, check_every, graph, strategy;
+    int32_t iteration;
+    int32_t reserved;
 } gap_solver_opts;
 
 /* Result of a solve.  iterations counts completed Table 1 iterations (SpMV + update);
@@ -129,8 +138,8 @@ typedef struct {
 } gap_solve_info;
 
 /* Fill *opts with the defaults: omega 1.6, eps 1e-10, max_iter 100000, ASSOR II,
- * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1, SYNC strategy.  Returns
- * GAP_EINVAL if NULL. */
+ * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1, SYNC strategy, one-launch
+ * iteration.  Returns GAP_EINVAL if NULL. */
 gap_status gap_default_opts(gap_solver_opts *opts);
 
 /* Create a handle for one gap (Eq 2.3 geometry, Sec 2.1 grid) that can hold up to
@@ -297,7 +306,8 @@ gap_status gap_read_system(gap_grid_t grid, int32_t k, double *kx, double *kz, d
 enum {
     GAP_KERNEL_PCG_A = 0,  /* u = z + beta u; u^T A u; beta and the stopping test (Table 1 steps 9, 3, 6) */
     GAP_KERNEL_PCG_B = 1,  /* alpha; p, r update; z = M^-1 r (ASSOR II sweeps); r^T z, r^T r (steps 4-8) */
-    GAP_KERNEL_COUNT = 2
+    GAP_KERNEL_PCG_ONE = 2, /* one-launch iteration: all of steps 3-9 */
+    GAP_KERNEL_COUNT = 3
 };
 gap_status gap_kernel_timing(gap_grid_t grid, int32_t enable);
 gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, double *total_ms);
@@ -306,8 +316,9 @@ gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, 
  * A workgroup of `threads` threads owns whole rings of one condition (thread t handles the
  * columns t, t + threads, ...; threads * cols_per_thread >= n_theta) and marches over a
  * chunk of rows; the rows of every condition are cut into chunks so that one launch places
- * wg_per_cu x (compute units) workgroups.  The A kernel (steps 9, 3 of Table 1) and the B
- * kernels (steps 4-8, and the initial residual) are configured separately.  occupancy_*
+ * wg_per_cu x (compute units) workgroups.  The A kernel (steps 9, 3 of Table 1), the B
+ * kernels (steps 4-8, and the initial residual) and the one-launch kernel (F: all steps, and
+ * its initial residual) are configured separately.  occupancy_*
  * report how many workgroups of the kernel fit on one CU with its shape (output only).
  * Results depend on the configuration only through the summation order of the reductions. */
 typedef struct {
@@ -319,6 +330,10 @@ typedef struct {
     int32_t cols_per_thread_b;
     int32_t wg_per_cu_b;
     int32_t occupancy_b;        /* output */
+    int32_t threads_f;          /* F: as for A */
+    int32_t cols_per_thread_f;
+    int32_t wg_per_cu_f;
+    int32_t occupancy_f;        /* output */
 } gap_pcg_config;
 
 /* Read the configuration the next solve_joint_pcg of this handle uses.
@@ -326,7 +341,7 @@ typedef struct {
 gap_status gap_get_pcg_config(gap_grid_t grid, gap_pcg_config *cfg);
 
 /* Select a configuration (cfg NULL: the default, the first candidate shape for n_theta with
- * as many workgroups per CU as fit, for both kernels).  Accepted shapes: threads x
+ * as many workgroups per CU as fit, for every kernel).  Accepted shapes: threads x
  * cols_per_thread one of 64x1, 128x1, 128x2, 256x1, 256x2, 256x4, 512x1, 512x2, 512x4,
  * 1024x1, 1024x2 with n_theta <= threads * cols_per_thread < 2 n_theta + 64; wg_per_cu in
  * [1, 8].  Errors: GAP_EINVAL (unsupported shape or range), GAP_EDEVICE. */
@@ -335,9 +350,10 @@ gap_status gap_set_pcg_config(gap_grid_t grid, const gap_pcg_config *cfg);
 /* Autotuner: time `iterations` PCG iterations of the assembled system (options of opts, run
  * from p = 0 without a stopping test) for every candidate shape of n_theta and every
  * wg_per_cu up to that shape's occupancy, with HIP events around each kernel launch; keep,
- * for A and for B separately, the fastest configuration (the default unless another is at
- * least 1 % faster), and return it in best (may be NULL) with the device time per iteration
- * of the chosen pair in us (may be NULL).  Overwrites p (caller device memory, n_cond * n
+ * for each kernel of the iteration kind opts->iteration selects (A and B, or F), the fastest
+ * configuration (the default unless another is at least 1 % faster), and return the whole
+ * configuration in best (may be NULL) with the device time per iteration of the chosen
+ * kernels in us (may be NULL).  Overwrites p (caller device memory, n_cond * n
  * doubles) and the handle's Krylov state; call solve_joint_pcg afterwards.  Stream-ordered on
  * stream, synchronizes it; resets the counters of gap_kernel_stats.  Errors: GAP_EINVAL (NULL
  * grid/opts/p, iterations outside [2, 10000]), GAP_ESTATE (nothing assembled), GAP_EDEVICE. */

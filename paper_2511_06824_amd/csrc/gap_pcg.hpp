@@ -41,6 +41,10 @@ struct PcgScalars {
     int active_b;               // conditions still iterating, bit c (written by A, read by B)
     double rel;                 // ||r_G|| / ||S_G|| of the last completed iteration
     double rel_cond[GAP_MAXC];  // per condition
+    // one-launch iteration (gap_pcg1.hpp): iteration index and per-condition r.z of the
+    // launch's own iteration, both by launch parity (read from [par], written to [par ^ 1])
+    int iter_f[2];
+    double gam[2][GAP_MAXC];
 };
 
 struct PcgDev {
@@ -54,11 +58,16 @@ struct PcgDev {
     double* r[2];               // residual, ping-pong by iteration parity
     double* u[2];               // search direction, ping-pong by iteration parity
     double* z;                  // preconditioned residual
+    double* zf[2];              // one-launch iteration: z by iteration parity (zf[0] == z)
     // partial sums, one slot per chunk: slot = c * chunks + k
     double* part_rz[2];         // r.z, parity of the iteration that consumes it as d_j
     double* part_rr;            // ||r||^2
     double* part_ss;            // ||S||^2 (init)
     double* part_uau;           // u^T A u
+    // one-launch iteration: partial sums by launch parity, 5 arrays each (r.z, r.r, z^T A z,
+    // z^T A u, u^T A u) of fstride slots
+    double* fpart[2];
+    int fstride;
     PcgScalars* sc;
     int op[GAP_MAXC];
     int nt, nz, n_cond;

@@ -12,6 +12,7 @@
 
 #include "gap_kernels.hpp"
 #include "gap_pcg.hpp"
+#include "gap_pcg1.hpp"
 #include "gap_adjoint.hpp"
 
 namespace {
@@ -97,9 +98,17 @@ std::vector<PcgShape> pcg_candidates(int nt)
     return {{1024, 2}, {512, 4}};        // n_theta <= 2048 (validated at create)
 }
 
-// Dynamic LDS of the A kernel (u row, double-buffered) and of the B kernels (u and y rows,
-// two rows of the first ASSOR sweep).
-size_t pcg_lds_bytes(int which, int nt) { return (size_t)(which == 0 ? 2 : 4) * nt * sizeof(double); }
+// Kernels of the PCG iteration, by the `which` argument of the launch helpers.
+enum { kPcgA = 0, kPcgB = 1, kPcgInit = 2, kPcgOne = 3, kPcgOneInit = 4 };
+
+// Dynamic LDS: A (u row, double-buffered); B and its init (u and y rows, two rows of the
+// first ASSOR sweep); the one-launch kernel and its init (those four, two z rows and a ring
+// of three rows of east-face conductances).
+size_t pcg_lds_bytes(int which, int nt)
+{
+    const int rows = which == kPcgA ? 2 : (which <= kPcgInit ? 4 : 9);
+    return (size_t)rows * nt * sizeof(double);
+}
 
 // Row chunks per condition: as many workgroups as the device holds at once (occupancy x CUs),
 // so that one launch runs in a single round; but at least kMinChunkCells cells per chunk and
@@ -163,8 +172,13 @@ std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
 template <int NT, int Q>
 const void* pcg_fn(int which)
 {
-    return which == 0 ? (const void*)k_pcg_a<NT, Q>
-         : which == 1 ? (const void*)k_pcg_b<NT, Q, false> : (const void*)k_pcg_b<NT, Q, true>;
+    switch (which) {
+    case kPcgA: return (const void*)k_pcg_a<NT, Q>;
+    case kPcgB: return (const void*)k_pcg_b<NT, Q, false>;
+    case kPcgInit: return (const void*)k_pcg_b<NT, Q, true>;
+    case kPcgOne: return (const void*)k_pcg_f<NT, Q, false>;
+    default: return (const void*)k_pcg_f<NT, Q, true>;
+    }
 }
 
 template <int NT, int Q>
@@ -172,7 +186,8 @@ hipError_t pcg_prepare_t(int which, int nt, int* occupancy)
 {
     const void* fn = pcg_fn<NT, Q>(which);
     const size_t lds = pcg_lds_bytes(which, nt);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pcg_lds_bytes(1, NT * Q));
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)pcg_lds_bytes(which, NT * Q));
     if (e != hipSuccess) return e;
     int nb = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds);
@@ -182,12 +197,17 @@ hipError_t pcg_prepare_t(int which, int nt, int* occupancy)
 }
 
 template <int NT, int Q>
-hipError_t launch_pcg_t(int which, int lds_nt, const PcgDev* reqs, const int* work, int blocks, hipStream_t st)
+hipError_t launch_pcg_t(int which, int lds_nt, const PcgDev* reqs, const int* work, int blocks, hipStream_t st,
+                        int par)
 {
     const size_t lds = pcg_lds_bytes(which, lds_nt);
-    if (which == 0) hipLaunchKernelGGL((k_pcg_a<NT, Q>), dim3(blocks), dim3(NT), lds, st, reqs, work);
-    else if (which == 1) hipLaunchKernelGGL((k_pcg_b<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, reqs, work);
-    else hipLaunchKernelGGL((k_pcg_b<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, reqs, work);
+    switch (which) {
+    case kPcgA: hipLaunchKernelGGL((k_pcg_a<NT, Q>), dim3(blocks), dim3(NT), lds, st, reqs, work); break;
+    case kPcgB: hipLaunchKernelGGL((k_pcg_b<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, reqs, work); break;
+    case kPcgInit: hipLaunchKernelGGL((k_pcg_b<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, reqs, work); break;
+    case kPcgOne: hipLaunchKernelGGL((k_pcg_f<NT, Q, false>), dim3(blocks), dim3(NT), lds, st, reqs, work, par); break;
+    default: hipLaunchKernelGGL((k_pcg_f<NT, Q, true>), dim3(blocks), dim3(NT), lds, st, reqs, work, 0); break;
+    }
     return hipGetLastError();
 }
 
@@ -202,30 +222,38 @@ hipError_t pcg_prepare(PcgShape sh, int which, int nt, int* occupancy)
     return hipErrorInvalidValue;
 }
 
-// which: 0 = A(j), 1 = B(j), 2 = initial residual.  lds_nt: the largest ring of the
-// requests in the launch; blocks = entries of the work table.
+// which: kPcgA = A(j), kPcgB = B(j), kPcgInit = initial residual of the two-launch
+// iteration; kPcgOne / kPcgOneInit the one-launch iteration and its initial residual, par
+// the launch parity.  lds_nt: the largest ring of the requests in the launch; blocks =
+// entries of the work table.
 hipError_t launch_pcg(PcgShape sh, int which, int lds_nt, const PcgDev* reqs, const int* work, int blocks,
-                      hipStream_t st)
+                      hipStream_t st, int par = 0)
 {
 #define GAP_SHAPE_CASE(nt_, q_) \
-    if (sh.NT == nt_ && sh.Q == q_) return launch_pcg_t<nt_, q_>(which, lds_nt, reqs, work, blocks, st);
+    if (sh.NT == nt_ && sh.Q == q_) return launch_pcg_t<nt_, q_>(which, lds_nt, reqs, work, blocks, st, par);
     GAP_PCG_SHAPES(GAP_SHAPE_CASE)
 #undef GAP_SHAPE_CASE
     return hipErrorInvalidValue;
 }
 
-// Capture `iters` iterations (A, B launch pairs) into a graph.
+// Capture `iters` iterations into a graph: A, B launch pairs, or (one_launch) launches of
+// the one-launch kernel with parities par0, par0 ^ 1, ... on work_b.
 hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh_a, PcgShape sh_b, int lds_nt, const PcgDev* reqs,
                          const int* work_a,
-                         int blocks_a, const int* work_b, int blocks_b, hipGraphExec_t* exec)
+                         int blocks_a, const int* work_b, int blocks_b, hipGraphExec_t* exec, bool one_launch = false,
+                         int par0 = 0)
 {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int it = 0; it < iters && le == hipSuccess; ++it) {
-        le = launch_pcg(sh_a, 0, lds_nt, reqs, work_a, blocks_a, cap);
-        if (le == hipSuccess) le = launch_pcg(sh_b, 1, lds_nt, reqs, work_b, blocks_b, cap);
+        if (one_launch) {
+            le = launch_pcg(sh_b, kPcgOne, lds_nt, reqs, work_b, blocks_b, cap, (par0 + it) & 1);
+            continue;
+        }
+        le = launch_pcg(sh_a, kPcgA, lds_nt, reqs, work_a, blocks_a, cap);
+        if (le == hipSuccess) le = launch_pcg(sh_b, kPcgB, lds_nt, reqs, work_b, blocks_b, cap);
     }
     e = hipStreamEndCapture(cap, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -255,8 +283,9 @@ struct gap_grid_s {
     double *tex = nullptr;                                   // centres, east faces, axial faces
     double *kx = nullptr, *kz = nullptr, *minv = nullptr;
     double *S = nullptr, *r0 = nullptr, *r1 = nullptr, *u0 = nullptr, *u1 = nullptr, *z = nullptr;
+    double *z1 = nullptr;                                    // second z of the one-launch iteration
     double *partial = nullptr;                               // force-integration partials
-    double *pcg_part = nullptr;                              // PCG partials: 5 arrays of max_cond * max_pcg_chunks
+    double *pcg_part = nullptr;                              // PCG partials: 15 arrays of max_cond * nz (5 two-launch, 2 x 5 one-launch)
     size_t pcg_part_stride = 0;
     PcgScalars *sc = nullptr;
     PcgScalars *sc_host = nullptr;                           // pinned
@@ -275,6 +304,8 @@ struct gap_grid_s {
     PcgShape shape_a{}, shape_b{};                           // PCG kernel shapes in use (A; B and init)
     int occ[3] = {1, 1, 1};                                  // workgroups per CU of the PCG kernels A, B, init
     int wg_a = 1, wg_b = 1;                                  // workgroups per CU the row chunking targets
+    PcgShape shape_f{};                                      // the one-launch kernel (and its init)
+    int occ_f = 1, wg_f = 1;
     int lds_max = 65536;                                     // bytes of LDS one workgroup may use
     int minv_kind = -1;
     double minv_omega = 0.0;
@@ -289,6 +320,7 @@ struct gap_grid_s {
     struct Graph {
         const int* table = nullptr;                          // schedule the graph was captured with
         int block = 0;
+        int par0 = -1;                                       // one-launch: parity of the first launch; -1: two-launch
         hipGraphExec_t exec = nullptr;
     };
     hipStream_t cap_stream = nullptr;
@@ -312,7 +344,7 @@ namespace {
 
 void release(gap_grid_t g)
 {
-    double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->partial,
+    double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->z1, g->partial,
                       g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part, g->step_buf};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
@@ -394,12 +426,17 @@ void fill_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o)
     a.u[0] = g->u0;
     a.u[1] = g->u1;
     a.z = g->z;
+    a.zf[0] = g->z;
+    a.zf[1] = g->z1;
     const size_t ps = g->pcg_part_stride;
     a.part_rz[0] = g->pcg_part;
     a.part_rz[1] = g->pcg_part + ps;
     a.part_rr = g->pcg_part + 2 * ps;
     a.part_ss = g->pcg_part + 3 * ps;
     a.part_uau = g->pcg_part + 4 * ps;
+    a.fpart[0] = g->pcg_part + 5 * ps;
+    a.fpart[1] = g->pcg_part + 10 * ps;
+    a.fstride = (int)ps;
     a.sc = g->sc;
     a.nt = g->nt;
     a.nz = g->nz;
@@ -412,20 +449,30 @@ void fill_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o)
 gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_t st)
 {
     const int check_every = o->check_every ? o->check_every : 32;
+    const bool one = o->iteration == GAP_ITERATION_ONE_LAUNCH;
     fill_pcg(g, a, o);
-    pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_a * g->cus, a.chunks_a, a.rows_a);
-    pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_b * g->cus, a.chunks_b, a.rows_b);
+    if (one) {
+        // one launch per iteration on the B chunking fields
+        pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_f * g->cus, a.chunks_b, a.rows_b);
+        a.chunks_a = a.chunks_b;
+        a.rows_a = a.rows_b;
+    } else {
+        pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_a * g->cus, a.chunks_a, a.rows_a);
+        pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_b * g->cus, a.chunks_b, a.rows_b);
+    }
+    const PcgShape sh_b = one ? g->shape_f : g->shape_b;
 
-    // schedule tables for this (kernel shape, n_cond, chunk counts, operator map); graphs are
-    // cached by table, so the shape belongs to the key
-    std::vector<int> key = {g->shape_a.NT, g->shape_a.Q, g->shape_b.NT, g->shape_b.Q, a.n_cond, a.chunks_a, a.chunks_b};
+    // schedule tables for this (iteration kind, kernel shapes, n_cond, chunk counts, operator
+    // map); graphs are cached by table, so the shapes belong to the key
+    std::vector<int> key = {one ? 1 : 0, one ? 0 : g->shape_a.NT, one ? 0 : g->shape_a.Q, sh_b.NT, sh_b.Q, a.n_cond,
+                            a.chunks_a, a.chunks_b};
     for (int c = 0; c < a.n_cond; ++c) key.push_back(a.op[c]);
     gap_grid_s::Sched* sch = nullptr;
     for (auto& e : g->scheds)
         if (e.key == key) sch = &e;
     if (!sch) {
         std::vector<std::vector<int>> ga, gb;
-        pcg_groups(0, a.chunks_a, a.n_cond, a.op, ga);
+        if (!one) pcg_groups(0, a.chunks_a, a.n_cond, a.op, ga);
         pcg_groups(0, a.chunks_b, a.n_cond, a.op, gb);
         const std::vector<int> ta = pcg_schedule(ga), tb = pcg_schedule(gb);
         gap_grid_s::Sched e;
@@ -436,7 +483,8 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         e.blocks_b = (int)tb.size();
         g->scheds.push_back(e);
         sch = &g->scheds.back();
-        HIPCHK(hipMemcpyAsync(sch->table, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        if (!ta.empty())
+            HIPCHK(hipMemcpyAsync(sch->table, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(sch->table + ta.size(), tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
     }
@@ -457,21 +505,31 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     *g->req_host = a;
     HIPCHK(hipMemcpyAsync(g->req_dev, g->req_host, sizeof(PcgDev), hipMemcpyHostToDevice, st));
 
-    hipError_t le = launch_pcg(g->shape_b, 2, g->nt, g->req_dev, work_b, sch->blocks_b, st);
+    hipError_t le = launch_pcg(sh_b, one ? kPcgOneInit : kPcgInit, g->nt, g->req_dev, work_b, sch->blocks_b, st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
 
-    // One block = check_every iterations (A, B launch pairs); after each block the host reads
-    // the device record.  Launches after convergence return at once.  `closing`: one more A
-    // launch, which ends a solve that has reached max_iter.
+    // One block = check_every iterations; after each block the host reads the device record.
+    // Launches after convergence return at once.  `closing`: one more launch (A, or the
+    // one-launch kernel), which ends a solve that has reached max_iter.  The one-launch kernel
+    // takes the parity of its launch count since the initial residual.
+    long launched = 0;
     auto enqueue_block = [&](hipStream_t s, int iters, bool closing) -> hipError_t {
         for (int it = 0; it < iters + (closing ? 1 : 0); ++it) {
+            if (one) {
+                timing_mark(g, GAP_KERNEL_PCG_ONE, true, s);
+                hipError_t e1 = launch_pcg(sh_b, kPcgOne, g->nt, g->req_dev, work_b, sch->blocks_b, s, (int)(launched & 1));
+                timing_mark(g, GAP_KERNEL_PCG_ONE, false, s);
+                ++launched;
+                if (e1 != hipSuccess) return e1;
+                continue;
+            }
             timing_mark(g, GAP_KERNEL_PCG_A, true, s);
-            hipError_t e1 = launch_pcg(g->shape_a, 0, g->nt, g->req_dev, work_a, sch->blocks_a, s);
+            hipError_t e1 = launch_pcg(g->shape_a, kPcgA, g->nt, g->req_dev, work_a, sch->blocks_a, s);
             timing_mark(g, GAP_KERNEL_PCG_A, false, s);
             if (e1 != hipSuccess) return e1;
             if (it == iters) break;
             timing_mark(g, GAP_KERNEL_PCG_B, true, s);
-            e1 = launch_pcg(g->shape_b, 1, g->nt, g->req_dev, work_b, sch->blocks_b, s);
+            e1 = launch_pcg(g->shape_b, kPcgB, g->nt, g->req_dev, work_b, sch->blocks_b, s);
             timing_mark(g, GAP_KERNEL_PCG_B, false, s);
             if (e1 != hipSuccess) return e1;
         }
@@ -479,30 +537,36 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     };
     // Event pairs around each launch need plain launches: events recorded by graph nodes
     // cannot be read back with hipEventElapsedTime.  The kernels read the request record
-    // from device memory, so one graph per (schedule, block size) serves every solve.
+    // from device memory, so one graph per (schedule, block size, starting parity) serves
+    // every solve.
     const bool use_graph = o->graph != 0 && !g->timing;
-    hipGraphExec_t exec = nullptr;
-    if (use_graph) {
+    auto graph_for = [&](int par0, hipGraphExec_t* out) -> gap_status {
+        const int want = one ? par0 : -1;
         for (auto& gr : g->graphs)
-            if (gr.block == check_every && gr.table == sch->table) exec = gr.exec;
-        if (!exec) {
-            if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            hipError_t ce = capture_block(g->cap_stream, check_every, g->shape_a, g->shape_b, g->nt, g->req_dev, work_a, sch->blocks_a, work_b,
-                                          sch->blocks_b, &exec);
-            if (ce != hipSuccess) return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce));
-            if (g->graphs.size() >= 4) {
-                (void)hipGraphExecDestroy(g->graphs.front().exec);
-                g->graphs.erase(g->graphs.begin());
+            if (gr.block == check_every && gr.table == sch->table && gr.par0 == want) {
+                *out = gr.exec;
+                return GAP_OK;
             }
-            gap_grid_s::Graph gr;
-            gr.table = sch->table;
-            gr.block = check_every;
-            gr.exec = exec;
-            g->graphs.push_back(gr);
+        if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+        hipGraphExec_t exec = nullptr;
+        hipError_t ce = capture_block(g->cap_stream, check_every, g->shape_a, sh_b, g->nt, g->req_dev, work_a,
+                                      sch->blocks_a, work_b, sch->blocks_b, &exec, one, par0);
+        if (ce != hipSuccess) return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce));
+        if (g->graphs.size() >= 4) {
+            (void)hipGraphExecDestroy(g->graphs.front().exec);
+            g->graphs.erase(g->graphs.begin());
         }
-    }
+        gap_grid_s::Graph gr;
+        gr.table = sch->table;
+        gr.block = check_every;
+        gr.par0 = want;
+        gr.exec = exec;
+        g->graphs.push_back(gr);
+        *out = exec;
+        return GAP_OK;
+    };
     // Full blocks while at least check_every iterations remain before max_iter; then the
-    // remaining iterations and the closing A launch, so that a solve limited by max_iter
+    // remaining iterations and the closing launch, so that a solve limited by max_iter
     // launches no idle block.
     const long max_blocks = o->max_iter / check_every + 2;
     long enqueued = 0;
@@ -511,7 +575,11 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         const bool last = remaining < check_every;
         const int iters = last ? (int)remaining : check_every;
         if (use_graph && !last) {
+            hipGraphExec_t exec = nullptr;
+            gap_status gs = graph_for((int)(launched & 1), &exec);
+            if (gs != GAP_OK) return gs;
             HIPCHK(hipGraphLaunch(exec, st));
+            launched += one ? iters : 0;
         } else {
             if (g->timing) {
                 gap_status ts = timing_reserve(g, 2 * iters + 1);
@@ -561,6 +629,20 @@ hipError_t use_shape(gap_grid_t g, PcgShape sa, PcgShape sb, int wg_a, int wg_b)
     return hipSuccess;
 }
 
+// Switch the handle's one-launch kernel to shape sf; wg_f as for use_shape.
+hipError_t use_shape_f(gap_grid_t g, PcgShape sf, int wg_f)
+{
+    int occ[2];
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = pcg_prepare(sf, k ? kPcgOneInit : kPcgOne, g->nt, &occ[k]);
+        if (e != hipSuccess) return e;
+    }
+    g->shape_f = sf;
+    g->occ_f = std::min(occ[0], occ[1]);
+    g->wg_f = wg_f > 0 ? wg_f : g->occ_f;
+    return hipSuccess;
+}
+
 gap_status validate_opts(const gap_solver_opts* o)
 {
     if (!o) return fail(GAP_EINVAL, "opts is NULL");
@@ -574,6 +656,8 @@ gap_status validate_opts(const gap_solver_opts* o)
     if (o->check_every < 0) return fail(GAP_EINVAL, "check_every must be >= 0");
     if (o->strategy != GAP_STRATEGY_SYNC && o->strategy != GAP_STRATEGY_ASYNC)
         return fail(GAP_EINVAL, "unknown strategy");
+    if (o->iteration != GAP_ITERATION_TWO_LAUNCH && o->iteration != GAP_ITERATION_ONE_LAUNCH)
+        return fail(GAP_EINVAL, "unknown iteration kind");
     return GAP_OK;
 }
 
@@ -649,6 +733,7 @@ gap_status gap_default_opts(gap_solver_opts* o)
     o->check_every = 32;
     o->graph = 1;
     o->strategy = GAP_STRATEGY_SYNC;
+    o->iteration = GAP_ITERATION_ONE_LAUNCH;
     return GAP_OK;
 }
 
@@ -721,8 +806,8 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
             g->lds_max = lds;
-        g->shape_a = g->shape_b = pcg_candidates(g->nt)[0];
-        const size_t need = pcg_lds_bytes(1, g->shape_b.NT * g->shape_b.Q) + 2048;
+        g->shape_a = g->shape_b = g->shape_f = pcg_candidates(g->nt)[0];
+        const size_t need = pcg_lds_bytes(kPcgOne, g->shape_f.NT * g->shape_f.Q) + 2048;
         if (need > (size_t)g->lds_max) {
             release(g);
             return fail(GAP_EINVAL, "n_theta = %d needs %zu bytes of LDS per workgroup, the device allows %d",
@@ -734,6 +819,7 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     g->pcg_part_stride = max_pcg;
     {
         hipError_t pe = use_shape(g, g->shape_a, g->shape_b, 0, 0);
+        if (pe == hipSuccess) pe = use_shape_f(g, g->shape_f, 0);
         if (pe != hipSuccess) {
             release(g);
             return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(pe));
@@ -745,8 +831,9 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     ALLOC(g->u0, max_cond * n);
     ALLOC(g->u1, max_cond * n);
     ALLOC(g->z, max_cond * n);
+    ALLOC(g->z1, max_cond * n);
     ALLOC(g->partial, 10 * max_chunks);
-    ALLOC(g->pcg_part, 5 * max_pcg);
+    ALLOC(g->pcg_part, 15 * max_pcg);
 #undef ALLOC
     if (hipMalloc((void**)&g->sc, sizeof(PcgScalars)) != hipSuccess) {
         g->sc = nullptr;
@@ -770,7 +857,7 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     hipError_t e = hipMemcpy(g->trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(g->tex, 0, (2 * n + (g->nz + 1) * nt) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(g->sc, 0, sizeof(PcgScalars));
-    if (e == hipSuccess) e = hipMemset(g->pcg_part, 0, 5 * g->pcg_part_stride * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(g->pcg_part, 0, 15 * g->pcg_part_stride * sizeof(double));
     if (e != hipSuccess) {
         release(g);
         return fail(GAP_EDEVICE, "initialising tables: %s", hipGetErrorString(e));
@@ -1251,6 +1338,10 @@ gap_status gap_get_pcg_config(gap_grid_t g, gap_pcg_config* cfg)
     cfg->cols_per_thread_b = g->shape_b.Q;
     cfg->wg_per_cu_b = g->wg_b;
     cfg->occupancy_b = std::min(g->occ[1], g->occ[2]);
+    cfg->threads_f = g->shape_f.NT;
+    cfg->cols_per_thread_f = g->shape_f.Q;
+    cfg->wg_per_cu_f = g->wg_f;
+    cfg->occupancy_f = g->occ_f;
     return GAP_OK;
 }
 
@@ -1261,12 +1352,13 @@ gap_status check_shape(gap_grid_t g, PcgShape sh)
     const int cols = sh.NT * sh.Q;
     if (!shape_known(sh) || cols < g->nt || cols >= 2 * g->nt + 64)
         return fail(GAP_EINVAL, "shape %d x %d does not fit a ring of %d cells", sh.NT, sh.Q, g->nt);
-    if (pcg_lds_bytes(1, cols) + 2048 > (size_t)g->lds_max)
+    if (pcg_lds_bytes(kPcgOne, cols) + 2048 > (size_t)g->lds_max)
         return fail(GAP_EINVAL, "shape %d x %d needs more LDS than a workgroup may use", sh.NT, sh.Q);
     return GAP_OK;
 }
 
-// One timed run of the tuner: average device us per launch of A and of B.
+// One timed run of the tuner: average device us per launch of A and of B (two-launch
+// iteration), or of the one-launch kernel in *us_a (*us_b = 0).
 gap_status tune_run(gap_grid_t g, const gap_solver_opts* t, double* p, void* stream, double* us_a, double* us_b)
 {
     for (int k = 0; k < GAP_KERNEL_COUNT; ++k) {
@@ -1277,10 +1369,11 @@ gap_status tune_run(gap_grid_t g, const gap_solver_opts* t, double* p, void* str
     gap_status s = solve_joint_pcg(g, t, p, nullptr, stream);
     g->timing = false;
     if (s != GAP_OK && s != GAP_ENOCONV) return s;
-    if (!g->launches[GAP_KERNEL_PCG_A] || !g->launches[GAP_KERNEL_PCG_B])
-        return fail(GAP_EDEVICE, "the tuning run recorded no launches");
-    *us_a = 1e3 * g->total_ms[GAP_KERNEL_PCG_A] / (double)g->launches[GAP_KERNEL_PCG_A];
-    *us_b = 1e3 * g->total_ms[GAP_KERNEL_PCG_B] / (double)g->launches[GAP_KERNEL_PCG_B];
+    const int ka = t->iteration == GAP_ITERATION_ONE_LAUNCH ? GAP_KERNEL_PCG_ONE : GAP_KERNEL_PCG_A;
+    const int kb = t->iteration == GAP_ITERATION_ONE_LAUNCH ? -1 : GAP_KERNEL_PCG_B;
+    if (!g->launches[ka] || (kb >= 0 && !g->launches[kb])) return fail(GAP_EDEVICE, "the tuning run recorded no launches");
+    *us_a = 1e3 * g->total_ms[ka] / (double)g->launches[ka];
+    *us_b = kb >= 0 ? 1e3 * g->total_ms[kb] / (double)g->launches[kb] : 0.0;
     return GAP_OK;
 }
 
@@ -1290,22 +1383,28 @@ gap_status gap_set_pcg_config(gap_grid_t g, const gap_pcg_config* cfg)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
     GAP_NOT_IN_BATCH(g, "gap_set_pcg_config");
-    PcgShape sa = pcg_candidates(g->nt)[0], sb = sa;
-    int wa = 0, wb = 0;
+    PcgShape sa = pcg_candidates(g->nt)[0], sb = sa, sf = sa;
+    int wa = 0, wb = 0, wf = 0;
     if (cfg) {
         sa.NT = cfg->threads_a;
         sa.Q = cfg->cols_per_thread_a;
         sb.NT = cfg->threads_b;
         sb.Q = cfg->cols_per_thread_b;
+        sf.NT = cfg->threads_f;
+        sf.Q = cfg->cols_per_thread_f;
         gap_status cs = check_shape(g, sa);
         if (cs == GAP_OK) cs = check_shape(g, sb);
+        if (cs == GAP_OK) cs = check_shape(g, sf);
         if (cs != GAP_OK) return cs;
-        if (cfg->wg_per_cu_a < 1 || cfg->wg_per_cu_a > 8 || cfg->wg_per_cu_b < 1 || cfg->wg_per_cu_b > 8)
-            return fail(GAP_EINVAL, "wg_per_cu must lie in [1, 8]");
-        wa = cfg->wg_per_cu_a;
-        wb = cfg->wg_per_cu_b;
+        const int w[3] = {cfg->wg_per_cu_a, cfg->wg_per_cu_b, cfg->wg_per_cu_f};
+        for (int k = 0; k < 3; ++k)
+            if (w[k] < 1 || w[k] > 8) return fail(GAP_EINVAL, "wg_per_cu must lie in [1, 8]");
+        wa = w[0];
+        wb = w[1];
+        wf = w[2];
     }
     hipError_t e = use_shape(g, sa, sb, wa, wb);
+    if (e == hipSuccess) e = use_shape_f(g, sf, wf);
     if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
     return GAP_OK;
 }
@@ -1328,8 +1427,9 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     t.warm_start = 0;
     t.strategy = GAP_STRATEGY_SYNC;
     const bool timing = g->timing;
-    const PcgShape orig_a = g->shape_a, orig_b = g->shape_b;    // restored if tuning fails
-    const int orig_wa = g->wg_a, orig_wb = g->wg_b;
+    const PcgShape orig_a = g->shape_a, orig_b = g->shape_b, orig_f = g->shape_f;    // restored if tuning fails
+    const int orig_wa = g->wg_a, orig_wb = g->wg_b, orig_wf = g->wg_f;
+    const bool one = o->iteration == GAP_ITERATION_ONE_LAUNCH;
     struct Pick {
         PcgShape sh;
         int wg = 0;
@@ -1340,16 +1440,24 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     gap_status result = GAP_OK;
     for (const PcgShape sh : pcg_candidates(g->nt)) {
         if (result != GAP_OK) break;
-        if (pcg_lds_bytes(1, sh.NT * sh.Q) + 2048 > (size_t)g->lds_max) continue;
+        if (pcg_lds_bytes(one ? kPcgOne : kPcgB, sh.NT * sh.Q) + 2048 > (size_t)g->lds_max) continue;
         int occ[3];
         bool ok = true;
-        for (int which = 0; which < 3 && ok; ++which) ok = pcg_prepare(sh, which, g->nt, &occ[which]) == hipSuccess;
+        if (one) {
+            for (int k = 0; k < 2 && ok; ++k) ok = pcg_prepare(sh, k ? kPcgOneInit : kPcgOne, g->nt, &occ[k]) == hipSuccess;
+            occ[0] = std::min(occ[0], occ[1]);
+            occ[1] = occ[2] = occ[0];
+        } else {
+            for (int which = 0; which < 3 && ok; ++which) ok = pcg_prepare(sh, which, g->nt, &occ[which]) == hipSuccess;
+        }
         if (!ok) continue;
         const int ob = std::min(occ[1], occ[2]);
-        // A and B are timed in the same runs; wg_per_cu of A and of B advance together
+        // A and B are timed in the same runs; wg_per_cu of A and of B advance together.  The
+        // one-launch kernel is timed as "A".
         for (int w = 1; w <= std::max(occ[0], ob) && result == GAP_OK; ++w) {
             const int wa = std::min(w, occ[0]), wb = std::min(w, ob);
-            if (use_shape(g, sh, sh, wa, wb) != hipSuccess) {
+            const hipError_t pe = one ? use_shape_f(g, sh, wa) : use_shape(g, sh, sh, wa, wb);
+            if (pe != hipSuccess) {
                 result = fail(GAP_EDEVICE, "preparing the PCG kernels");
                 break;
             }
@@ -1362,7 +1470,7 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
             }
             if (result != GAP_OK) break;
             if (!pa.have || ta < pa.us) pa = {sh, wa, ta, true};
-            if (!pb.have || tb < pb.us) pb = {sh, wb, tb, true};
+            if (!pb.have || tb < pb.us || one) pb = {sh, wb, tb, true};
             const bool is_def = sh.NT == def.NT && sh.Q == def.Q;
             if (is_def && wa == occ[0]) da = {sh, wa, ta, true};
             if (is_def && wb == ob) db = {sh, wb, tb, true};
@@ -1371,12 +1479,14 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     g->timing = timing;
     if (result != GAP_OK || !pa.have || !pb.have) {
         (void)use_shape(g, orig_a, orig_b, orig_wa, orig_wb);
+        (void)use_shape_f(g, orig_f, orig_wf);
         return result != GAP_OK ? result : fail(GAP_EDEVICE, "no kernel shape could be prepared");
     }
     // keep the default unless the best is at least 1 % faster (stable choice on near-ties)
     if (da.have && da.us <= 1.01 * pa.us) pa = da;
     if (db.have && db.us <= 1.01 * pb.us) pb = db;
-    hipError_t e = use_shape(g, pa.sh, pb.sh, pa.wg, pb.wg);
+    // the kernels of the other iteration kind keep their configuration
+    hipError_t e = one ? use_shape_f(g, pa.sh, pa.wg) : use_shape(g, pa.sh, pb.sh, pa.wg, pb.wg);
     if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
     gap_pcg_config win{};
     gap_get_pcg_config(g, &win);
@@ -1482,9 +1592,9 @@ gap_status gap_grid_bytes(const gap_geom* geom, int32_t max_cond, int64_t* bytes
     const ChunkMap cm1 = make_chunks((int)nz, 1), cm9 = make_chunks((int)nz, GAP_MAX_COND);
     int64_t d = 4 * nt + 2 * n + (nz + 1) * nt;              // tables and texture samples
     d += max_op * n + max_op * (n + nt);                     // face conductances
-    d += 6 * (int64_t)max_cond * n;                          // S, r (2), u (2), z
+    d += 7 * (int64_t)max_cond * n;                          // S, r (2), u (2), z (2)
     d += 10 * (int64_t)std::max(cm1.total, cm9.total);       // force partials
-    d += 5 * (int64_t)max_cond * nz;                         // PCG partials
+    d += 15 * (int64_t)max_cond * nz;                        // PCG partials
     d += (int64_t)max_cond * n;                              // the caller's pressure field
     *bytes = d * (int64_t)sizeof(double) + 4096;
     return GAP_OK;

@@ -32,9 +32,10 @@ GAP_SCALARS_GLOBAL, GAP_SCALARS_PER_COND = 0, 1
 GAP_STRATEGY_SYNC, GAP_STRATEGY_ASYNC = 0, 1
 GAP_CAVITATION_NONE, GAP_CAVITATION_CLAMP = 0, 1
 GAP_MAX_COND = 9
-GAP_KERNEL_PCG_A, GAP_KERNEL_PCG_B = 0, 1
-GAP_KERNEL_COUNT = 2
-KERNEL_NAMES = ["k_pcg_a", "k_pcg_b"]
+GAP_ITERATION_TWO_LAUNCH, GAP_ITERATION_ONE_LAUNCH = 0, 1
+GAP_KERNEL_PCG_A, GAP_KERNEL_PCG_B, GAP_KERNEL_PCG_ONE = 0, 1, 2
+GAP_KERNEL_COUNT = 3
+KERNEL_NAMES = ["k_pcg_a", "k_pcg_b", "k_pcg_f"]
 
 
 class gap_geom(ctypes.Structure):
@@ -54,7 +55,7 @@ class gap_solver_opts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("neumann", ctypes.c_int32), ("scalars", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("strategy", ctypes.c_int32)]
+                ("strategy", ctypes.c_int32), ("iteration", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gap_solve_info(ctypes.Structure):
@@ -69,7 +70,9 @@ class gap_pcg_config(ctypes.Structure):
     _fields_ = [("threads_a", ctypes.c_int32), ("cols_per_thread_a", ctypes.c_int32),
                 ("wg_per_cu_a", ctypes.c_int32), ("occupancy_a", ctypes.c_int32),
                 ("threads_b", ctypes.c_int32), ("cols_per_thread_b", ctypes.c_int32),
-                ("wg_per_cu_b", ctypes.c_int32), ("occupancy_b", ctypes.c_int32)]
+                ("wg_per_cu_b", ctypes.c_int32), ("occupancy_b", ctypes.c_int32),
+                ("threads_f", ctypes.c_int32), ("cols_per_thread_f", ctypes.c_int32),
+                ("wg_per_cu_f", ctypes.c_int32), ("occupancy_f", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

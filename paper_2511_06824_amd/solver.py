@@ -71,12 +71,13 @@ class JointGapSolver:
 
     @staticmethod
     def options(omega=1.6, eps=1e-10, max_iter=100000, precond=G.GAP_PRECOND_ASSOR2, scalars=G.GAP_SCALARS_GLOBAL,
-                warm_start=False, check_every=0, neumann=1, graph=True, strategy=G.GAP_STRATEGY_SYNC):
+                warm_start=False, check_every=0, neumann=1, graph=True, strategy=G.GAP_STRATEGY_SYNC,
+                iteration=G.GAP_ITERATION_ONE_LAUNCH):
         o = G.gap_default_opts()
         o.omega, o.eps, o.max_iter = float(omega), float(eps), int(max_iter)
         o.precond, o.scalars, o.neumann = int(precond), int(scalars), int(neumann)
         o.warm_start, o.check_every, o.graph = int(bool(warm_start)), int(check_every), int(bool(graph))
-        o.strategy = int(strategy)
+        o.strategy, o.iteration = int(strategy), int(iteration)
         return o
 
     def solve(self, opts=None, raise_on_error=True, **kw):
@@ -113,10 +114,12 @@ class JointGapSolver:
         return G.gap_get_pcg_config(self.handle).as_dict()
 
     def set_pcg_config(self, threads=None, cols_per_thread=None, wg_per_cu_a=None, wg_per_cu_b=None,
-                       threads_b=None, cols_per_thread_b=None):
-        """Select the PCG kernel configuration: shape (threads x columns per thread) of A, and of
-        B when threads_b / cols_per_thread_b are given (else the same); no arguments: the
-        default."""
+                       threads_b=None, cols_per_thread_b=None, threads_f=None, cols_per_thread_f=None,
+                       wg_per_cu_f=None):
+        """Select the PCG kernel configuration: shape (threads x columns per thread) of A, of B
+        when threads_b / cols_per_thread_b are given (else the same as A) and of the one-launch
+        kernel F when threads_f / cols_per_thread_f are given (else the same as B); F's row
+        chunking follows wg_per_cu_f, else wg_per_cu_b.  No arguments: the default."""
         if threads is None:
             G.gap_set_pcg_config(self.handle, None)
             return self.pcg_config
@@ -125,8 +128,12 @@ class JointGapSolver:
         cfg.threads_a, cfg.cols_per_thread_a = int(threads), int(cols_per_thread)
         cfg.threads_b = int(threads if threads_b is None else threads_b)
         cfg.cols_per_thread_b = int(cols_per_thread if cols_per_thread_b is None else cols_per_thread_b)
+        cfg.threads_f = int(cfg.threads_b if threads_f is None else threads_f)
+        cfg.cols_per_thread_f = int(cfg.cols_per_thread_b if cols_per_thread_f is None else cols_per_thread_f)
         cfg.wg_per_cu_a = cur.wg_per_cu_a if wg_per_cu_a is None else int(wg_per_cu_a)
         cfg.wg_per_cu_b = cur.wg_per_cu_b if wg_per_cu_b is None else int(wg_per_cu_b)
+        cfg.wg_per_cu_f = (cfg.wg_per_cu_b if wg_per_cu_b is not None else cur.wg_per_cu_f) \
+            if wg_per_cu_f is None else int(wg_per_cu_f)
         G.gap_set_pcg_config(self.handle, cfg)
         return self.pcg_config
 

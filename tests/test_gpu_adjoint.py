@@ -188,10 +188,12 @@ def test_adjoint_clamp_mode_is_finite_and_close_to_fd():
     assert block_err(J, Jc) < 5e-2
 
 
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                         ids=["two_launch", "one_launch"])
 @pytest.mark.parametrize("scalars,strategy", [("per_cond", "sync"), ("per_cond", "async"), ("global", "async")])
-def test_scalar_and_strategy_variants_follow_oracle(scalars, strategy):
+def test_scalar_and_strategy_variants_follow_oracle(scalars, strategy, iteration):
     case = synth.textured_case(96, 48, 3)
-    log(f"case: {case.label}, {scalars} scalars, {strategy}")
+    log(f"case: {case.label}, {scalars} scalars, {strategy}, iteration kind {iteration}")
     gap = gap_of(case)
     tex = texture_of(case)
     blocks_, rhs = [], []
@@ -205,7 +207,8 @@ def test_scalar_and_strategy_variants_follow_oracle(scalars, strategy):
     s.assemble(case.e, case.edot, case.delta, 9)
     p, info = s.solve(omega=1.6, eps=1e-10,
                       scalars=G.GAP_SCALARS_PER_COND if scalars == "per_cond" else G.GAP_SCALARS_GLOBAL,
-                      strategy=G.GAP_STRATEGY_ASYNC if strategy == "async" else G.GAP_STRATEGY_SYNC)
+                      strategy=G.GAP_STRATEGY_ASYNC if strategy == "async" else G.GAP_STRATEGY_SYNC,
+                      iteration=iteration)
     p = p.reshape(9, -1).cpu().numpy()
     assert abs(info.iterations - it_ref) <= 2, (info.iterations, it_ref)
     for k in range(9):

@@ -41,19 +41,21 @@ def test_linear_axial_profile_closed_form(ecc, U):
     assert err <= 1e-9
 
 
-def test_largest_axial_size_follows_the_oracle_recurrence():
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                         ids=["two_launch", "one_launch"])
+def test_largest_axial_size_follows_the_oracle_recurrence(iteration):
     """n_axial = 65536 (the largest accepted) on a 16-cell ring, one condition: 100 iterations of
     the GPU recurrence against 100 iterations of the oracle's Table 1 PCG with ASSOR II."""
     nt, nz = 16, 65536
     case = synth.smooth_case(nt, nz, 1)
-    log(f"case: {case.label}, 100 PCG iterations against the oracle")
+    log(f"case: {case.label}, 100 PCG iterations against the oracle, iteration kind {iteration}")
     gap = gap_of(case)
     A, S = oracle.assemble(gap, case.e, case.edot)
     M = oracle.assor2_precond(A, 1.8)
     p_ref, it_ref, hist = oracle.pcg(A, S, M, 1e-300, 100)
     s = JointGapSolver.from_case(case, max_cond=1)
     s.assemble(case.e, case.edot, None, 1)
-    p, info = s.solve(omega=1.8, eps=1e-300, max_iter=100, raise_on_error=False)
+    p, info = s.solve(omega=1.8, eps=1e-300, max_iter=100, raise_on_error=False, iteration=iteration)
     p = p.reshape(-1).cpu().numpy()
     kx, kz, Sg = [t.cpu().numpy() for t in s.read_system(0)]
     s.close()

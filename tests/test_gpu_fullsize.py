@@ -23,6 +23,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+from paper_2511_06824_amd import gapsolve as G  # noqa: E402
 from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
 
 ENTRY_TOL = 1e-12     # face conductances, relative per entry (see the small-grid assembly test)
@@ -46,14 +47,16 @@ def sample_cells(nt, nz, rng, count=3000):
     return np.concatenate([i, edge_i, col_i]), np.concatenate([j, edge_j, col_j])
 
 
-def test_joint_textured_2048x1024_full_size():
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                         ids=["two_launch", "one_launch"])
+def test_joint_textured_2048x1024_full_size(iteration):
     case = synth.make_case("joint_textured_2048x1024", 0)
-    log(f"case: {case.label}, 9 conditions, full size")
+    log(f"case: {case.label}, 9 conditions, full size, iteration kind {iteration}")
     gap, tex = gap_of(case), texture_of(case)
     nt, nz = case.n_theta, case.n_axial
     s = JointGapSolver.from_case(case, max_cond=9)
     s.assemble(case.e, case.edot, case.delta, 9)
-    opts = s.options(omega=case.omega, eps=case.eps)
+    opts = s.options(omega=case.omega, eps=case.eps, iteration=iteration)
     cfg, _ = s.tune(opts, iterations=20)
     log(f"  launch configuration {cfg}")
     p, info = s.solve(opts)

@@ -24,6 +24,9 @@ from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
 
 P_TOL, F_TOL, J_TOL = 1e-9, 1e-8, 1e-5
 EPS_PARITY = 1e-13
+# both iteration kinds: Table 1 as printed (two launches) and the one-launch default
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                                     ids=["two_launch", "one_launch"])
 
 
 def log(msg):
@@ -83,23 +86,25 @@ def test_smooth_64x32_single_condition(seed):
     assert force_err(F, F_ref) <= F_TOL
 
 
+@ITERATIONS
 @pytest.mark.parametrize("seed", [0, 7])
-def test_smooth_64x32_joint_nine_conditions(seed):
+def test_smooth_64x32_joint_nine_conditions(seed, iteration):
     case = synth.smooth_case(64, 32, seed)
-    log(f"case: {case.label}, 9 conditions")
+    log(f"case: {case.label}, 9 conditions, iteration kind {iteration}")
     p_ref, F_ref = oracle_case(case, 9)
-    p, F, J, info = gpu_case(case, 9)
+    p, F, J, info = gpu_case(case, 9, iteration=iteration)
     assert pressure_err(p, p_ref) <= P_TOL
     assert force_err(F, F_ref) <= F_TOL
     assert jac_err(J, oracle.jacobian_fd(F_ref, case.delta)) <= J_TOL
 
 
+@ITERATIONS
 @pytest.mark.parametrize("shape", [(3, 2), (5, 7), (67, 33), (300, 41), (1000, 3), (257, 9)])
-def test_ragged_grids_textured(shape):
+def test_ragged_grids_textured(shape, iteration):
     case = synth.textured_case(*shape, 3)
-    log(f"case: {case.label}, 9 conditions")
+    log(f"case: {case.label}, 9 conditions, iteration kind {iteration}")
     p_ref, F_ref = oracle_case(case, 9, method="dense" if shape[0] * shape[1] <= 64 else "band")
-    p, F, J, info = gpu_case(case, 9)
+    p, F, J, info = gpu_case(case, 9, iteration=iteration)
     assert pressure_err(p, p_ref) <= P_TOL
     assert force_err(F, F_ref) <= F_TOL
 
@@ -125,25 +130,28 @@ def test_joint_smooth_512x256():
     assert jac_err(J, oracle.jacobian_fd(F_ref, case.delta)) <= J_TOL
 
 
+@ITERATIONS
 @pytest.mark.parametrize("precond,name", [(G.GAP_PRECOND_ASSOR2, "assor2"), (G.GAP_PRECOND_ASSOR1, "assor1"),
                                           (G.GAP_PRECOND_JACOBI, "jacobi")])
-def test_iteration_counts_follow_oracle_pcg(precond, name):
-    """Same recurrence as the oracle's Table 1 PCG on the joint matrix (global scalars)."""
+def test_iteration_counts_follow_oracle_pcg(precond, name, iteration):
+    """Same recurrence as the oracle's Table 1 PCG on the joint matrix (global scalars); the
+    one-launch iteration forms alpha's denominator from other sums and agrees up to rounding."""
     case = synth.textured_case(96, 48, 2)
-    log(f"case: {case.label}, 9 conditions, {name}")
+    log(f"case: {case.label}, 9 conditions, {name}, iteration kind {iteration}")
     gap = gap_of(case)
     AG, SG = oracle.assemble_joint(gap, case.e, case.edot, case.delta, texture_of(case))
     M = {"assor2": oracle.assor2_precond(AG, 1.6), "assor1": oracle.assor1_precond(AG, 1.6),
          "jacobi": oracle.jacobi_precond(AG)}[name]
     pG, it_ref, hist = oracle.pcg(AG, SG, M, 1e-10, 100000)
-    p, F, J, info = gpu_case(case, 9, eps=1e-10, precond=precond, omega=1.6)
+    p, F, J, info = gpu_case(case, 9, eps=1e-10, precond=precond, omega=1.6, iteration=iteration)
     assert abs(info.iterations - it_ref) <= 2, (info.iterations, it_ref)
     assert np.linalg.norm(p.ravel() - pG) / np.linalg.norm(pG) < 1e-8
 
 
+@ITERATIONS
 @pytest.mark.parametrize("name,precond", [("assor2", G.GAP_PRECOND_ASSOR2), ("assor1", G.GAP_PRECOND_ASSOR1)])
 @pytest.mark.parametrize("omega", [0.1, 0.46, 1.0, 1.54, 1.9])
-def test_omega_sweep_iteration_counts_follow_oracle(name, precond, omega):
+def test_omega_sweep_iteration_counts_follow_oracle(name, precond, omega, iteration):
     """The relaxation-factor study (omega = 0.1 + 0.18 i): the GPU recurrence follows the
     oracle's Table 1 PCG with the same preconditioner at every omega."""
     case = synth.smooth_case(64, 32, 3)
@@ -151,27 +159,29 @@ def test_omega_sweep_iteration_counts_follow_oracle(name, precond, omega):
     AG, SG = oracle.assemble_joint(gap_of(case), case.e, case.edot, case.delta)
     M = (oracle.assor2_precond if name == "assor2" else oracle.assor1_precond)(AG, omega)
     pG, it_ref, _ = oracle.pcg(AG, SG, M, 1e-10, 100000)
-    p, F, J, info = gpu_case(case, 9, eps=1e-10, precond=precond, omega=omega)
+    p, F, J, info = gpu_case(case, 9, eps=1e-10, precond=precond, omega=omega, iteration=iteration)
     assert abs(info.iterations - it_ref) <= 2, (info.iterations, it_ref)
     assert np.linalg.norm(p.ravel() - pG) / np.linalg.norm(pG) < 1e-8
 
 
-def test_per_condition_scalars_reach_same_solution():
+@ITERATIONS
+def test_per_condition_scalars_reach_same_solution(iteration):
     case = synth.smooth_case(128, 64, 4)
-    log(f"case: {case.label}, 9 conditions, per-condition scalars")
+    log(f"case: {case.label}, 9 conditions, per-condition scalars, iteration kind {iteration}")
     p_ref, F_ref = oracle_case(case, 9)
-    p, F, J, info = gpu_case(case, 9, scalars=G.GAP_SCALARS_PER_COND)
+    p, F, J, info = gpu_case(case, 9, scalars=G.GAP_SCALARS_PER_COND, iteration=iteration)
     assert pressure_err(p, p_ref) <= P_TOL
     assert force_err(F, F_ref) <= F_TOL
 
 
-def test_warm_start_from_solution_takes_no_iterations():
+@ITERATIONS
+def test_warm_start_from_solution_takes_no_iterations(iteration):
     case = synth.smooth_case(64, 32, 2)
-    log(f"case: {case.label}, warm start")
+    log(f"case: {case.label}, warm start, iteration kind {iteration}")
     s = JointGapSolver.from_case(case, max_cond=9)
     s.assemble(case.e, case.edot, case.delta, 9)
-    s.solve(eps=1e-12, omega=case.omega)
-    _, info = s.solve(eps=1e-10, omega=case.omega, warm_start=True)
+    s.solve(eps=1e-12, omega=case.omega, iteration=iteration)
+    _, info = s.solve(eps=1e-10, omega=case.omega, warm_start=True, iteration=iteration)
     assert info.iterations == 0
     s.close()
 

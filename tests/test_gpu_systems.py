@@ -25,18 +25,26 @@ def solve_copy(s, **opt):
     return p.clone().cpu().numpy(), info.iterations, info.rel_residual
 
 
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                                     ids=["two_launch", "one_launch"])
+
+
+@ITERATIONS
 @pytest.mark.parametrize("shape", [(256, 128), (2048, 64), (100, 37)])
-def test_graph_replays_match_eager_bitwise(shape):
+def test_graph_replays_match_eager_bitwise(shape, iteration):
+    """Cached graphs replayed between eager work; an odd block size (7) makes the one-launch
+    kernel's graphs start at both launch parities."""
     case = synth.textured_case(*shape, 2)
-    log(f"case: {case.label}, graph vs eager")
+    log(f"case: {case.label}, graph vs eager, iteration kind {iteration}")
     s = JointGapSolver.from_case(case, max_cond=9)
     s.assemble(case.e, case.edot, case.delta, 9)
-    pe, ie, re = solve_copy(s, eps=1e-10, omega=1.6, graph=False)
-    pg1, ig1, rg1 = solve_copy(s, eps=1e-10, omega=1.6, graph=True)      # captures
+    kw = dict(eps=1e-10, omega=1.6, iteration=iteration)
+    pe, ie, re = solve_copy(s, graph=False, **kw)
+    pg1, ig1, rg1 = solve_copy(s, graph=True, **kw)                      # captures
     F = s.integrate().clone()                                              # eager work between replays
     torch.cuda.synchronize()
-    pg2, ig2, rg2 = solve_copy(s, eps=1e-10, omega=1.6, graph=True)      # replays the cached graph
-    pg3, ig3, rg3 = solve_copy(s, eps=1e-10, omega=1.6, graph=True, check_every=7)   # new block size
+    pg2, ig2, rg2 = solve_copy(s, graph=True, **kw)                      # replays the cached graph
+    pg3, ig3, rg3 = solve_copy(s, graph=True, check_every=7, **kw)       # new block size
     for p, i, r in [(pg1, ig1, rg1), (pg2, ig2, rg2), (pg3, ig3, rg3)]:
         assert i == ie and r == re
         assert np.array_equal(p, pe)
@@ -44,20 +52,49 @@ def test_graph_replays_match_eager_bitwise(shape):
     s.close()
 
 
-def test_timing_hooks_do_not_change_results():
+@ITERATIONS
+def test_timing_hooks_do_not_change_results(iteration):
     case = synth.smooth_case(512, 128, 1)
-    log(f"case: {case.label}, timing on/off")
+    log(f"case: {case.label}, timing on/off, iteration kind {iteration}")
     s = JointGapSolver.from_case(case, max_cond=9)
     s.assemble(case.e, case.edot, case.delta, 9)
-    p0, i0, _ = solve_copy(s, eps=1e-10, omega=1.8)
+    kw = dict(eps=1e-10, omega=1.8, iteration=iteration)
+    p0, i0, _ = solve_copy(s, **kw)
     G.gap_kernel_timing(s.handle, 1)
-    p1, i1, _ = solve_copy(s, eps=1e-10, omega=1.8)
-    p2, i2, _ = solve_copy(s, eps=1e-10, omega=1.8, graph=False)
+    p1, i1, _ = solve_copy(s, **kw)
+    p2, i2, _ = solve_copy(s, graph=False, **kw)
     G.gap_kernel_timing(s.handle, 0)
-    na, ta = G.gap_kernel_stats(s.handle, G.GAP_KERNEL_PCG_A)
-    nb, tb = G.gap_kernel_stats(s.handle, G.GAP_KERNEL_PCG_B)
+    n = [G.gap_kernel_stats(s.handle, k) for k in range(G.GAP_KERNEL_COUNT)]
     assert np.array_equal(p0, p1) and np.array_equal(p0, p2) and i0 == i1 == i2
-    assert na >= 2 * i0 and nb >= 2 * i0 and ta > 0 and tb > 0
+    timed = [G.GAP_KERNEL_PCG_A, G.GAP_KERNEL_PCG_B] if iteration == G.GAP_ITERATION_TWO_LAUNCH \
+        else [G.GAP_KERNEL_PCG_ONE]
+    for k in range(G.GAP_KERNEL_COUNT):
+        if k in timed:
+            assert n[k][0] >= 2 * i0 and n[k][1] > 0
+        else:
+            assert n[k][0] == 0
+    s.close()
+
+
+def test_one_launch_agrees_with_table1_iteration():
+    """The one-launch iteration takes Table 1's steps with alpha's denominator expanded: the
+    same iteration count (within one) and the same iterate up to rounding, on every
+    preconditioner and scalar / strategy variant."""
+    case = synth.textured_case(300, 96, 5)
+    log(f"case: {case.label}, one-launch against two-launch")
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    for v in [dict(), dict(precond=G.GAP_PRECOND_JACOBI), dict(precond=G.GAP_PRECOND_ASSOR1),
+              dict(scalars=G.GAP_SCALARS_PER_COND), dict(strategy=G.GAP_STRATEGY_ASYNC),
+              dict(scalars=G.GAP_SCALARS_PER_COND, strategy=G.GAP_STRATEGY_ASYNC)]:
+        out = []
+        for it in (G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH):
+            p, info = s.solve(eps=1e-12, omega=1.6, iteration=it, **v)
+            out.append((p.clone().cpu().numpy().reshape(9, -1), info.iterations, info.rel_residual))
+        (p2, i2, r2), (p1, i1, r1) = out
+        d = max(np.linalg.norm(p1[k] - p2[k]) / np.linalg.norm(p2[k]) for k in range(9))
+        log(f"  {v}: iterations {i2} / {i1}, residual {r2:.2e} / {r1:.2e}, difference {d:.1e}")
+        assert abs(i1 - i2) <= 1 and r1 <= 1e-12 and d <= 1e-10
     s.close()
 
 

@@ -46,8 +46,12 @@ def reference(nt, nz, n_cond):
     return _ref[key]
 
 
-def check(s, case, n_cond, p_ref, F_ref):
-    p, info = s.solve(omega=case.omega, eps=EPS)
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                                     ids=["two_launch", "one_launch"])
+
+
+def check(s, case, n_cond, p_ref, F_ref, iteration=G.GAP_ITERATION_ONE_LAUNCH):
+    p, info = s.solve(omega=case.omega, eps=EPS, iteration=iteration)
     F = s.integrate().cpu().numpy()
     p = p.reshape(n_cond, -1).cpu().numpy()
     perr = max(np.linalg.norm(p[k] - p_ref[k]) / np.linalg.norm(p_ref[k]) for k in range(n_cond))
@@ -56,44 +60,58 @@ def check(s, case, n_cond, p_ref, F_ref):
     return perr, ferr, info
 
 
+@ITERATIONS
 @pytest.mark.parametrize("nt,nz,n_cond", CASES, ids=[f"{a}x{b}x{c}" for a, b, c in CASES])
-def test_every_configuration_matches_oracle(nt, nz, n_cond):
+def test_every_configuration_matches_oracle(nt, nz, n_cond, iteration):
     case, p_ref, F_ref = reference(nt, nz, n_cond)
     s = JointGapSolver.from_case(case, max_cond=9 if n_cond == 9 else 1)
     s.assemble(case.e, case.edot, case.delta, n_cond)
     cfg0 = s.pcg_config
-    assert (cfg0["threads_a"], cfg0["cols_per_thread_a"]) == SHAPES[nt][0]
-    assert (cfg0["threads_b"], cfg0["cols_per_thread_b"]) == SHAPES[nt][0]
+    for k in "abf":
+        assert (cfg0[f"threads_{k}"], cfg0[f"cols_per_thread_{k}"]) == SHAPES[nt][0]
     configs = []
-    for NT, Q in SHAPES[nt]:
-        occ = s.set_pcg_config(NT, Q, 1, 1)
-        for wa, wb in sorted({(1, 1), (occ["occupancy_a"], occ["occupancy_b"]), (1, occ["occupancy_b"])}):
-            configs.append(((NT, Q), (NT, Q), wa, wb))
-    configs.append((SHAPES[nt][-1], SHAPES[nt][0], 1, 1))          # A and B with different shapes
-    for (NA, QA), (NB, QB), wa, wb in configs:
-        cfg = s.set_pcg_config(NA, QA, wa, wb, threads_b=NB, cols_per_thread_b=QB)
-        log(f"case: {case.label} x{n_cond}, config {cfg}")
-        perr, ferr, info = check(s, case, n_cond, p_ref, F_ref)
+    if iteration == G.GAP_ITERATION_TWO_LAUNCH:
+        for NT, Q in SHAPES[nt]:
+            occ = s.set_pcg_config(NT, Q, 1, 1)
+            for wa, wb in sorted({(1, 1), (occ["occupancy_a"], occ["occupancy_b"]), (1, occ["occupancy_b"])}):
+                configs.append(dict(threads=NT, cols_per_thread=Q, wg_per_cu_a=wa, wg_per_cu_b=wb))
+        NA, QA = SHAPES[nt][-1]
+        NB, QB = SHAPES[nt][0]                                        # A and B with different shapes
+        configs.append(dict(threads=NA, cols_per_thread=QA, wg_per_cu_a=1, wg_per_cu_b=1, threads_b=NB,
+                            cols_per_thread_b=QB))
+    else:
+        d = SHAPES[nt][0]
+        for NT, Q in SHAPES[nt]:
+            occ = s.set_pcg_config(d[0], d[1], 1, 1, threads_f=NT, cols_per_thread_f=Q, wg_per_cu_f=1)
+            for wf in sorted({1, occ["occupancy_f"]}):
+                configs.append(dict(threads=d[0], cols_per_thread=d[1], wg_per_cu_a=1, wg_per_cu_b=1, threads_f=NT,
+                                    cols_per_thread_f=Q, wg_per_cu_f=wf))
+    for kw in configs:
+        cfg = s.set_pcg_config(**kw)
+        log(f"case: {case.label} x{n_cond}, iteration kind {iteration}, config {cfg}")
+        perr, ferr, info = check(s, case, n_cond, p_ref, F_ref, iteration)
         log(f"  iterations {info.iterations}, pressure {perr:.2e}, forces {ferr:.2e}")
         assert perr <= P_TOL and ferr <= F_TOL
     s.close()
 
 
-def test_autotuner_choice_is_valid_and_matches_oracle():
+@ITERATIONS
+def test_autotuner_choice_is_valid_and_matches_oracle(iteration):
     case, p_ref, F_ref = reference(300, 23, 9)
-    log(f"case: {case.label}, autotuner")
+    log(f"case: {case.label}, autotuner, iteration kind {iteration}")
     s = JointGapSolver.from_case(case, max_cond=9)
     s.assemble(case.e, case.edot, case.delta, 9)
-    cfg, us = s.tune(iterations=10, omega=case.omega)
+    cfg, us = s.tune(iterations=10, omega=case.omega, iteration=iteration)
     log(f"  tuned {cfg}, {us:.1f} us per iteration")
-    assert (cfg["threads_a"], cfg["cols_per_thread_a"]) in SHAPES[300]
-    assert (cfg["threads_b"], cfg["cols_per_thread_b"]) in SHAPES[300]
-    assert 1 <= cfg["wg_per_cu_a"] <= cfg["occupancy_a"] and 1 <= cfg["wg_per_cu_b"] <= cfg["occupancy_b"]
+    for k in "abf":
+        assert (cfg[f"threads_{k}"], cfg[f"cols_per_thread_{k}"]) in SHAPES[300]
+        assert 1 <= cfg[f"wg_per_cu_{k}"] <= cfg[f"occupancy_{k}"]
     assert us > 0.0 and s.pcg_config == cfg
-    perr, ferr, _ = check(s, case, 9, p_ref, F_ref)   # the system survives tuning unchanged
+    perr, ferr, _ = check(s, case, 9, p_ref, F_ref, iteration)   # the system survives tuning unchanged
     assert perr <= P_TOL and ferr <= F_TOL
     d = s.set_pcg_config()
-    assert (d["threads_a"], d["cols_per_thread_a"]) == SHAPES[300][0] == (d["threads_b"], d["cols_per_thread_b"])
+    for k in "abf":
+        assert (d[f"threads_{k}"], d[f"cols_per_thread_{k}"]) == SHAPES[300][0]
     s.close()
 
 
@@ -109,6 +127,15 @@ def test_configuration_validation():
     with pytest.raises(G.GapError) as ei:
         s.set_pcg_config(512, 1, 1, 1, threads_b=64, cols_per_thread_b=1)     # B shape too small
     assert ei.value.status == G.GAP_EINVAL
+    with pytest.raises(G.GapError) as ei:
+        s.set_pcg_config(512, 1, 1, 1, threads_f=64, cols_per_thread_f=1)     # F shape too small
+    assert ei.value.status == G.GAP_EINVAL
+    with pytest.raises(G.GapError) as ei:
+        s.set_pcg_config(512, 1, 1, 1, wg_per_cu_f=9)
+    assert ei.value.status == G.GAP_EINVAL
+    with pytest.raises(G.GapError) as ei:                                     # unknown iteration kind
+        s.solve(eps=1e-10, iteration=2)
+    assert ei.value.status == G.GAP_EINVAL
     s.assemble(case.e, case.edot, None, 1)
     with pytest.raises(G.GapError) as ei:
         G.gap_tune_pcg(s.handle, s.options(), s.p.data_ptr(), 1)
@@ -116,22 +143,23 @@ def test_configuration_validation():
     s.close()
 
 
-def test_iteration_limited_solve_launches_no_idle_block():
+@ITERATIONS
+def test_iteration_limited_solve_launches_no_idle_block(iteration):
     """max_iter = 40 with blocks of 16: 16 + 16 iterations, then the 8 remaining and the
-    closing A launch; no block of idle launches."""
+    closing launch (A, or the one-launch kernel); no block of idle launches."""
     case = synth.smooth_case(128, 64, 2)
-    log(f"case: {case.label}, max_iter 40, check_every 16")
+    log(f"case: {case.label}, max_iter 40, check_every 16, iteration kind {iteration}")
     s = JointGapSolver.from_case(case, max_cond=9)
     s.assemble(case.e, case.edot, case.delta, 9)
     G.gap_kernel_timing(s.handle, 1)
-    _, info = s.solve(omega=1.8, eps=1e-300, max_iter=40, check_every=16, raise_on_error=False)
-    na, _ = G.gap_kernel_stats(s.handle, G.GAP_KERNEL_PCG_A)
-    nb, _ = G.gap_kernel_stats(s.handle, G.GAP_KERNEL_PCG_B)
+    kw = dict(omega=1.8, eps=1e-300, max_iter=40, raise_on_error=False, iteration=iteration)
+    _, info = s.solve(check_every=16, **kw)
+    n = [G.gap_kernel_stats(s.handle, k)[0] for k in range(G.GAP_KERNEL_COUNT)]
     G.gap_kernel_timing(s.handle, 0)
     assert info.iterations == 40 and info.status == G.GAP_ENOCONV
-    assert (na, nb) == (41, 40)
-    # the same iterate as an uninterrupted run of 40 iterations in one block
+    assert n == ([41, 40, 0] if iteration == G.GAP_ITERATION_TWO_LAUNCH else [0, 0, 41])
+    # the same iterate as an uninterrupted run of 40 iterations in one block (graph replay)
     p1 = s.p.clone()
-    s.solve(omega=1.8, eps=1e-300, max_iter=40, check_every=40, raise_on_error=False)
+    s.solve(check_every=40, **kw)
     assert torch.equal(p1, s.p)
     s.close()
