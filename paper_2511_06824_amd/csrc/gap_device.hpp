@@ -88,3 +88,15 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
 }
 
 __device__ __forceinline__ bool finite_d(double x) { return x - x == 0.0; }
+
+// Global-memory views of generic pointers.  Kernels that read their buffer addresses from a
+// record in device memory see generic pointers, for which the compiler emits flat loads and
+// stores; those count against the LDS wait counter as well, so every wait for an LDS read
+// also waits for all outstanding memory loads (including loads issued a row step ahead).
+// Accesses through these views are global instructions, counted on the memory counter only.
+#define GAP_AS1 __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GAP_AS1 T* as_global(T* p)
+{
+    return (GAP_AS1 T*)p;
+}

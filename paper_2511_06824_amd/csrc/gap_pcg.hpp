@@ -14,6 +14,10 @@
 // (east wrap of the last column in L, west wrap of the first column in L^T) stay inside one
 // workgroup.  The chunk of rows [j0, j1) reads one or two halo rows on each side.
 //
+// Buffer addresses come from the request record in device memory; the kernels access them
+// through global-memory views (as_global), so that waits for LDS reads do not also wait for
+// the loads in flight.
+//
 // Cache hints: the row-by-row z and u_prev loads and the u stores of A, and the p loads and z
 // stores of B, are non-temporal.  Those streams are not re-read within a launch (the first
 // rows of a chunk, which neighbouring chunks also read as halo, keep normal loads), and
@@ -175,11 +179,11 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
     extern __shared__ double lds[];
     double* su = lds;             // [2][nt]  u of the current row, by row parity
     const int op = a.op[c];
-    const double* kx = a.kx + (size_t)op * n;
-    const double* kz = a.kz + (size_t)op * (n + nt);
-    const double* zc = a.z + (size_t)c * n;
-    const double* ui = a.u[(j + 1) & 1] + (size_t)c * n;
-    double* uo = a.u[j & 1] + (size_t)c * n;
+    const GAP_AS1 double* kx = as_global(a.kx + (size_t)op * n);
+    const GAP_AS1 double* kz = as_global(a.kz + (size_t)op * (n + nt));
+    const GAP_AS1 double* zc = as_global(a.z + (size_t)c * n);
+    const GAP_AS1 double* ui = as_global(a.u[(j + 1) & 1] + (size_t)c * n);
+    GAP_AS1 double* uo = as_global(a.u[j & 1] + (size_t)c * n);
     const bool first = (j == 0);
     const int t = threadIdx.x;
 
@@ -387,14 +391,14 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
     const bool spmv = !INIT || a.warm;
     const bool assor = (a.precond == 2);
     const int op = a.op[c];
-    const double* kx = a.kx + (size_t)op * n;
-    const double* kz = a.kz + (size_t)op * (n + nt);
-    const double* mv = assor ? nullptr : a.minv + (size_t)op * n;
-    const double* uu = (INIT ? a.p : a.u[j & 1]) + (size_t)c * n;
-    const double* rin = (INIT ? a.S : a.r[j & 1]) + (size_t)c * n;
-    double* rout = a.r[(j + 1) & 1] + (size_t)c * n;
-    double* pp = a.p + (size_t)c * n;
-    double* zz = a.z + (size_t)c * n;
+    const GAP_AS1 double* kx = as_global(a.kx + (size_t)op * n);
+    const GAP_AS1 double* kz = as_global(a.kz + (size_t)op * (n + nt));
+    const GAP_AS1 double* mv = as_global(assor ? a.kx : a.minv + (size_t)op * n);   // read only when !assor
+    const GAP_AS1 double* uu = as_global((INIT ? a.p : a.u[j & 1]) + (size_t)c * n);
+    const GAP_AS1 double* rin = as_global((INIT ? a.S : a.r[j & 1]) + (size_t)c * n);
+    GAP_AS1 double* rout = as_global(a.r[(j + 1) & 1] + (size_t)c * n);
+    GAP_AS1 double* pp = as_global(a.p + (size_t)c * n);
+    GAP_AS1 double* zz = as_global(a.z + (size_t)c * n);
     const double om = a.omega;
     const double scale = om * (2.0 - om);
 

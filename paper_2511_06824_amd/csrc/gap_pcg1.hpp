@@ -72,17 +72,19 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
     const bool spmv = !INIT || a.warm;
     const bool has_prev = !INIT && j > 0;
     const int op = a.op[c];
-    const double* kx = a.kx + (size_t)op * n;
-    const double* kz = a.kz + (size_t)op * (n + nt);
-    const double* mv = assor ? nullptr : a.minv + (size_t)op * n;
+    const GAP_AS1 double* kx = as_global(a.kx + (size_t)op * n);
+    const GAP_AS1 double* kz = as_global(a.kz + (size_t)op * (n + nt));
+    const GAP_AS1 double* mv = as_global(assor ? a.kx : a.minv + (size_t)op * n);   // read only when !assor
     const size_t co = (size_t)c * n;
-    const double* zin = (INIT ? a.p : a.zf[j & 1]) + co;    // the vector A multiplies: z_j (u_j after beta), p_0
-    const double* uin = a.u[(j + 1) & 1] + co;              // u_{j-1}
-    double* uout = a.u[j & 1] + co;
-    const double* rin = (INIT ? a.S : a.r[j & 1]) + co;
-    double* rout = a.r[(j + 1) & 1] + co;
-    double* zout = a.zf[(j + 1) & 1] + co;
-    double* pp = a.p + co;
+    // cell indices within one condition's vector are 32-bit (n <= 2^27): the loads and stores
+    // then take a scalar base and a 32-bit vector offset
+    const GAP_AS1 double* zin = as_global((INIT ? a.p : a.zf[j & 1]) + co);    // the vector A multiplies: z_j (u_j after beta), p_0
+    const GAP_AS1 double* uin = as_global(a.u[(j + 1) & 1] + co);              // u_{j-1}
+    GAP_AS1 double* uout = as_global(a.u[j & 1] + co);
+    const GAP_AS1 double* rin = as_global((INIT ? a.S : a.r[j & 1]) + co);
+    GAP_AS1 double* rout = as_global(a.r[(j + 1) & 1] + co);
+    GAP_AS1 double* zout = as_global(a.zf[(j + 1) & 1] + co);
+    GAP_AS1 double* pp = as_global(a.p + co);
 
     const int s_begin = max(j0 - 1, 0);
     const int s_stop = j1 + 1;              // steps s >= nz only drain the lagged stages
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
         kxn[q] = nzl[q] = nul[q] = nkz[q] = nr[q] = np[q] = 0.0;
         um_[q] = uc_[q] = up_[q] = 0.0;
         if (i < nt) {
-            const size_t g = (size_t)s_begin * nt + i;
+            const unsigned g = (unsigned)s_begin * nt + i;
             if (spmv) {
                 if (s_begin > 0) {
                     um[q] = zin[g - nt];
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
             }
             nzl[q] = nul[q] = kxn[q] = nkz[q] = nr[q] = np[q] = 0.0;
             if (i < nt && next) {
-                const size_t g1 = (size_t)(s + 1) * nt + i;
+                const unsigned g1 = (unsigned)(s + 1) * nt + i;
                 kxn[q] = kx[g1];
                 nkz[q] = kz[g1 + nt];
                 nr[q] = rin[g1];
@@ -260,21 +262,20 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
         }
         __syncthreads();
         // ---- P2 -------------------------------------------------------------------------
-        double rp[Q], dinv[Q], au[Q], kxc[Q], kW[Q];
+        double rp[Q], dinv[Q], au[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = t + q * NT;
-            rp[q] = dinv[q] = au[q] = kxc[q] = kW[q] = 0.0;
+            rp[q] = dinv[q] = au[q] = 0.0;
             if (i < nt) {
                 const int ie = (i + 1 < nt) ? i + 1 : 0;
                 if (real) {
                     const int iw = i ? i - 1 : nt - 1;
-                    kxc[q] = skc[i];
-                    kW[q] = skc[iw];
-                    const double D = ((kxc[q] + kW[q]) + kzS[q]) + kzN[q];
+                    const double kxc = skc[i], kW = skc[iw];
+                    const double D = ((kxc + kW) + kzS[q]) + kzN[q];
                     double r1 = rc[q];
                     if (spmv) {
-                        double v = D * uc[q] - kxc[q] * su[ie] - kW[q] * su[iw];
+                        double v = D * uc[q] - kxc * su[ie] - kW * su[iw];
                         if (s > 0) v -= kzS[q] * um[q];
                         if (s < nz - 1) v -= kzN[q] * up[q];
                         au[q] = v;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                     rp[q] = r1;
                     dinv[q] = 1.0 / D;
                     if (own) {
-                        const size_t g = (size_t)s * nt + i;
+                        const unsigned g = (unsigned)s * nt + i;
                         rout[g] = r1;
                         acc_rr += r1 * r1;
                         if (INIT) {
@@ -324,8 +325,8 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                 if (real) {
                     y = sy[i];
                     double lo = 0.0;
-                    if (i > 0) lo += kW[q] * sy[i - 1];
-                    if (i == nt - 1) lo += kxc[q] * sy[0];
+                    if (i > 0) lo += skc[i - 1] * sy[i - 1];            // west face of row s
+                    if (i == nt - 1) lo += skc[i] * sy[0];              // east wrap face
                     if (s > 0) lo += kzS[q] * yprev[q];
                     v = y + om * dinv[q] * lo;
                 }
@@ -342,11 +343,11 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                 }
                 yprev[q] = y;
             } else if (make_z) {
-                zv = mv[(size_t)(s - 1) * nt + i] * rpprev[q];
+                zv = mv[(unsigned)(s - 1) * nt + i] * rpprev[q];
             }
             if (make_z) {
                 if (own_z) {
-                    __builtin_nontemporal_store(zv, &zout[(size_t)(s - 1) * nt + i]);
+                    __builtin_nontemporal_store(zv, &zout[(unsigned)(s - 1) * nt + i]);
                     acc_rz += rpprev[q] * zv;
                     acc_zau += zv * aup[q];
                 }
