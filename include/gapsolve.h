@@ -115,8 +115,8 @@ typedef struct {
  *                (u and u^T A u; then alpha and the updates).  GAP_ITERATION_ONE_LAUNCH:
  *                one launch per iteration, with u^T A u = z^T A z + 2 beta z^T A u_prev +
  *                beta^2 u_prev^T A u_prev from sums the previous launch forms (A is
- *                symmetric).  The iterates agree up to rounding.  Batched solves
- *                (gap_batch_*) always use the two-launch iteration.                    */
+ *                symmetric).  The iterates agree up to rounding.  All requests of one
+ *                batch (gap_batch_*) use the same kind.                                */
 typedef struct {
     double omega, eps;
     int32_t max_iter, precond, neumann, scalars, warm_start, check_every, graph, strategy;
@@ -385,8 +385,10 @@ gap_status gap_batch_destroy(gap_batch_t batch);
  * residual on `stream` and returns the request id in *id.  The grid lends its Krylov
  * buffers and device record to the batch: until gap_batch_remove, assembling, solving,
  * tuning, re-configuring or destroying it returns GAP_ESTATE, and p and opts must stay
- * unchanged.  A grid is in at most one batch (GAP_EINVAL otherwise).  Errors: GAP_EINVAL,
- * GAP_ESTATE, GAP_EBUDGET (all 128 slots in use), GAP_ENOMEM, GAP_EDEVICE. */
+ * unchanged.  A grid is in at most one batch (GAP_EINVAL otherwise).  The first request
+ * of an empty batch fixes its iteration kind (opts->iteration); a request asking for the
+ * other kind returns GAP_EINVAL.  Errors: GAP_EINVAL, GAP_ESTATE, GAP_EBUDGET (all 128 slots
+ * in use), GAP_ENOMEM, GAP_EDEVICE. */
 gap_status gap_batch_add(gap_batch_t batch, gap_grid_t grid, const gap_solver_opts *opts, double *p, int32_t *id,
                          void *stream);
 

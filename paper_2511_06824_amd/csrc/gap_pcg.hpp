@@ -72,6 +72,8 @@ struct PcgDev {
     // z^T A u, u^T A u) of fstride slots
     double* fpart[2];
     int fstride;
+    int par_off;                // one-launch iteration: the request's iteration parity is the
+                                // launch parity xor par_off (batches; 0 for a solve of its own)
     PcgScalars* sc;
     int op[GAP_MAXC];
     int nt, nz, n_cond;

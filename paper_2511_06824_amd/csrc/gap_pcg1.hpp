@@ -26,8 +26,10 @@
 // Buffers that one launch both reads (with halo rows) and writes alternate by iteration
 // parity: u, r, z and the partial sums.  The iteration index and the per-condition r.z that
 // the next launch divides by sit in the device record by launch parity `par`: launch j reads
-// slot [par] and its record writer fills [par ^ 1].  The host alternates par, starting at 0
-// after the initial launch; launches after the solve has stopped return at once.
+// slot [par] and its record writer fills [par ^ 1].  The host alternates the launch parity,
+// starting at 0 after the initial launch; a batch, whose requests join at different launches,
+// gives each request an offset (par = launch parity xor par_off).  Launches after a solve has
+// stopped return at once.
 //
 // Row pipeline, one row step s per loop trip, two barriers per step:
 //   P1  u and the east-face conductances of row s to LDS; loads of step s + 1 issued
@@ -46,11 +48,12 @@ constexpr int kOnePassParts = 5;   // r.z, r.r, z^T A z, z^T A u, u^T A u
 // r.z, r.r, z^T A z, S.S; the record is reset and the next launch runs with par = 0.
 template <int NT, int Q, bool INIT>
 __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __restrict__ reqs,
-                                                                 const int* __restrict__ work, int par)
+                                                                 const int* __restrict__ work, int launch_par)
 {
     int req, c, kc;
     if (!pcg_work(work, blockIdx.x, req, c, kc)) return;
     const PcgDev& a = reqs[req];
+    const int par = (launch_par ^ a.par_off) & 1;
     if (!INIT && a.sc->done) return;
     const int nt = a.nt, nz = a.nz;
     const int j0 = kc * a.rows_b, j1 = min(j0 + a.rows_b, nz), slot = c * a.chunks_b + kc;

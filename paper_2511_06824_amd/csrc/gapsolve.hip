@@ -1527,6 +1527,8 @@ struct gap_batch_s {
         gap_grid_t g = nullptr;
         bool done = false;
         bool held = false;                                   // excluded from the launches until released
+        bool scheduled = false;                              // in the launches of the current schedule
+        long f_count = 0;                                    // one-launch kernel launches that included it
     };
     std::vector<Req> reqs;
     PcgDev *reqs_dev = nullptr, *reqs_host = nullptr;        // slot-indexed request records
@@ -1537,11 +1539,13 @@ struct gap_batch_s {
     bool dirty = true;
     int* init_work = nullptr;
     size_t init_cap = 0;
-    int occ_a = 1, occ_b = 1, cus = 256;
+    int occ_a = 1, occ_b = 1, occ_f = 1, cus = 256;
     PcgShape shape = pcg_candidates(2048)[0];            // the shape of the largest ring
+    int mode = GAP_ITERATION_ONE_LAUNCH;                     // iteration kind of the requests (set by the first)
+    long launches = 0;                                       // one-launch kernel launches so far
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
-    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0;
+    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0, exec_par0 = 0;
     const int* exec_work = nullptr;
     int next_id = 1;
 };
@@ -1624,11 +1628,15 @@ gap_status gap_batch_create(gap_batch_t* out)
     int occ_b = 1, occ_i = 1;
     if (e == hipSuccess) e = pcg_prepare(b->shape, 1, kBatchShape, &occ_b);
     if (e == hipSuccess) e = pcg_prepare(b->shape, 2, kBatchShape, &occ_i);
+    int occ_f = 1, occ_fi = 1;
+    if (e == hipSuccess) e = pcg_prepare(b->shape, kPcgOne, kBatchShape, &occ_f);
+    if (e == hipSuccess) e = pcg_prepare(b->shape, kPcgOneInit, kBatchShape, &occ_fi);
     if (e != hipSuccess) {
         batch_release(b);
         return fail(GAP_EDEVICE, "creating the batch: %s", hipGetErrorString(e));
     }
     b->occ_b = std::min(occ_b, occ_i);
+    b->occ_f = std::min(occ_f, occ_fi);
     *out = b;
     return GAP_OK;
 }
@@ -1649,6 +1657,10 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "gap_batch_add needs an assembled grid");
     if (g->batch) return fail(GAP_EINVAL, "this grid is already in a batch");
+    if (!b->reqs.empty() && o->iteration != b->mode)
+        return fail(GAP_EINVAL, "the requests of a batch share one iteration kind (the batch runs %s launches)",
+                    b->mode == GAP_ITERATION_ONE_LAUNCH ? "one-launch" : "two-launch");
+    const bool one = o->iteration == GAP_ITERATION_ONE_LAUNCH;
     int slot = -1;
     std::vector<bool> used(gap_batch_s::kCap, false);
     for (const auto& r : b->reqs) used[r.slot] = true;
@@ -1673,8 +1685,15 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     fill_pcg(g, a, o);
     // chunking depends only on the request and the batch kernel shape, so a request gets
     // the same reduction order (bitwise the same result) alone and in any mix
-    pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_a * b->cus, a.chunks_a, a.rows_a);
-    pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_b * b->cus, a.chunks_b, a.rows_b);
+    if (one) {
+        pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_f * b->cus, a.chunks_b, a.rows_b);
+        a.chunks_a = a.chunks_b;
+        a.rows_a = a.rows_b;
+    } else {
+        pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_a * b->cus, a.chunks_a, a.rows_a);
+        pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_b * b->cus, a.chunks_b, a.rows_b);
+    }
+    a.par_off = 0;                               // set when the request enters a schedule
     HIPCHK(hipStreamSynchronize(st));
     b->reqs_host[slot] = a;
     HIPCHK(hipMemcpyAsync(b->reqs_dev + slot, b->reqs_host + slot, sizeof(PcgDev), hipMemcpyHostToDevice, st));
@@ -1685,7 +1704,8 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     gap_status es = ensure_ints(&b->init_work, &b->init_cap, tb.size());
     if (es != GAP_OK) return es;
     HIPCHK(hipMemcpyAsync(b->init_work, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    hipError_t le = launch_pcg(b->shape, 2, kBatchShape, b->reqs_dev, b->init_work, (int)tb.size(), st);
+    hipError_t le = launch_pcg(b->shape, one ? kPcgOneInit : kPcgInit, kBatchShape, b->reqs_dev, b->init_work,
+                               (int)tb.size(), st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
     HIPCHK(hipStreamSynchronize(st));
 
@@ -1693,6 +1713,7 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     r.id = b->next_id++;
     r.slot = slot;
     r.g = g;
+    b->mode = o->iteration;
     g->batch = b;
     b->reqs.push_back(r);
     b->dirty = true;
@@ -1705,13 +1726,24 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
     if (!b) return fail(GAP_EINVAL, "batch is NULL");
     if (iterations < 1) return fail(GAP_EINVAL, "iterations must be >= 1");
     hipStream_t st = (hipStream_t)stream;
+    const bool one = b->mode == GAP_ITERATION_ONE_LAUNCH;
     if (b->dirty) {
         std::vector<std::vector<int>> ga, gb;
-        for (const auto& r : b->reqs) {
-            if (r.done || r.held) continue;
-            const PcgDev& a = b->reqs_host[r.slot];
-            pcg_groups(r.slot, a.chunks_a, a.n_cond, a.op, ga);
+        for (auto& r : b->reqs) {
+            r.scheduled = !(r.done || r.held);
+            if (!r.scheduled) continue;
+            PcgDev& a = b->reqs_host[r.slot];
+            if (!one) pcg_groups(r.slot, a.chunks_a, a.n_cond, a.op, ga);
             pcg_groups(r.slot, a.chunks_b, a.n_cond, a.op, gb);
+            if (one) {
+                // the request's next iteration has the parity of its own launch count
+                const int off = (int)((r.f_count ^ b->launches) & 1);
+                if (a.par_off != off) {
+                    a.par_off = off;
+                    HIPCHK(hipMemcpyAsync(b->reqs_dev + r.slot, b->reqs_host + r.slot, sizeof(PcgDev),
+                                          hipMemcpyHostToDevice, st));
+                }
+            }
         }
         const std::vector<int> ta = pcg_schedule(ga), tb = pcg_schedule(gb);
         gap_status es = ensure_ints(&b->work, &b->work_cap, ta.size() + tb.size() + 1);
@@ -1724,17 +1756,18 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
         b->blocks_b = (int)tb.size();
         b->dirty = false;
     }
-    if (b->blocks_a > 0) {
+    if ((one ? b->blocks_b : b->blocks_a) > 0) {
         const int* wa = b->work;
         const int* wb = b->work + b->blocks_a;
+        const int par0 = one ? (int)(b->launches & 1) : 0;
         if (use_graph) {
             if (!b->exec || b->exec_iters != iterations || b->exec_blocks_a != b->blocks_a ||
-                b->exec_blocks_b != b->blocks_b || b->exec_work != b->work) {
+                b->exec_blocks_b != b->blocks_b || b->exec_work != b->work || b->exec_par0 != par0) {
                 if (b->exec) (void)hipGraphExecDestroy(b->exec);
                 b->exec = nullptr;
                 if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, b->shape, kBatchShape, b->reqs_dev, wa, b->blocks_a, wb,
-                                              b->blocks_b, &b->exec);
+                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, b->shape, kBatchShape, b->reqs_dev, wa,
+                                              b->blocks_a, wb, b->blocks_b, &b->exec, one, par0);
                 if (ce != hipSuccess) {
                     b->exec = nullptr;
                     return fail(GAP_EDEVICE, "capturing the batch block: %s", hipGetErrorString(ce));
@@ -1743,14 +1776,25 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
                 b->exec_blocks_a = b->blocks_a;
                 b->exec_blocks_b = b->blocks_b;
                 b->exec_work = b->work;
+                b->exec_par0 = par0;
             }
             HIPCHK(hipGraphLaunch(b->exec, st));
         } else {
             for (int it = 0; it < iterations; ++it) {
-                hipError_t le = launch_pcg(b->shape, 0, kBatchShape, b->reqs_dev, wa, b->blocks_a, st);
-                if (le == hipSuccess) le = launch_pcg(b->shape, 1, kBatchShape, b->reqs_dev, wb, b->blocks_b, st);
+                hipError_t le;
+                if (one) {
+                    le = launch_pcg(b->shape, kPcgOne, kBatchShape, b->reqs_dev, wb, b->blocks_b, st, (par0 + it) & 1);
+                } else {
+                    le = launch_pcg(b->shape, kPcgA, kBatchShape, b->reqs_dev, wa, b->blocks_a, st);
+                    if (le == hipSuccess) le = launch_pcg(b->shape, kPcgB, kBatchShape, b->reqs_dev, wb, b->blocks_b, st);
+                }
                 if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of a batch iteration: %s", hipGetErrorString(le));
             }
+        }
+        if (one) {
+            b->launches += iterations;
+            for (auto& r : b->reqs)
+                if (r.scheduled) r.f_count += iterations;
         }
     }
     hipLaunchKernelGGL(k_gather_records, dim3(1), dim3(gap_batch_s::kCap), 0, st, (const PcgDev*)b->reqs_dev,

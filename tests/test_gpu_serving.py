@@ -27,19 +27,32 @@ CASES = [synth.smooth_case(64, 32, 0), synth.textured_case(128, 64, 1), synth.sm
          synth.textured_case(256, 128, 3), synth.smooth_case(96, 48, 4, eps=1e-12)]
 
 
-def batch_solve(cases, eps_override=None, iters=8, use_graph=True):
-    """Solve the cases together in one batch; returns pressures, infos by case index."""
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                                     ids=["two_launch", "one_launch"])
+
+
+def batch_solve(cases, eps_override=None, iters=8, use_graph=True, iteration=G.GAP_ITERATION_ONE_LAUNCH,
+                join_every=0):
+    """Solve the cases together in one batch; returns pressures, infos by case index.
+    join_every > 0: the cases join one at a time, one step of `iters` iterations apart."""
     b = G.gap_batch_create()
     stream = torch.cuda.current_stream().cuda_stream
     solvers, ids = [], []
-    for c in cases:
+    pending = list(cases)
+    out = {}
+
+    def add(c):
         s = JointGapSolver.from_case(c, max_cond=9)
         s.assemble(c.e, c.edot, c.delta, 9)
-        opts = s.options(omega=c.omega, eps=eps_override or c.eps)
+        opts = s.options(omega=c.omega, eps=eps_override or c.eps, iteration=iteration)
         ids.append(G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream))
         solvers.append((s, opts))
-    out = {}
+
+    while pending and (not join_every or not ids):
+        add(pending.pop(0))
     while len(out) < len(cases):
+        if pending and join_every:
+            add(pending.pop(0))
         G.gap_batch_step(b, iters, use_graph, stream)
         for bid in G.gap_batch_poll(b):
             k = ids.index(bid)
@@ -52,20 +65,74 @@ def batch_solve(cases, eps_override=None, iters=8, use_graph=True):
     return out
 
 
-def test_results_alone_and_in_the_mix_are_bitwise_equal():
-    log("case: batch mix of 5 grids vs each alone")
-    mix = batch_solve(CASES)
+@ITERATIONS
+def test_results_alone_and_in_the_mix_are_bitwise_equal(iteration):
+    log(f"case: batch mix of 5 grids vs each alone, iteration kind {iteration}")
+    mix = batch_solve(CASES, iteration=iteration)
+    staggered = batch_solve(CASES, iteration=iteration, iters=7, join_every=1)   # joins at odd launch counts
     for k, c in enumerate(CASES):
-        alone = batch_solve([c])[0]
-        assert alone[1] == mix[k][1]
-        assert np.array_equal(alone[0], mix[k][0]), c.label
-        assert np.array_equal(alone[2], mix[k][2]), c.label
+        alone = batch_solve([c], iteration=iteration)[0]
+        for other in (mix[k], staggered[k]):
+            assert alone[1] == other[1]
+            assert np.array_equal(alone[0], other[0]), c.label
+            assert np.array_equal(alone[2], other[2]), c.label
 
 
-def test_batched_results_match_the_oracle():
-    log("case: batch mix vs oracle")
+def test_one_launch_batch_matches_a_solve_of_its_own():
+    """A request in a one-launch batch, joining at an odd launch count, takes the iterations
+    of the same grid solved by solve_joint_pcg (its chunking follows the batch shape, so the
+    iterates agree up to the summation order)."""
+    c = synth.textured_case(192, 64, 10)
+    log(f"case: {c.label}, batch vs own solve")
+    got = batch_solve([CASES[0], c], iters=5, join_every=1, eps_override=1e-12)[1]
+    s = JointGapSolver.from_case(c, max_cond=9)
+    s.assemble(c.e, c.edot, c.delta, 9)
+    p, info = s.solve(omega=c.omega, eps=1e-12)
+    p = p.cpu().numpy()
+    s.close()
+    assert abs(info.iterations - got[1]) <= 1
+    for k in range(9):
+        assert np.linalg.norm(got[0][k] - p[k]) <= 1e-10 * np.linalg.norm(p[k])
+
+
+def test_batch_refuses_a_second_iteration_kind():
+    log("case: batch with mixed iteration kinds")
+    b = G.gap_batch_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    made = []
+    for k, it in enumerate((G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_TWO_LAUNCH)):
+        c = synth.smooth_case(64, 32, 30 + k)
+        s = JointGapSolver.from_case(c, max_cond=9)
+        s.assemble(c.e, c.edot, c.delta, 9)
+        made.append(s)
+        opts = s.options(omega=c.omega, eps=c.eps, iteration=it)
+        if k == 0:
+            bid = G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
+        else:
+            with pytest.raises(G.GapError) as ei:
+                G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
+            assert ei.value.status == G.GAP_EINVAL
+    while not G.gap_batch_poll(b):
+        G.gap_batch_step(b, 16, True, stream)
+    G.gap_batch_remove(b, bid, stream)
+    # empty again: the next request sets the kind
+    s = made[1]
+    opts = s.options(omega=1.6, eps=1e-10, iteration=G.GAP_ITERATION_TWO_LAUNCH)
+    bid = G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
+    while not G.gap_batch_poll(b):
+        G.gap_batch_step(b, 16, True, stream)
+    _, info = G.gap_batch_remove(b, bid, stream)
+    assert info.status == G.GAP_OK
+    for s in made:
+        s.close()
+    G.gap_batch_destroy(b)
+
+
+@ITERATIONS
+def test_batched_results_match_the_oracle(iteration):
+    log(f"case: batch mix vs oracle, iteration kind {iteration}")
     cases = [synth.smooth_case(64, 32, 5), synth.textured_case(96, 48, 6)]
-    got = batch_solve(cases, eps_override=1e-13, use_graph=False)
+    got = batch_solve(cases, eps_override=1e-13, use_graph=False, iteration=iteration)
     for k, c in enumerate(cases):
         gap, tex = gap_of(c), texture_of(c)
         for j, (ek, edk) in enumerate(oracle.conditions(c.e, c.edot, c.delta)):
@@ -76,10 +143,11 @@ def test_batched_results_match_the_oracle():
             assert np.linalg.norm(Fg[:2] - F[:2]) <= 1e-8 * np.linalg.norm(F[:2])
 
 
-def test_graph_and_plain_batch_steps_agree_bitwise():
-    log("case: batch graph vs plain steps")
-    a = batch_solve(CASES[:3], use_graph=True)
-    b = batch_solve(CASES[:3], use_graph=False)
+@ITERATIONS
+def test_graph_and_plain_batch_steps_agree_bitwise(iteration):
+    log(f"case: batch graph vs plain steps, iteration kind {iteration}")
+    a = batch_solve(CASES[:3], use_graph=True, iters=7, iteration=iteration)
+    b = batch_solve(CASES[:3], use_graph=False, iters=7, iteration=iteration)
     for k in range(3):
         assert np.array_equal(a[k][0], b[k][0]) and a[k][1] == b[k][1]
 
@@ -105,25 +173,28 @@ def test_server_drains_a_poisson_stream():
     assert all(np.all(np.isfinite(r.F)) and np.all(np.isfinite(r.J)) for r in done)
 
 
-def test_held_request_keeps_its_state_and_result():
-    """A held request does not advance; released, it finishes bitwise as when run alone."""
-    log("case: batch hold and release")
+@ITERATIONS
+def test_held_request_keeps_its_state_and_result(iteration):
+    """A held request does not advance; released, it finishes bitwise as when run alone.  It
+    is held after an odd number of its own iterations, while the batch steps by 7."""
+    log(f"case: batch hold and release, iteration kind {iteration}")
     cases = [synth.smooth_case(128, 64, 7), synth.textured_case(96, 48, 8)]
-    alone = batch_solve([cases[1]])[0]
+    alone = batch_solve([cases[1]], iteration=iteration)[0]
     b = G.gap_batch_create()
     stream = torch.cuda.current_stream().cuda_stream
     solvers, ids = [], []
     for c in cases:
         s = JointGapSolver.from_case(c, max_cond=9)
         s.assemble(c.e, c.edot, c.delta, 9)
-        opts = s.options(omega=c.omega, eps=c.eps)
+        opts = s.options(omega=c.omega, eps=c.eps, iteration=iteration)
         ids.append(G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream))
         solvers.append(s)
+    G.gap_batch_step(b, 7, True, stream)
     G.gap_batch_hold(b, ids[1], 1)
     for _ in range(3):
         G.gap_batch_step(b, 8, True, stream)
     p_held = solvers[1].pressure().clone()
-    G.gap_batch_step(b, 8, True, stream)
+    G.gap_batch_step(b, 7, True, stream)
     assert torch.equal(p_held, solvers[1].pressure())        # no launch touched it
     G.gap_batch_hold(b, ids[1], 0)
     result = None
