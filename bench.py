@@ -273,6 +273,7 @@ def main():
     ap.add_argument("--no-study", action="store_true", help="skip the preconditioner / omega study")
     ap.add_argument("--no-dynamics", action="store_true", help="skip the general-iteration time steps")
     ap.add_argument("--no-two-launch", action="store_true", help="skip the two-launch iteration comparison")
+    ap.add_argument("--no-seeds", action="store_true", help="skip the two extra seeds of the workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
@@ -398,6 +399,42 @@ def main():
                           "traffic": (sum(recorded_traffic(k) or 0 for k in stats if k in nbytes)
                                       if all(recorded_traffic(k) for k in stats if k in nbytes) else None)}
 
+    # Lanczos estimate of the preconditioned spectrum from the device-recorded PCG scalars of
+    # one more solve (outside the timed region)
+    from paper_2511_06824_amd.diagnostics import condition_estimate
+    G.gap_pcg_history(solver.handle, 16384)
+    solver.assemble(case.e, case.edot, case.delta, 9)
+    _, info_h = solver.solve(opts)
+    alpha_h, beta_h = G.gap_get_pcg_history(solver.handle, 16384)
+    G.gap_pcg_history(solver.handle, 0)
+    lam_lo, lam_hi, kappa = condition_estimate(alpha_h, beta_h)
+    spectrum = {"lambda_min": lam_lo, "lambda_max": lam_hi, "kappa": kappa,
+                "kappa_x_unit_roundoff": kappa * 2.0 ** -53, "iterations": info_h.iterations,
+                "true_rel_residual": info_h.true_rel_residual,
+                "method": "Lanczos tridiagonal of the recorded alpha, beta (global joint recurrence)"}
+    print(f"bench: spectrum {spectrum}", file=sys.stderr, flush=True)
+
+    # the same workload at two more seeds (other dimple depths and eccentricities), with the
+    # tuned configuration: one warm step, one timed step each
+    seeds = None
+    if not args.no_seeds:
+        seeds = []
+        cfg_struct = G.gap_get_pcg_config(solver.handle)
+        for sd in (args.seed + 1, args.seed + 2):
+            c2 = synth.make_case(args.workload, sd)
+            s2 = JointGapSolver.from_case(c2, max_cond=9, device=dev)
+            G.gap_set_pcg_config(s2.handle, cfg_struct)
+            o2 = s2.options(omega=c2.omega, eps=c2.eps)
+            s2.step(c2.e, c2.edot, c2.delta, o2)
+            torch.cuda.synchronize()
+            ts0 = time.perf_counter()
+            _, _, info2 = s2.step(c2.e, c2.edot, c2.delta, o2)
+            torch.cuda.synchronize()
+            seeds.append({"seed": sd, "solves_per_s": round(1.0 / (time.perf_counter() - ts0), 5),
+                          "iterations": info2.iterations, "true_rel_residual": info2.true_rel_residual})
+            s2.close()
+            print(f"bench: seed {seeds[-1]}", file=sys.stderr, flush=True)
+
     plain = None
     if not args.no_plain:
         plain = run_plain(case, G, JointGapSolver, dev, tune=not args.no_tune)
@@ -435,7 +472,7 @@ def main():
         "true_rel_residual": max(true_rel),
         "graph_solves_per_s": round(graph_solves_per_s, 5),
         "pcg_config": solver.pcg_config, "tune": tune, "per_condition_scalars": per_cond,
-        "two_launch_iteration": two_launch,
+        "two_launch_iteration": two_launch, "spectrum": spectrum, "other_seeds": seeds,
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},

@@ -312,6 +312,24 @@ enum {
 gap_status gap_kernel_timing(gap_grid_t grid, int32_t enable);
 gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, double *total_ms);
 
+/* Measurement support: record the PCG scalars of every iteration of the following solves of
+ * this handle (Table 1 steps 3 and 9): alpha_j and beta_{j-1}, the beta that formed u_j (0 at
+ * j = 0), for iterations j < capacity.  With GLOBAL scalars they are the joint recurrence's;
+ * with PER_COND, condition 0's.  They define the Lanczos tridiagonal of the preconditioned
+ * operator, whose extreme eigenvalues estimate the condition number that bounds the
+ * attainable accuracy.  Device memory: 16 B per recorded iteration, held by the handle.
+ * capacity 0 stops recording and frees the buffer.  Errors: GAP_EINVAL (NULL grid,
+ * capacity outside [0, 2^24]), GAP_ESTATE (grid in a batch), GAP_ENOMEM, GAP_EDEVICE. */
+gap_status gap_pcg_history(gap_grid_t grid, int32_t capacity);
+
+/* Copy the scalars recorded during the last solve of this handle (solve_joint_pcg or a solve
+ * inside jacobian_adjoint, solve_with_adjoint, general_iteration_step) to host arrays of cap
+ * doubles: alpha[j], beta[j] for j < *count = min(that solve's iterations, capacity, cap).
+ * Synchronizes stream.  Errors: GAP_EINVAL (NULL argument, cap < 0), GAP_ESTATE (not
+ * recording), GAP_EDEVICE. */
+gap_status gap_get_pcg_history(gap_grid_t grid, double *alpha, double *beta, int32_t cap, int32_t *count,
+                               void *stream);
+
 /* ---- Launch configuration of the PCG iteration kernels (tuning; no effect on the method).
  * A workgroup of `threads` threads owns whole rings of one condition (thread t handles the
  * columns t, t + threads, ...; threads * cols_per_thread >= n_theta) and marches over a

@@ -74,6 +74,8 @@ struct PcgDev {
     int fstride;
     int par_off;                // one-launch iteration: the request's iteration parity is the
                                 // launch parity xor par_off (batches; 0 for a solve of its own)
+    double* hist;               // or null: alpha_j at [2j], beta_{j-1} at [2j+1], j < hist_cap
+    int hist_cap;               // (measurement: the scalars of condition 0's recurrence)
     PcgScalars* sc;
     int op[GAP_MAXC];
     int nt, nz, n_cond;
@@ -293,6 +295,7 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
         s->active_b = (int)active;
         s->status = bad ? -4 : (converged ? 0 : (j >= a.max_iter ? -3 : 0));
         if (stop) s->done = 1;
+        if (a.hist && !stop && j < a.hist_cap) a.hist[2 * j + 1] = beta;
     }
     if (stop || !(active & (1u << c))) return;
 
@@ -468,7 +471,10 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_b(const PcgDev* __
             }
             return;
         }
-        if (writer && threadIdx.x == 0) a.sc->iter_a = j + 1;
+        if (writer && threadIdx.x == 0) {
+            a.sc->iter_a = j + 1;
+            if (a.hist && j < a.hist_cap) a.hist[2 * j] = alpha;
+        }
         if (!(active & (1u << c))) return;
     } else if (writer && threadIdx.x == 0) {
         a.sc->iter_a = 0;

@@ -205,6 +205,10 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
             s->active_b = (int)active;
             s->status = bad ? -4 : (converged ? 0 : (j >= a.max_iter ? -3 : 0));
             if (stop) s->done = 1;
+            if (a.hist && !stop && j < a.hist_cap) {
+                a.hist[2 * j] = alpha;
+                a.hist[2 * j + 1] = beta;
+            }
         }
         if (stop) return;
         if (!(active & (1u << c))) {

@@ -299,6 +299,8 @@ struct gap_grid_s {
     double *adj_rhs = nullptr, *adj_lam = nullptr;           // adjoint right-hand sides and solutions
     double *adj_part = nullptr;                              // sensitivity partials
     double *step_buf = nullptr;                              // general iteration: F (9 x 4) and J (4 x 8)
+    double *hist = nullptr;                                  // PCG scalars per iteration (measurement), or null
+    int hist_cap = 0;
     gap_batch_s* batch = nullptr;                            // the batch this handle is in (its buffers are lent)
     int cus = 256;                                           // compute units of the device
     PcgShape shape_a{}, shape_b{};                           // PCG kernel shapes in use (A; B and init)
@@ -345,7 +347,7 @@ namespace {
 void release(gap_grid_t g)
 {
     double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->z1, g->partial,
-                      g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part, g->step_buf};
+                      g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part, g->step_buf, g->hist};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& gr : g->graphs)
@@ -437,6 +439,8 @@ void fill_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o)
     a.fpart[0] = g->pcg_part + 5 * ps;
     a.fpart[1] = g->pcg_part + 10 * ps;
     a.fstride = (int)ps;
+    a.hist = g->hist;
+    a.hist_cap = g->hist_cap;
     a.sc = g->sc;
     a.nt = g->nt;
     a.nz = g->nz;
@@ -1324,6 +1328,47 @@ gap_status gap_kernel_stats(gap_grid_t g, int32_t kernel, int64_t* launches, dou
     if (kernel < 0 || kernel >= GAP_KERNEL_COUNT) return fail(GAP_EINVAL, "unknown kernel %d", kernel);
     if (launches) *launches = g->launches[kernel];
     if (total_ms) *total_ms = g->total_ms[kernel];
+    return GAP_OK;
+}
+
+gap_status gap_pcg_history(gap_grid_t g, int32_t capacity)
+{
+    if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "gap_pcg_history");
+    if (capacity < 0 || capacity > (1 << 24)) return fail(GAP_EINVAL, "capacity must lie in [0, 2^24]");
+    if (g->hist) {
+        HIPCHK(hipDeviceSynchronize());
+        (void)hipFree(g->hist);
+        g->hist = nullptr;
+        g->hist_cap = 0;
+    }
+    if (capacity > 0) {
+        gap_status s = dmalloc(&g->hist, 2 * (size_t)capacity);
+        if (s != GAP_OK) return s;
+        HIPCHK(hipMemset(g->hist, 0, 2 * (size_t)capacity * sizeof(double)));
+        g->hist_cap = capacity;
+    }
+    return GAP_OK;
+}
+
+gap_status gap_get_pcg_history(gap_grid_t g, double* alpha, double* beta, int32_t cap, int32_t* count, void* stream)
+{
+    if (!g || !alpha || !beta || !count || cap < 0) return fail(GAP_EINVAL, "grid, alpha, beta and count must be non-NULL, cap >= 0");
+    if (!g->hist) return fail(GAP_ESTATE, "PCG scalars are not being recorded (gap_pcg_history)");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(st));
+    const int k = std::min(std::min(g->sc_host->iterations, g->hist_cap), (int)cap);
+    *count = 0;
+    if (k > 0) {
+        std::vector<double> h(2 * (size_t)k);
+        HIPCHK(hipMemcpyAsync(h.data(), g->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int j = 0; j < k; ++j) {
+            alpha[j] = h[2 * j];
+            beta[j] = j ? h[2 * j + 1] : 0.0;
+        }
+    }
+    *count = k;
     return GAP_OK;
 }
 

@@ -134,6 +134,8 @@ _SIGNATURES = {
     "gap_tune_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.POINTER(gap_pcg_config),
                      ctypes.POINTER(ctypes.c_double), _P],
     "gap_kernel_stats": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "gap_pcg_history": [_P, ctypes.c_int32],
+    "gap_get_pcg_history": [_P, _D8, _D8, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
 }
 
 
@@ -300,6 +302,22 @@ def gap_kernel_stats(handle, kernel):
     ms = ctypes.c_double(0.0)
     _check(load().gap_kernel_stats(handle, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def gap_pcg_history(handle, capacity):
+    """Record alpha_j and beta_{j-1} of the next solves' iterations j < capacity (0: stop)."""
+    _check(load().gap_pcg_history(handle, int(capacity)))
+
+
+def gap_get_pcg_history(handle, cap, stream=None):
+    """(alpha, beta) of the last solve as numpy arrays: alpha[j] = alpha_j, beta[j] = beta_{j-1}
+    (the beta that formed u_j; beta[0] = 0)."""
+    import numpy as np
+    a = (ctypes.c_double * max(int(cap), 1))()
+    b = (ctypes.c_double * max(int(cap), 1))()
+    n = ctypes.c_int32(0)
+    _check(load().gap_get_pcg_history(handle, a, b, int(cap), ctypes.byref(n), _stream(stream)))
+    return np.array(a[: n.value]), np.array(b[: n.value])
 
 
 def gap_get_pcg_config(handle):

@@ -108,6 +108,10 @@ def test_new_entry_points_reject_null_handles(lib):
     assert lib.gap_batch_hold(None, 1, 1) == G.GAP_EINVAL
     assert lib.gap_get_pcg_config(None, None) == G.GAP_EINVAL
     assert lib.gap_set_pcg_config(None, None) == G.GAP_EINVAL
+    assert lib.gap_pcg_history(None, 16) == G.GAP_EINVAL
+    a = (ctypes.c_double * 4)()
+    n = ctypes.c_int32(0)
+    assert lib.gap_get_pcg_history(None, a, a, 4, ctypes.byref(n), None) == G.GAP_EINVAL
     opts = G.gap_default_opts()
     J = (ctypes.c_double * 32)()
     assert lib.solve_with_adjoint(None, ctypes.byref(opts), P(8), None, J, None, None) == G.GAP_EINVAL

@@ -24,6 +24,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2511_06824_amd import gapsolve as G  # noqa: E402
+from paper_2511_06824_amd.diagnostics import condition_estimate  # noqa: E402
 from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
 
 ENTRY_TOL = 1e-12     # face conductances, relative per entry (see the small-grid assembly test)
@@ -59,7 +60,15 @@ def test_joint_textured_2048x1024_full_size(iteration):
     opts = s.options(omega=case.omega, eps=case.eps, iteration=iteration)
     cfg, _ = s.tune(opts, iterations=20)
     log(f"  launch configuration {cfg}")
+    G.gap_pcg_history(s.handle, 8192)
     p, info = s.solve(opts)
+    alpha, beta = G.gap_get_pcg_history(s.handle, 8192)
+    G.gap_pcg_history(s.handle, 0)
+    lo, hi, kappa = condition_estimate(alpha, beta)
+    # the attainable relative accuracy of an FP64 solve is about kappa times the unit roundoff
+    log(f"  Lanczos estimate of the preconditioned spectrum: {lo:.4e} .. {hi:.4e}, kappa {kappa:.4e}, "
+        f"kappa x 2^-53 = {kappa * 2.0 ** -53:.1e}")
+    assert len(alpha) == info.iterations and 1.0 < kappa < 1e9
     F = s.integrate().cpu().numpy()
     p = p.reshape(9, -1).cpu().numpy()
     log(f"  iterations {info.iterations}, recurrence residual {info.rel_residual:.2e}")
