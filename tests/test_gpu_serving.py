@@ -255,3 +255,51 @@ def test_a_grid_in_a_batch_is_lent_to_it():
     s.close()
     G.gap_batch_destroy(b)
     G.gap_batch_destroy(b2)
+
+
+@ITERATIONS
+def test_random_joins_and_holds_keep_results_bitwise(iteration):
+    """A seeded random schedule: requests join between steps of 3-9 iterations, and are held
+    and released at random; each finishes bitwise as when solved alone.  This exercises the
+    one-launch kernel's per-request parity offsets under arbitrary launch counts."""
+    log(f"case: random batch schedule, iteration kind {iteration}")
+    rng = np.random.default_rng(2024)
+    cases = [synth.smooth_case(64, 32, 40 + k) if k % 2 else synth.textured_case(96, 24, 40 + k) for k in range(6)]
+    alone = [batch_solve([c], iteration=iteration)[0] for c in cases]
+    b = G.gap_batch_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    solvers, ids, held, results = [], [], set(), {}
+    pending = list(range(len(cases)))
+    while len(results) < len(cases):
+        if pending and (not ids or rng.random() < 0.5):
+            k = pending.pop(0)
+            c = cases[k]
+            s = JointGapSolver.from_case(c, max_cond=9)
+            s.assemble(c.e, c.edot, c.delta, 9)
+            opts = s.options(omega=c.omega, eps=c.eps, iteration=iteration)
+            ids.append(G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream))
+            solvers.append(s)
+        live = [i for i in ids if i not in results]
+        for bid in live:
+            if bid in held and rng.random() < 0.5:
+                G.gap_batch_hold(b, bid, 0)
+                held.discard(bid)
+            elif bid not in held and rng.random() < 0.25 and len(held) + 1 < len(live):
+                G.gap_batch_hold(b, bid, 1)
+                held.add(bid)
+        G.gap_batch_step(b, int(rng.integers(3, 10)), bool(rng.random() < 0.5), stream)
+        for bid in G.gap_batch_poll(b):
+            k = ids.index(bid)
+            _, info = G.gap_batch_remove(b, bid, stream)
+            results[bid] = (solvers[k].pressure().cpu().numpy().copy(), info.iterations)
+            held.discard(bid)
+        if not [i for i in ids if i not in results and i not in held] and held:
+            bid = held.pop()                       # keep something running
+            G.gap_batch_hold(b, bid, 0)
+    for k, bid in enumerate(ids):
+        p, it = results[bid]
+        assert it == alone[k][1], (k, it, alone[k][1])
+        assert np.array_equal(p, alone[k][0]), k
+    for s in solvers:
+        s.close()
+    G.gap_batch_destroy(b)
