@@ -314,6 +314,8 @@ def main():
     ap.add_argument("--no-dynamics", action="store_true", help="skip the general-iteration time steps")
     ap.add_argument("--no-two-launch", action="store_true", help="skip the two-launch iteration comparison")
     ap.add_argument("--no-seeds", action="store_true", help="skip the two extra seeds of the workload")
+    ap.add_argument("--no-strategies", action="store_true", help="skip the sync / async strategy comparison")
+    ap.add_argument("--no-paper-meshes", action="store_true", help="skip the joint vs sequential runs at 400x360, 800x760")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the joint solve of one request runs on one device; "
@@ -448,6 +450,27 @@ def main():
                           "traffic": (sum(recorded_traffic(k) or 0 for k in stats if k in nbytes)
                                       if all(recorded_traffic(k) for k in stats if k in nbytes) else None)}
 
+    # the stopping strategies (Eq 3.9 synchronized, Eq 3.10 asynchronized on the device) with
+    # Jacobi and ASSOR II, graph-replayed, one solve each after a warm one
+    strategies = None
+    if not args.no_strategies:
+        strategies = []
+        for pname, pc in (("jacobi", G.GAP_PRECOND_JACOBI), ("assor2", G.GAP_PRECOND_ASSOR2)):
+            for sname, st in (("sync", G.GAP_STRATEGY_SYNC), ("async", G.GAP_STRATEGY_ASYNC)):
+                o3 = solver.options(omega=case.omega, eps=case.eps, precond=pc, strategy=st)
+                solver.assemble(case.e, case.edot, case.delta, 9)
+                solver.solve(o3)
+                torch.cuda.synchronize()
+                t30 = time.perf_counter()
+                _, info3 = solver.solve(o3)
+                torch.cuda.synchronize()
+                dt3 = time.perf_counter() - t30
+                strategies.append({"precond": pname, "strategy": sname, "iterations": info3.iterations,
+                                   "ms_per_solve": round(1e3 * dt3, 2),
+                                   "us_per_iteration": round(1e6 * dt3 / max(info3.iterations, 1), 2),
+                                   "max_cond_rel_residual": max(info3.rel_residual_cond[k] for k in range(9))})
+                print(f"bench: strategy {strategies[-1]}", file=sys.stderr, flush=True)
+
     # Lanczos estimate of the preconditioned spectrum from the device-recorded PCG scalars of
     # one more solve (outside the timed region)
     from paper_2511_06824_amd.diagnostics import condition_estimate
@@ -499,6 +522,10 @@ def main():
     if not args.no_study:
         study = run_precond_study(JointGapSolver, dev)
 
+    meshes = None
+    if not args.no_paper_meshes:
+        meshes = run_paper_meshes(G, JointGapSolver, dev)
+
     dyn = None
     if not args.no_dynamics:
         dyn = run_dynamics(torch, G, JointGapSolver, dev)
@@ -521,7 +548,7 @@ def main():
         "true_rel_residual": max(true_rel),
         "graph_solves_per_s": round(graph_solves_per_s, 5),
         "pcg_config": solver.pcg_config, "tune": tune, "per_condition_scalars": per_cond,
-        "two_launch_iteration": two_launch, "spectrum": spectrum, "other_seeds": seeds,
+        "two_launch_iteration": two_launch, "spectrum": spectrum, "other_seeds": seeds, "strategies": strategies, "paper_meshes": meshes,
         "timed_region": "plain launches with a HIP event pair around every PCG kernel launch",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
@@ -532,7 +559,7 @@ def main():
     solver.close()
 
 
-def plain_solve(case, JointGapSolver, dev, tune=True, handle=None):
+def plain_solve(case, JointGapSolver, dev, tune=True, handle=None, precond=None):
     """One joint solve done the plain way (sequential GPU acceleration): the 9 conditions one
     at a time on the same kernels, eps and omega, with a host read of the residual after
     every iteration; forces per condition; the FD quotient of Eq 2.13-2.14 on the host.
@@ -547,7 +574,8 @@ def plain_solve(case, JointGapSolver, dev, tune=True, handle=None):
             ed[k - 5] += case.delta[k - 1]
         conds.append((e, ed))
     s1 = handle or JointGapSolver.from_case(case, max_cond=1, device=dev)
-    opts = s1.options(omega=case.omega, eps=case.eps, check_every=1, graph=False)
+    kw = {} if precond is None else {"precond": precond}
+    opts = s1.options(omega=case.omega, eps=case.eps, check_every=1, graph=False, **kw)
     if tune:
         s1.assemble(conds[0][0], conds[0][1], None, 1)
         s1.tune(opts, iterations=20)
@@ -563,6 +591,46 @@ def plain_solve(case, JointGapSolver, dev, tune=True, handle=None):
         s1.close()
     assert np.all(np.isfinite(J))
     return F, J, its
+
+
+def run_paper_meshes(G, JointGapSolver, dev, eps=1e-6):
+    """The structure of the paper's Tables 4-6 on synthetic inputs: at its meshes 400 x 360 and
+    800 x 760 (n_theta x n_axial), smooth (omega 1.8) and dimpled (omega 1.6), with Jacobi and
+    ASSOR II at the paper's eps 1e-6, one hot-path step done jointly (GMAF: the 9 conditions
+    in one solve, graph-replayed) and sequentially (SGA: the conditions one at a time with a
+    host read of the residual every iteration).  Best of 2 after a warm-up, wall clock of the
+    whole step (assembly, PCG, forces, FD Jacobian)."""
+    import torch
+    import synth
+    rows = []
+    for nt, nz in ((400, 360), (800, 760)):
+        for kind in ("smooth", "textured"):
+            case = (synth.smooth_case if kind == "smooth" else synth.textured_case)(nt, nz, 0, eps=eps)
+            sj = JointGapSolver.from_case(case, max_cond=9, device=dev)
+            s1 = JointGapSolver.from_case(case, max_cond=1, device=dev)
+            for pname, pc in (("jacobi", G.GAP_PRECOND_JACOBI), ("assor2", G.GAP_PRECOND_ASSOR2)):
+                oj = sj.options(omega=case.omega, eps=eps, precond=pc)
+                best_j = best_s = None
+                for rep_ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, _, ij = sj.step(case.e, case.edot, case.delta, oj)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    _, _, its = plain_solve(case, JointGapSolver, dev, tune=False, handle=s1, precond=pc)
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                    if rep_:
+                        best_j = t1 - t0 if best_j is None else min(best_j, t1 - t0)
+                        best_s = t2 - t1 if best_s is None else min(best_s, t2 - t1)
+                rows.append({"mesh": f"{nt}x{nz}", "kind": kind, "precond": pname, "omega": case.omega,
+                             "gmaf_iterations": ij.iterations, "sga_iterations_per_condition": round(its / 9, 1),
+                             "gmaf_ms": round(1e3 * best_j, 2), "sga_ms": round(1e3 * best_s, 2),
+                             "gmaf_over_sga_speed": round(best_s / best_j, 2)})
+                print(f"bench: paper mesh {rows[-1]}", file=sys.stderr, flush=True)
+            sj.close()
+            s1.close()
+    return rows
 
 
 def run_plain(case, G, JointGapSolver, dev, tune=True):
