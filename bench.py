@@ -28,9 +28,9 @@ def kernel_bytes(n, n_cond, n_op):
     """Algorithmic HBM bytes of one launch of each iteration kernel: every vector operand is
     read or written once per condition-DOF; the face conductances (kx, kz: 16 B per
     operator-DOF) once per distinct operator.  k_pcg_a reads z, u_prev and writes u; k_pcg_b
-    reads u, p, r and writes p, r, z; the one-launch k_pcg_f reads z, u_prev, p, r and writes
-    u, p, r, z."""
-    vec = {"k_pcg_a": 3, "k_pcg_b": 6, "k_pcg_f": 8}
+    reads u, p, r and writes p, r, z; the one-launch k_pcg_f reads z, u_prev, r and writes
+    u, r, z, and reads and writes p on every other launch (7 operands on average)."""
+    vec = {"k_pcg_a": 3, "k_pcg_b": 6, "k_pcg_f": 7}
     return {k: 8 * v * n * n_cond + 16 * n * n_op for k, v in vec.items()}
 
 

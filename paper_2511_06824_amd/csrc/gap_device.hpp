@@ -89,6 +89,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV])
 
 __device__ __forceinline__ bool finite_d(double x) { return x - x == 0.0; }
 
+// A double that every lane of the wave holds alike, moved to scalar registers (values the
+// workgroup derives from LDS are otherwise kept in vector registers, one copy per lane).
+__device__ __forceinline__ double wave_uniform(double x)
+{
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b & 0xffffffffull));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Global-memory views of generic pointers.  Kernels that read their buffer addresses from a
 // record in device memory see generic pointers, for which the compiler emits flat loads and
 // stores; those count against the LDS wait counter as well, so every wait for an LDS read

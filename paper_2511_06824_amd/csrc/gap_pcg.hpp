@@ -49,6 +49,12 @@ struct PcgScalars {
     // launch's own iteration, both by launch parity (read from [par], written to [par ^ 1])
     int iter_f[2];
     double gam[2][GAP_MAXC];
+    // one-launch iteration, also by launch parity: the stop flag and the active mask that the
+    // next launch reads (so that no workgroup of a launch sees that launch's own update), and
+    // alpha_j per condition (the term a launch of even j leaves pending in p)
+    int done_f[2];
+    int act_f[2];
+    double alf[2][GAP_MAXC];
 };
 
 struct PcgDev {

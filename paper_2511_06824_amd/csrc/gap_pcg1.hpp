@@ -19,9 +19,16 @@
 // needs z' on row j1 as well, which takes r' on rows [j0 - 1, j1 + 1] (each ASSOR sweep
 // reaches one row) and u on rows [j0 - 2, j1 + 2].
 //
-// Bytes per condition-DOF: reads z, u_prev, p, r; writes u, p, r', z' (64 B), plus the face
-// conductances once per operator.  The two-launch iteration of gap_pcg.hpp moves 72 B and
-// reads the conductances in both launches.
+// p is not read by the recurrence, so it moves every other iteration: a launch of odd j adds
+// alpha_{j-1} u_{j-1} + alpha_j u_j when a row's z_j and u_{j-1} arrive, and a launch of even j
+// leaves its term pending.  The launch that stops a condition after an even iteration settles
+// the pending term.  The iterates (alpha, beta, r, z, u) are unchanged; p differs only in the
+// order of its additions.
+//
+// Bytes per condition-DOF: reads z, u_prev, r and writes u, r', z' (48 B), plus p read and
+// written on odd iterations (56 B on average), plus the face conductances once per operator.
+// The two-launch iteration of gap_pcg.hpp moves 72 B and reads the conductances in both
+// launches.
 //
 // Buffers that one launch both reads (with halo rows) and writes alternate by iteration
 // parity: u, r, z and the partial sums.  The iteration index and the per-condition r.z that
@@ -33,10 +40,11 @@
 //
 // Row pipeline, one row step s per loop trip, two barriers per step:
 //   P1  u and the east-face conductances of row s to LDS; loads of step s + 1 issued
-//   P2  A u, r' and y = D^-1 r' of row s; stores of u, p, r' on owned rows; the east faces of
-//       row s - 2 for z'^T A z' (z' of that row reached LDS in the previous step)
+//   P2  A u, r' and y = D^-1 r' of row s; stores of u and r' on owned rows; the east faces
+//       of row s - 2 for z'^T A z' (z' of that row reached LDS in the previous step)
 //   P3  first ASSOR sweep (Eq 3.5) of row s; second sweep (Eq 3.6) and z' of row s - 1;
-//       the axial faces of z'^T A z' below row s - 1
+//       the axial faces of z'^T A z' below row s - 1; then u of row s + 2 from its loads, and
+//       on odd iterations its p
 // Steps s = nz and nz + 1 (last chunk of a ring) only drain the lagged stages.
 #pragma once
 
@@ -54,17 +62,21 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
     if (!pcg_work(work, blockIdx.x, req, c, kc)) return;
     const PcgDev& a = reqs[req];
     const int par = (launch_par ^ a.par_off) & 1;
-    if (!INIT && a.sc->done) return;
+    const bool writer_ = (c == 0 && kc == 0);
+    // stopped: return at once; the record writer carries the flag into the other parity slot
+    if (!INIT && a.sc->done_f[par]) {
+        if (writer_ && threadIdx.x == 0) a.sc->done_f[par ^ 1] = 1;
+        return;
+    }
     const int nt = a.nt, nz = a.nz;
     const int j0 = kc * a.rows_b, j1 = min(j0 + a.rows_b, nz), slot = c * a.chunks_b + kc;
-    const bool writer = (c == 0 && kc == 0);   // publishes the request's device record
+    const bool writer = writer_;               // publishes the request's device record
     const size_t fs = (size_t)a.fstride;
     double* wpart = a.fpart[INIT ? 0 : (par ^ 1)];
     const int t = threadIdx.x;
-    // A condition frozen by the asynchronized test carries its partials into the set the next
-    // launch reads, so that its residual stays the one it froze at.  The mask only shrinks, so
-    // reading it while this launch's writer updates it gives the same decision either way.
-    if (!INIT && a.async && !writer && !((a.sc->active_b >> c) & 1)) {
+    // A condition frozen by the asynchronized test in an earlier launch carries its partials
+    // into the set the next launch reads, so that its residual stays the one it froze at.
+    if (!INIT && a.async && !writer && !((a.sc->act_f[par] >> c) & 1)) {
         if (t == 0)
             for (int q = 0; q < kOnePassParts; ++q) wpart[q * fs + slot] = a.fpart[par][q * fs + slot];
         return;
@@ -106,14 +118,17 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
     // row step.  The east-face conductances live in the LDS ring (the western neighbour and
     // the two earlier rows come from there), v of row s-1 in its LDS row, and 1/D of row
     // s-1 is recomputed from the same four conductances in the same order.
-    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kzSprev[Q], rc[Q], pc[Q];
+    double um[Q], uc[Q], up[Q], kzS[Q], kzN[Q], kzSprev[Q], rc[Q];
     double yprev[Q], rpprev[Q], aup[Q], zprev[Q];
     double kxn[Q], nzl[Q], nul[Q], nkz[Q], nr[Q], np[Q];
     double um_[Q], uc_[Q], up_[Q];          // u_{j-1} of the first rows, combined after beta
+    // p moves on odd iterations only, by alpha_{j-1} u_{j-1} + alpha_j u_j, when the row's z_j
+    // and u_{j-1} arrive (a launch of even j leaves its term pending)
+    const bool odd = !INIT && (j & 1);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int i = t + q * NT;
-        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kzSprev[q] = rc[q] = pc[q] = 0.0;
+        um[q] = uc[q] = up[q] = kzS[q] = kzN[q] = kzSprev[q] = rc[q] = 0.0;
         yprev[q] = rpprev[q] = aup[q] = zprev[q] = 0.0;
         kxn[q] = nzl[q] = nul[q] = nkz[q] = nr[q] = np[q] = 0.0;
         um_[q] = uc_[q] = up_[q] = 0.0;
@@ -135,12 +150,11 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
             kzN[q] = kz[g + nt];
             kxn[q] = kx[g];
             rc[q] = rin[g];
-            if (!INIT && s_begin >= j0) pc[q] = __builtin_nontemporal_load(&pp[g]);
         }
     }
 
     // ---- scalars -----------------------------------------------------------------------
-    double alpha = 1.0, beta = 0.0;
+    double alpha = 1.0, beta = 0.0, a_prev = 0.0;
     if (!INIT) {
         __shared__ double sums[kOnePassParts + 1][GAP_MAXC];
         {
@@ -151,7 +165,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
         }
         // sums: 0 r.z (d_j), 1 r.r, 2 z^T A z, 3 z^T A u_{j-1}, 4 u_{j-1}^T A u_{j-1}, 5 S.S
         const double* gprev = a.sc->gam[par];   // d_{j-1} per condition
-        const unsigned was_active = (unsigned)a.sc->active_b;
+        const unsigned was_active = (unsigned)a.sc->act_f[par];
         unsigned active = 0;
         double rr = 0.0, ss = 0.0;
         for (int k = 0; k < a.n_cond; ++k) {
@@ -164,6 +178,8 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
         const double rel = sqrt(rr / (ss > 0.0 ? ss : 1.0));
         const bool converged = a.async ? (active == 0) : (rel <= a.eps);
         bool bad = !finite_d(rel);
+        double alk[GAP_MAXC];                  // alpha_j per condition
+        for (int k = 0; k < GAP_MAXC; ++k) alk[k] = 0.0;
         if (!converged && j < a.max_iter) {
             // u_j^T A u_j from the three sums, per condition for beta b
             auto den = [&](int k, double b) {
@@ -173,7 +189,8 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                 for (int k = 0; k < a.n_cond; ++k) {
                     if (!(active & (1u << k))) continue;
                     const double bk = j > 0 ? sums[0][k] / gprev[k] : 0.0;
-                    bad |= !finite_d(bk) || !finite_d(sums[0][k] / den(k, bk));
+                    alk[k] = sums[0][k] / den(k, bk);
+                    bad |= !finite_d(bk) || !finite_d(alk[k]);
                 }
                 beta = j > 0 ? sums[0][c] / gprev[c] : 0.0;
                 alpha = sums[0][c] / den(c, beta);
@@ -189,6 +206,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                     if (active & (1u << k)) uau += den(k, beta);
                 alpha = dn / uau;
                 bad |= !finite_d(beta) || !finite_d(alpha);
+                for (int k = 0; k < a.n_cond; ++k) alk[k] = alpha;
             }
         }
         const bool stop = bad || converged || j >= a.max_iter;
@@ -203,17 +221,36 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
             }
             s->iter_f[par ^ 1] = j + 1;
             s->active_b = (int)active;
+            s->act_f[par ^ 1] = (int)active;
+            for (int k = 0; k < a.n_cond; ++k) s->alf[par ^ 1][k] = alk[k];
             s->status = bad ? -4 : (converged ? 0 : (j >= a.max_iter ? -3 : 0));
-            if (stop) s->done = 1;
+            if (stop) {
+                s->done = 1;
+                s->done_f[par ^ 1] = 1;
+            }
             if (a.hist && !stop && j < a.hist_cap) {
                 a.hist[2 * j] = alpha;
                 a.hist[2 * j + 1] = beta;
             }
         }
-        if (stop) return;
-        if (!(active & (1u << c))) {
-            if (t == 0)
+        a_prev = odd ? a.sc->alf[par][c] : 0.0;
+        if (stop || !(active & (1u << c))) {
+            if (!stop && t == 0)
                 for (int q = 0; q < kOnePassParts; ++q) wpart[q * fs + slot] = a.fpart[par][q * fs + slot];
+            // this condition stops here: after an even iteration, alpha_{j-1} u_{j-1} is still
+            // pending in p (a condition frozen earlier settled it in its own last launch)
+            if (odd && ((was_active >> c) & 1)) {
+                for (int s = j0; s < j1; ++s) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int i = t + q * NT;
+                        if (i < nt) {
+                            const unsigned g = (unsigned)s * nt + i;
+                            pp[g] = pp[g] + a_prev * uin[g];
+                        }
+                    }
+                }
+            }
             return;
         }
     } else if (writer && t == 0) {
@@ -223,14 +260,32 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
         s->status = 0;
         s->iterations = 0;
         s->active_b = (1 << a.n_cond) - 1;
+        s->act_f[0] = s->act_f[1] = (1 << a.n_cond) - 1;
+        s->done_f[0] = s->done_f[1] = 0;
     }
 
+    // the scalars are alike in every lane: keep them in scalar registers
+    alpha = wave_uniform(alpha);
+    beta = wave_uniform(beta);
+    a_prev = wave_uniform(a_prev);
     if (has_prev) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             um[q] += beta * um_[q];
             uc[q] += beta * uc_[q];
             up[q] += beta * up_[q];
+        }
+    }
+    if (odd) {
+        // the first rows (s_begin <= j0, so row s_begin - 1 is never owned)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + q * NT;
+            if (i < nt) {
+                const unsigned g = (unsigned)s_begin * nt + i;
+                if (s_begin >= j0) pp[g] = pp[g] + (a_prev * uc_[q] + alpha * uc[q]);
+                if (s_begin + 1 >= j0 && s_begin + 1 < j1) pp[g + nt] = pp[g + nt] + (a_prev * up_[q] + alpha * up[q]);
+            }
         }
     }
 
@@ -260,7 +315,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                 kxn[q] = kx[g1];
                 nkz[q] = kz[g1 + nt];
                 nr[q] = rin[g1];
-                if (!INIT && s + 1 >= j0 && s + 1 < j1) np[q] = __builtin_nontemporal_load(&pp[g1]);
+                if (odd && s + 2 >= j0 && s + 2 < j1) np[q] = __builtin_nontemporal_load(&pp[g1 + nt]);
                 if (spmv && s + 2 <= u_hi) {
                     nzl[q] = __builtin_nontemporal_load(&zin[g1 + nt]);
                     if (has_prev) nul[q] = __builtin_nontemporal_load(&uin[g1 + nt]);
@@ -298,7 +353,6 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                             acc_ss += rc[q] * rc[q];
                             if (!a.warm) pp[g] = 0.0;
                         } else {
-                            pp[g] = pc[q] + alpha * uc[q];
                             __builtin_nontemporal_store(uc[q], &uout[g]);
                             acc_uau += uc[q] * au[q];
                         }
@@ -377,11 +431,12 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
             um[q] = uc[q];
             uc[q] = up[q];
             up[q] = has_prev ? nzl[q] + beta * nul[q] : nzl[q];
+            if (odd && s + 2 >= j0 && s + 2 < j1 && t + q * NT < nt)
+                pp[(unsigned)(s + 2) * nt + t + q * NT] = np[q] + (a_prev * nul[q] + alpha * up[q]);
             kzSprev[q] = kzS[q];
             kzS[q] = kzN[q];
             kzN[q] = nkz[q];
             rc[q] = nr[q];
-            pc[q] = np[q];
             rpprev[q] = rp[q];
             aup[q] = au[q];
         }
