@@ -5,19 +5,76 @@ two-launch iteration (Table 1 as printed: k_pcg_a, k_pcg_b) and the one-launch i
 
     python3 paper_2511_06824_amd/profile_pcg.py [--iterations N] [--copy-mib M] [--no-tune]
                                                 [--iteration one|two|both]
+    python3 paper_2511_06824_amd/profile_pcg.py --summarize FETCH_CSV WRITE_CSV
 
-The copy (torch's elementwise copy kernel, M MiB read and M MiB written) calibrates what
-the FETCH_SIZE / WRITE_SIZE counters read per byte actually moved.
+The copy (a device-to-device copy, M MiB read and M MiB written) calibrates what the
+FETCH_SIZE / WRITE_SIZE counters read per byte actually moved.  --summarize reads the two
+counter-collection CSVs of such runs (no GPU needed) and prints the calibrated bytes per
+launch of each iteration kernel in the steady state: a solve's first launch (j = 0, no
+u_prev yet) and its closing launch (which only reads the partials and stops) are left out,
+and the one-launch kernel is averaged over odd and even iterations separately, since p
+moves on odd iterations only.
 """
 
 import argparse
+import csv
 import os
 import sys
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
+def _dispatches(path, counter):
+    """{kernel name: [counter value in KiB by dispatch order]} from a rocprofv3 counter CSV."""
+    out = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            out.setdefault(row["Kernel_Name"], []).append((int(row["Dispatch_Id"]), float(row["Counter_Value"])))
+    return {k: [v for _, v in sorted(x)] for k, x in out.items()}
+
+
+def summarize(fetch_csv, write_csv, copy_mib=1024):
+    fetch, write = _dispatches(fetch_csv, "FETCH_SIZE"), _dispatches(write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    cf = [v for v in fetch.get("__amd_rocclr_copyBuffer", []) if v > copy_kib / 4]
+    cw = [v for v in write.get("__amd_rocclr_copyBuffer", []) if v > copy_kib / 4]
+    if not cf or not cw:
+        raise SystemExit("no calibration copy found in the counter files")
+    sf = copy_kib / (sum(cf) / len(cf))
+    sw = copy_kib / (sum(cw) / len(cw))
+    print(f"calibration: FETCH_SIZE {sum(cf) / len(cf):.1f} KiB per copy of {copy_kib:.0f} KiB -> scale {sf:.3f}; "
+          f"WRITE_SIZE {sum(cw) / len(cw):.1f} KiB -> scale {sw:.3f}")
+    print("| kernel | launches used | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |")
+    print("|---|---|---|---|---|")
+    mean = lambda x: sum(x) / len(x)
+    for name in sorted(fetch):
+        if not name.startswith("void k_pcg_") or ", true>" in name:
+            continue
+        f, w = fetch[name][1:-1], write.get(name, [])[1:-1]
+        if not f or len(f) != len(w):
+            continue
+        short = name.split("(")[0].replace("void ", "").replace(" ", "")
+        if short.startswith("k_pcg_f"):
+            groups = [("odd j", f[0::2], w[0::2]), ("even j", f[1::2], w[1::2])]
+            tot = []
+            for label, ff, ww in groups:
+                b = mean(ff) * 1024 * sf + mean(ww) * 1024 * sw
+                tot.append(b)
+                print(f"| {short}, {label} | {len(ff)} | {mean(ff):.1f} | {mean(ww):.1f} | {b:.0f} |")
+            print(f"| {short}, average | {len(f)} | | | {mean(tot):.0f} |")
+        else:
+            b = mean(f) * 1024 * sf + mean(w) * 1024 * sw
+            print(f"| {short} | {len(f)} | {mean(f):.1f} | {mean(w):.1f} | {b:.0f} |")
+
+
 def main():
+    if len(sys.argv) >= 2 and sys.argv[1] == "--summarize":
+        if len(sys.argv) != 4:
+            raise SystemExit("usage: profile_pcg.py --summarize FETCH_CSV WRITE_CSV")
+        summarize(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=1024)
