@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import gap_of
+from conftest import gap_of, texture_of
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +67,48 @@ def test_largest_axial_size_follows_the_oracle_recurrence(iteration):
     assert perr <= 1e-8 and rerr <= 1e-6
     assert abs(true_rel - info.rel_residual) <= 1e-6 * info.rel_residual
     np.testing.assert_allclose(Sg.ravel(), S, rtol=1e-11, atol=1e-11 * np.max(np.abs(S)))
+
+
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("scalars,strategy,eps,max_iter", [
+    ("global", "sync", 1e-300, 7), ("global", "sync", 1e-300, 8),
+    ("per_cond", "async", 3e-3, 1000), ("global", "async", 3e-3, 1000)],
+    ids=["cap_odd", "cap_even", "per_cond_async", "global_async"])
+def test_pressure_is_whole_after_a_stop_at_either_parity(scalars, strategy, eps, max_iter, iteration):
+    """p after the solve stops at an odd or an even iteration: by the iteration cap, or by
+    conditions frozen one by one under the asynchronized test (Eq 3.10).  The one-launch kernel
+    moves p on odd iterations only, so a stop after an even iteration has a term left to
+    settle.  The perturbations are large enough that the nine conditions freeze at iterations
+    of both parities (31 to 42 at eps 3e-3), and the stops come early, where the last
+    update of p is far above the 1e-8 bound."""
+    case = synth.textured_case(64, 32, 5)
+    delta = np.array([0.2 * case.c * f for f in (1.0, -1.0, 0.5, -0.7)] + [3e-2, -2e-2, 1e-2, 4e-2])
+    log(f"case: {case.label}, {scalars} scalars, {strategy}, eps {eps}, max_iter {max_iter}, "
+        f"iteration kind {iteration}")
+    gap, tex = gap_of(case), texture_of(case)
+    blocks_, rhs = [], []
+    for ek, edk in oracle.conditions(case.e, case.edot, delta):
+        A, S = oracle.assemble(gap, ek, edk, tex)
+        blocks_.append(A)
+        rhs.append(S)
+    M = [oracle.assor2_precond(A, 1.6) for A in blocks_]
+    p_ref, it_ref, _ = oracle.pcg_blocks(blocks_, rhs, M, eps, max_iter, scalars, strategy)
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, delta, 9)
+    p, info = s.solve(omega=1.6, eps=eps, max_iter=max_iter, raise_on_error=False,
+                      scalars=G.GAP_SCALARS_PER_COND if scalars == "per_cond" else G.GAP_SCALARS_GLOBAL,
+                      strategy=G.GAP_STRATEGY_ASYNC if strategy == "async" else G.GAP_STRATEGY_SYNC,
+                      iteration=iteration)
+    p = p.reshape(9, -1).cpu().numpy()
+    s.close()
+    errs = [np.linalg.norm(p[k] - p_ref[k]) / np.linalg.norm(p_ref[k]) for k in range(9)]
+    log(f"  iterations {info.iterations} (oracle {it_ref}), worst pressure error {max(errs):.1e}")
+    if strategy == "sync":
+        assert info.status == G.GAP_ENOCONV and info.iterations == max_iter == it_ref
+    else:
+        assert info.status == G.GAP_OK and abs(info.iterations - it_ref) <= 1
+    assert max(errs) <= 1e-8, errs
 
 
 def test_empty_batch_steps_and_polls():
