@@ -296,13 +296,17 @@ gap_status set_operating_point(gap_grid_t grid, double U, double V, double p_in,
 gap_status gap_read_system(gap_grid_t grid, int32_t k, double *kx, double *kz, double *S,
                            void *stream);
 
-/* Measurement support.  While enabled, solve_joint_pcg brackets every launch of the
- * iteration kernels with HIP events on the caller's stream and accumulates the elapsed
- * device time per kernel kind; gap_kernel_stats reads the counts and totals.  Enabling
- * (or re-enabling) resets the counters; disabling keeps them readable.  While enabled the
- * iteration blocks are launched without graph capture (opts->graph is ignored), since
- * events recorded by graph nodes cannot be timed; the results are bitwise the same.
- * Errors: GAP_EINVAL (NULL grid, unknown kernel), GAP_EDEVICE. */
+/* Measurement support.  gap_kernel_timing(grid, k) with k >= 1 enables timing: from then
+ * on solve_joint_pcg brackets one launch in k of the iteration kernels (every launch for
+ * k = 1; counted over this handle's iteration-kernel launches since the call) with HIP
+ * events on the caller's stream and accumulates the elapsed device time per kernel kind;
+ * gap_kernel_stats reads the number of timed launches and their total.  An odd k samples
+ * both launch parities of the one-launch kernel, and A and B of the two-launch iteration,
+ * equally.  k = 0 disables timing; enabling (or re-enabling) resets the counters,
+ * disabling keeps them readable.  While enabled the iteration blocks are launched without
+ * graph capture (opts->graph is ignored), since events recorded by graph nodes cannot be
+ * timed; the results are bitwise the same.
+ * Errors: GAP_EINVAL (NULL grid, k < 0, unknown kernel), GAP_EDEVICE. */
 enum {
     GAP_KERNEL_PCG_A = 0,  /* u = z + beta u; u^T A u; beta and the stopping test (Table 1 steps 9, 3, 6) */
     GAP_KERNEL_PCG_B = 1,  /* alpha; p, r update; z = M^-1 r (ASSOR II sweeps); r^T z, r^T r (steps 4-8) */

@@ -313,6 +313,9 @@ struct gap_grid_s {
     double minv_omega = 0.0;
     // kernel timing (measurement support)
     bool timing = false;
+    int timing_period = 1;                                   // time one launch in timing_period
+    long long ev_tick = 0;                                   // iteration-kernel launches since enabling
+    bool ev_open = false;                                    // the current launch is timed
     std::vector<hipEvent_t> ev;                              // pairs: start, stop
     std::vector<int> ev_kind;                                // kernel kind of each used pair
     int ev_used = 0;
@@ -388,16 +391,20 @@ gap_status timing_reserve(gap_grid_t g, int pairs)
     return GAP_OK;
 }
 
-// Record the start (before) or stop (after) event of a timed launch.
+// Record the start (before) or stop (after) event of a launch; while timing, one launch in
+// timing_period is timed, counted over the iteration-kernel launches since enabling.
 inline void timing_mark(gap_grid_t g, int kind, bool start, hipStream_t st)
 {
     if (!g->timing) return;
     if (start) {
+        g->ev_open = (g->ev_tick++ % g->timing_period) == 0;
+        if (!g->ev_open) return;
         g->ev_kind[g->ev_used] = kind;
         (void)hipEventRecord(g->ev[2 * g->ev_used], st);
-    } else {
+    } else if (g->ev_open) {
         (void)hipEventRecord(g->ev[2 * g->ev_used + 1], st);
         ++g->ev_used;
+        g->ev_open = false;
     }
 }
 
@@ -1311,14 +1318,18 @@ gap_status jacobian_fd(gap_grid_t g, const double* F, double* J, void* stream)
 gap_status gap_kernel_timing(gap_grid_t g, int32_t enable)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    if (enable < 0) return fail(GAP_EINVAL, "kernel timing period %d is negative", enable);
     if (enable) {
         for (int k = 0; k < GAP_KERNEL_COUNT; ++k) {
             g->launches[k] = 0;
             g->total_ms[k] = 0.0;
         }
+        g->timing_period = enable;
+        g->ev_tick = 0;
     }
     g->timing = enable != 0;
     g->ev_used = 0;
+    g->ev_open = false;
     return GAP_OK;
 }
 
@@ -1410,9 +1421,13 @@ gap_status tune_run(gap_grid_t g, const gap_solver_opts* t, double* p, void* str
         g->launches[k] = 0;
         g->total_ms[k] = 0.0;
     }
+    const int period = g->timing_period;
     g->timing = true;
+    g->timing_period = 1;
+    g->ev_tick = 0;
     gap_status s = solve_joint_pcg(g, t, p, nullptr, stream);
     g->timing = false;
+    g->timing_period = period;
     if (s != GAP_OK && s != GAP_ENOCONV) return s;
     const int ka = t->iteration == GAP_ITERATION_ONE_LAUNCH ? GAP_KERNEL_PCG_ONE : GAP_KERNEL_PCG_A;
     const int kb = t->iteration == GAP_ITERATION_ONE_LAUNCH ? -1 : GAP_KERNEL_PCG_B;

@@ -73,6 +73,22 @@ def test_timing_hooks_do_not_change_results(iteration):
             assert n[k][0] >= 2 * i0 and n[k][1] > 0
         else:
             assert n[k][0] == 0
+    # one launch in three: the same launches, a third of them timed, at the same average
+    per_solve = sum(n[k][0] for k in timed) // 2
+    G.gap_kernel_timing(s.handle, 3)
+    p3, i3, _ = solve_copy(s, **kw)
+    G.gap_kernel_timing(s.handle, 0)
+    n3 = [G.gap_kernel_stats(s.handle, k) for k in range(G.GAP_KERNEL_COUNT)]
+    assert np.array_equal(p0, p3) and i3 == i0
+    assert sum(n3[k][0] for k in timed) == (per_solve + 2) // 3
+    avg1 = sum(n[k][1] for k in timed) / sum(n[k][0] for k in timed)
+    avg3 = sum(n3[k][1] for k in timed) / sum(n3[k][0] for k in timed)
+    log(f"  timed launches {per_solve} per solve, {sum(n3[k][0] for k in timed)} at one in three; "
+        f"average {1e3 * avg1:.1f} us against {1e3 * avg3:.1f} us")
+    assert 0.5 < avg3 / avg1 < 2.0
+    with pytest.raises(G.GapError) as ei:
+        G.gap_kernel_timing(s.handle, -1)
+    assert ei.value.status == G.GAP_EINVAL
     s.close()
 
 
