@@ -104,12 +104,17 @@ def cpu_baselines(samples, iterations_gpu, n_cond):
 
 
 def kernel_source_digest():
-    """sha256 of the PCG kernel sources: counter figures taken for other sources are stale."""
+    """sha256 of the PCG kernel sources with their // comments and blank space removed:
+    counter figures taken for other code are stale, while edits of comments keep them."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("gap_pcg.hpp", "gap_pcg1.hpp", "gap_device.hpp"):
-        with open(os.path.join(ROOT, "paper_2511_06824_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2511_06824_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).split()
+                if code:
+                    h.update((" ".join(code) + "\n").encode())
     return h.hexdigest()[:16]
 
 
@@ -122,8 +127,8 @@ def recorded_traffic(kernel):
     digest = None
     value = None
     for line in open(path):
-        if line.startswith("kernel source digest:"):
-            digest = line.split(":", 1)[1].strip()
+        if line.startswith("kernel source digest"):
+            digest = line.rsplit(":", 1)[1].strip()
         if line.startswith(f"traffic bytes per launch {kernel}:"):
             value = int(line.split(":", 1)[1].strip())
     return value if digest == kernel_source_digest() else None

@@ -8,10 +8,11 @@
 // three sums the previous launch can form: it produces z (z^T A z), holds A u_prev from its
 // own SpMV (z^T A u_prev) and u_prev itself (u_prev^T A u_prev).  So one launch per
 // iteration suffices.  It reduces the partials of the previous launch into beta, alpha and
-// the stopping test (Eq 3.9 / 3.10), then forms u = z + beta u_prev, A u, p += alpha u,
+// the stopping test (Eq 3.9 / 3.10), then forms u = z + beta u_prev, A u,
 // r' = r - alpha A u, z' = M^-1 r', and the partials r'.z', r'.r', z'^T A z', z'^T A u,
-// u^T A u.  The iterates are Table 1's up to rounding: the expansion cancels by the ratio
-// z^T A z / u^T A u, a few units on the gap systems.
+// u^T A u; p += alpha u is folded into every other launch (below).  The iterates are
+// Table 1's up to rounding: the expansion cancels by the ratio z^T A z / u^T A u, a few
+// units on the gap systems.
 //
 // z'^T A z' is summed face by face: k_f (z_i - z_j)^2 over interior faces plus k_f z_i^2 over
 // the two Dirichlet end faces, a sum of non-negative terms.  A row owns its east faces (the
@@ -21,8 +22,8 @@
 //
 // p is not read by the recurrence, so it moves every other iteration: a launch of odd j adds
 // alpha_{j-1} u_{j-1} + alpha_j u_j when a row's z_j and u_{j-1} arrive, and a launch of even j
-// leaves its term pending.  The launch that stops a condition after an even iteration settles
-// the pending term.  The iterates (alpha, beta, r, z, u) are unchanged; p differs only in the
+// leaves its term pending.  The launch that stops or freezes a condition right after an even
+// iteration settles the pending term over the condition's rows.  The iterates (alpha, beta, r, z, u) are unchanged; p differs only in the
 // order of its additions.
 //
 // Bytes per condition-DOF: reads z, u_prev, r and writes u, r', z' (48 B), plus p read and

@@ -39,9 +39,12 @@ def test_recorded_traffic_needs_the_current_kernel_sources(tmp_path, monkeypatch
     prof.write_text(f"kernel source digest: {digest}\ntraffic bytes per launch k_pcg_f: 123456\n")
     assert bench.recorded_traffic("k_pcg_f") == 123456
     assert bench.recorded_traffic("k_pcg_a") is None
-    # a changed kernel source makes the recorded figure stale
+    # an edited comment keeps the recorded figure; changed code makes it stale
     src = root / "paper_2511_06824_amd" / "csrc" / "gap_pcg1.hpp"
-    src.write_text(src.read_text() + "\n// changed\n")
+    src.write_text(src.read_text() + "\n// a comment\n\n")
+    assert bench.kernel_source_digest() == digest
+    assert bench.recorded_traffic("k_pcg_f") == 123456
+    src.write_text(src.read_text() + "constexpr int kProbe = 1;\n")
     assert bench.kernel_source_digest() != digest
     assert bench.recorded_traffic("k_pcg_f") is None
     prof.unlink()
