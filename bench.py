@@ -138,14 +138,14 @@ def _round(d):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.8, 1.2)):
+def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.5, 0.8, 1.0, 1.2)):
     """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
     128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server (HBM-budget
     admission, continuous batching, smallest request first under a work cap of one joint
     2048x1024 system per step) is
     measured first with all requests queued at t = 0 (its capacity); then arrivals run at
     each load x that capacity, against the same requests solved one at a time in arrival
-    order as joint solves, and (at the first load) as plain one-condition-at-a-time solves."""
+    order as joint solves, and (at load 0.8) as plain one-condition-at-a-time solves."""
     import numpy as np
     import synth
     from paper_2511_06824_amd.serve import BatchBackend, GapServer, Request, WallClock, latency_stats, run_fifo
@@ -185,13 +185,13 @@ def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.8, 1.2)):
     print(f"bench: served stream capacity batched {capacity:.3f}/s, one at a time {fifo_capacity:.3f}/s",
           file=sys.stderr, flush=True)
     runs = []
-    for li, load in enumerate(loads):
+    for load in loads:
         rate = load * capacity
         arrivals = synth.poisson_arrivals(np.random.default_rng(seed + 1), rate, count)
         b = latency_stats(batched(make(arrivals)))
         f = latency_stats(run_fifo(make(arrivals)))
         run = {"load": load, "arrival_rate_per_s": round(rate, 3), "batched": _round(b), "one_at_a_time_joint": _round(f)}
-        if li == 0:
+        if load == 0.8:
             run["one_at_a_time_plain"] = _round(latency_stats(plain_fifo(make(arrivals))))
         print(f"bench: served stream at {load} x capacity: batched p50 {b['p50_s']:.3f} s p99 {b['p99_s']:.3f} s, "
               f"one at a time p50 {f['p50_s']:.3f} s p99 {f['p99_s']:.3f} s", file=sys.stderr, flush=True)
