@@ -1,5 +1,5 @@
-// One-launch PCG iteration for gfx950, FP64: Table 1 with ASSOR II (Eq 3.4-3.6), or the
-// stored diagonal of Jacobi (Eq 2.8) / ASSOR I (Eq 3.2).
+// One-launch PCG iteration for gfx950, FP64: Table 1 with ASSOR II (Eq 3.4-3.6), Jacobi
+// (Eq 2.8, 1/D formed from the conductances) or the stored diagonal of ASSOR I (Eq 3.2).
 //
 // Table 1 needs two grid-wide reductions per iteration: alpha's denominator u^T A u depends
 // on the new search direction u = z + beta u_prev over the whole grid, so p and r cannot move
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
     const int op = a.op[c];
     const GAP_AS1 double* kx = as_global(a.kx + (size_t)op * n);
     const GAP_AS1 double* kz = as_global(a.kz + (size_t)op * (n + nt));
-    const GAP_AS1 double* mv = as_global(assor ? a.kx : a.minv + (size_t)op * n);   // read only when !assor
+    const GAP_AS1 double* mv = as_global(assor ? a.kx : a.minv + (size_t)op * n);   // read by ASSOR I only
     const size_t co = (size_t)c * n;
     // cell indices within one condition's vector are 32-bit (n <= 2^27): the loads and stores
     // then take a scalar base and a 32-bit vector offset
@@ -405,7 +405,14 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
                 }
                 yprev[q] = y;
             } else if (make_z) {
-                zv = mv[(unsigned)(s - 1) * nt + i] * rpprev[q];
+                if (a.precond == 0) {
+                    // Jacobi (Eq 2.8): 1/D of row s - 1 from its four conductances, added in the
+                    // order the stored diagonal was formed, so z is the same to the bit
+                    const int iw = i ? i - 1 : nt - 1;
+                    zv = (1.0 / (((skp[i] + skp[iw]) + kzSprev[q]) + kzS[q])) * rpprev[q];
+                } else {
+                    zv = mv[(unsigned)(s - 1) * nt + i] * rpprev[q];
+                }
             }
             if (make_z) {
                 if (own_z) {
