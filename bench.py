@@ -60,6 +60,59 @@ def _oracle_sample(args):
     return t1 - t0, (t2 - t1) / iters, t3 - t2, t3 - t0
 
 
+def band_sample(workload, seed, rings=64):
+    """The oracle's own definition on the headline input, bounded: assembly of condition 0 at
+    full size, banded Cholesky factorization and solve of the leading `rings` rings of its
+    operator (oracle.band_factor / band_solve, natural order, bandwidth n_theta), and the force
+    integral at full size.  The factor of a leading principal block is the leading part of the
+    full factor, computed by the same operations, so the cost per ring is the full
+    factorization's; the block's last n_theta rows have a shorter band, which makes the
+    extrapolation low by about 1 / (2 rings).  Runs with the BLAS's own thread count."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    import oracle
+    import synth
+    case = synth.make_case(workload, seed)
+    gap = oracle.Gap(case.R, case.c, case.L, case.mu, case.U, case.V, case.p_in, case.p_out,
+                     case.n_theta, case.n_axial)
+    tex = oracle.dimple_texture(case.R, case.dimple_theta, case.dimple_z, case.dimple_radius,
+                                case.dimple_depth) if case.n_dimples else oracle.no_texture
+    ek, edk = oracle.conditions(case.e, case.edot, case.delta)[0]
+    rings = min(rings, case.n_axial)
+    m = rings * case.n_theta
+    t0 = time.perf_counter()
+    A, S = oracle.assemble(gap, ek, edk, tex)
+    t1 = time.perf_counter()
+    cb = oracle.band_factor(A[:m, :m], case.n_theta)
+    t2 = time.perf_counter()
+    oracle.band_solve(cb, S[:m])
+    t3 = time.perf_counter()
+    del cb
+    # the force integral over a field of the full size (its cost does not depend on the values)
+    oracle.forces_for_condition(gap, ek, np.zeros(case.n), tex)
+    t4 = time.perf_counter()
+    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("internal_api") == "openblas"] or [1])
+    return {"assemble_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "forces_s": t4 - t3,
+            "rings": rings, "n_axial": case.n_axial, "threads": threads, "sample_s": t4 - t0}
+
+
+def band_baseline(b, n_cond=9, n_op=5):
+    """cpu_baseline from the band sample: n_cond assemblies, n_op factorizations (conditions
+    5-8 share the operator of condition 0), n_cond solves and force integrals, the
+    factorization and the solve scaled from `rings` rings to the full axial length."""
+    scale = b["n_axial"] / b["rings"]
+    solve_s = (n_cond * b["assemble_s"] + n_op * scale * b["factor_s"] + n_cond * scale * b["solve_s"]
+               + n_cond * b["forces_s"])
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": b["threads"], "kind": "oracle",
+            "sample": (f"oracle (banded Cholesky, the exact solve) on condition 0 of the same input, "
+                       f"{b['threads']} BLAS threads: full-size assembly {b['assemble_s']:.2f} s, factorization "
+                       f"and solve of the leading {b['rings']} of {b['n_axial']} rings {b['factor_s']:.2f} s and "
+                       f"{b['solve_s']:.2f} s, full-size force integral {b['forces_s']:.2f} s; scaled to {n_cond} "
+                       f"assemblies, {n_op} factorizations (conditions 5-8 share the operator of 0), {n_cond} "
+                       f"solves and force integrals over all {b['n_axial']} rings"),
+            "sample_seconds": round(b["sample_s"], 3), "seconds_per_solve": round(solve_s, 3)}
+
+
 def cpu_samples(workload, seed, n_cond, all_cores, iters=200):
     """The oracle's samples, taken before the GPU is initialized (the all-core leg forks
     worker processes): condition 0 on one core, and (all_cores) the n_cond conditions at
@@ -77,13 +130,14 @@ def cpu_samples(workload, seed, n_cond, all_cores, iters=200):
 
 
 def cpu_baselines(samples, iterations_gpu, n_cond):
-    """cpu_baseline (one core: condition 0's sample scaled to n_cond conditions and the GPU's
-    iteration count) and the all-core figure (each condition's own sample scaled the same way,
+    """Extrapolations of the oracle's PCG (not its exact solve, which is cpu_baseline): one core,
+    condition 0's sample scaled to n_cond conditions and the GPU's iteration count; and the
+    all-core figure (each condition's own sample scaled the same way,
     the conditions spread over the worker processes, longest first)."""
     single, multi, iters = samples
     asm, per_it, frc, samp = single
     solve_s = n_cond * (asm + iterations_gpu * per_it + frc)
-    one = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    one = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle PCG, extrapolated",
            "sample": (f"oracle on condition 0 of the same input, one thread: assembly {asm:.2f} s, "
                       f"{iters} ASSOR-II PCG iterations {per_it * iters:.2f} s, forces {frc:.2f} s; "
                       f"scaled to {n_cond} conditions x {iterations_gpu} iterations"),
@@ -95,7 +149,7 @@ def cpu_baselines(samples, iterations_gpu, n_cond):
         for t in sorted((a + iterations_gpu * pi + f for a, pi, f, _ in res), reverse=True):
             loads[loads.index(min(loads))] += t
         span = max(loads)
-        allc = {"value": 1.0 / span, "unit": "solves/s", "cores": cores, "kind": "oracle",
+        allc = {"value": 1.0 / span, "unit": "solves/s", "cores": cores, "kind": "oracle PCG, extrapolated",
                 "sample": (f"oracle on all {n_cond} conditions at once, one process per core ({cores} processes, "
                            f"one thread each, {wall:.1f} s wall): each condition's assembly, {iters} PCG iterations "
                            f"and forces, scaled to {iterations_gpu} iterations"),
@@ -335,11 +389,14 @@ def main():
 
     # the oracle's CPU samples first: the all-core leg forks workers, which must happen before
     # this process initializes the GPU
-    samples = None
+    samples, band = None, None
     if not args.no_cpu_baseline:
         samples = cpu_samples(args.workload, args.seed, 9, all_cores=not args.no_cpu_all_cores)
-        print(f"bench: oracle samples taken ({samples[0][3]:.1f} s one core"
+        print(f"bench: oracle PCG samples taken ({samples[0][3]:.1f} s one core"
               + (f", {samples[1][2]:.1f} s wall on {samples[1][0]} processes)" if samples[1] else ")"),
+              file=sys.stderr, flush=True)
+        band = band_sample(args.workload, args.seed)
+        print(f"bench: oracle band sample taken ({band['sample_s']:.1f} s, {band['threads']} threads)",
               file=sys.stderr, flush=True)
 
     import torch
@@ -543,9 +600,10 @@ def main():
     if not args.no_dynamics:
         dyn = run_dynamics(torch, G, JointGapSolver, dev)
 
-    cpu, cpu_all = None, None
+    cpu, cpu_pcg, cpu_all = None, None, None
     if samples is not None:
-        cpu, cpu_all = cpu_baselines(samples, int(round(mean_iters)), n_cond)
+        cpu = band_baseline(band, n_cond, n_op)
+        cpu_pcg, cpu_all = cpu_baselines(samples, int(round(mean_iters)), n_cond)
 
     out = {
         "metric": METRIC, "value": args.steps / elapsed, "unit": "solves/s", "n_gpus": 1,
@@ -566,7 +624,7 @@ def main():
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in stats.items()},
         "roofline": roofline, "roofline_iteration": roofline_iteration, "plain_baseline": plain, "serving": serving, "adjoint_vs_fd": adjoint, "precond_study": study, "dynamics": dyn,
-        "cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all,
+        "cpu_baseline": cpu, "cpu_pcg_extrapolation": cpu_pcg, "cpu_pcg_extrapolation_all_cores": cpu_all,
     }
     print(json.dumps(out), flush=True)
     solver.close()

@@ -34,7 +34,7 @@ against a closed form, an invariant, a brute-force solve or a textbook limit.
 
 from .film import Gap, cell_centers, film, film_naive, film_rate, dimple_texture, no_texture
 from .fvm import face_conductances, source, cell_values, stencil_matrix, assemble, conditions, assemble_joint
-from .direct import solve_band, solve_dense, sor_solve
+from .direct import solve_band, band_factor, band_solve, solve_dense, sor_solve
 from .pcg import pcg, pcg_blocks, jacobi_precond, assor1_precond, assor2_precond, assor2_explicit
 from .forces import (effective_pressure, force_moment, forces_for_condition, force_moment_split,
                      forces_split_for_condition, rebuild_field)
@@ -45,7 +45,7 @@ from . import dynamics
 __all__ = [
     "Gap", "cell_centers", "film", "film_naive", "film_rate", "dimple_texture", "no_texture",
     "face_conductances", "source", "cell_values", "stencil_matrix", "assemble", "conditions", "assemble_joint",
-    "solve_band", "solve_dense", "sor_solve",
+    "solve_band", "band_factor", "band_solve", "solve_dense", "sor_solve",
     "pcg", "pcg_blocks", "jacobi_precond", "assor1_precond", "assor2_precond", "assor2_explicit",
     "effective_pressure", "force_moment", "forces_for_condition", "force_moment_split",
     "forces_split_for_condition", "rebuild_field",

@@ -51,22 +51,40 @@ def _load():
 
 
 def upper_band(A, u):
-    """LAPACK upper band storage ab[u + i - j, j] = A[i, j] for j - u <= i <= j."""
+    """LAPACK upper band storage ab[u + i - j, j] = A[i, j] for j - u <= i <= j.
+
+    Built in Fortran order, so that LAPACK factors it in place: at 2048 x 1024 the band
+    alone is 34 GB, and a second copy would not fit in the memory of a host."""
     A = sp.coo_matrix(A)
     n = A.shape[0]
     keep = (A.col >= A.row)
     if np.any(A.col[keep] - A.row[keep] > u):
         raise ValueError("matrix has entries beyond the declared bandwidth")
-    ab = np.zeros((u + 1, n), dtype=A.dtype)
+    if not np.all(np.isfinite(A.data)):
+        raise ValueError("matrix has non-finite entries")
+    ab = np.zeros((u + 1, n), dtype=A.dtype, order="F")
     np.add.at(ab, (u + A.row[keep] - A.col[keep], A.col[keep]), A.data[keep])
     return ab
 
 
+def band_factor(A, bandwidth):
+    """Upper Cholesky factor U (A = U^T U) in LAPACK band storage (dpbtrf), in place."""
+    ab = upper_band(A, bandwidth)
+    return sla.cholesky_banded(ab, overwrite_ab=True, lower=False, check_finite=False)
+
+
+def band_solve(cb, S):
+    """Solve with a factor from ``band_factor``: S may hold one or several right-hand sides
+    (n,) or (n, m)."""
+    S = np.asarray(S, dtype=float)
+    if not np.all(np.isfinite(S)):
+        raise ValueError("right-hand side has non-finite entries")
+    return sla.cho_solve_banded((cb, False), S, check_finite=False)
+
+
 def solve_band(A, S, bandwidth):
     """Exact solution of the SPD system by banded Cholesky elimination."""
-    ab = upper_band(A, bandwidth)
-    cb = sla.cholesky_banded(ab, lower=False, check_finite=True)
-    return sla.cho_solve_banded((cb, False), np.asarray(S, dtype=float), check_finite=True)
+    return band_solve(band_factor(A, bandwidth), S)
 
 
 def solve_dense(A, S):

@@ -145,3 +145,17 @@ def make_case(name, seed=0, **kw):
     w = WORKLOADS[name]
     f = smooth_case if w["kind"] == "smooth" else textured_case
     return f(w["n_theta"], w["n_axial"], seed, **kw)
+
+
+def projection_weights(n, count=4, seed=7000):
+    """Seeded standard-normal weight vectors (count, n) for random projections w . p of a
+    pressure field: a check of the whole field against stored values without storing it."""
+    return np.stack([np.random.default_rng(seed + m).standard_normal(n) for m in range(count)])
+
+
+def golden_sample_index(n_theta, n_axial, col_stride=32, row_stride=16):
+    """Rows and columns of the stored pressure sample: every row_stride-th ring and every
+    col_stride-th column, plus the last ring (outlet end) and the last column (wrap)."""
+    rows = np.unique(np.concatenate([np.arange(0, n_axial, row_stride), [n_axial - 1]]))
+    cols = np.unique(np.concatenate([np.arange(0, n_theta, col_stride), [n_theta - 1]]))
+    return rows, cols

@@ -119,3 +119,31 @@ def test_empty_batch_steps_and_polls():
         G.gap_batch_step(b, 4, use_graph, stream)
     assert G.gap_batch_poll(b) == []
     G.gap_batch_destroy(b)
+
+
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
+                         ids=["two_launch", "one_launch"])
+def test_non_finite_warm_start_reports_enonfinite_and_the_handle_recovers(iteration):
+    """A warm-start field holding a NaN: r_0 = S - A p_0 is NaN near that cell, so the first
+    reduction is not finite.  The solve stops with GAP_ENONFINITE (NaN arithmetic only, every
+    kernel runs its bounded loops), and a cold solve on the same handle afterwards gives the
+    same pressure, bit for bit, as the one before."""
+    case = synth.smooth_case(64, 32, 3)
+    log(f"case: {case.label}, NaN in the warm start, iteration kind {iteration}")
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    p0, info0 = s.solve(omega=1.8, eps=1e-12, iteration=iteration)
+    p0 = p0.clone()
+    s.p[5 * s.n + 1234] = float("nan")
+    _, info = s.solve(omega=1.8, eps=1e-12, warm_start=True, raise_on_error=False, iteration=iteration)
+    log(f"  status {info.status} after {info.iterations} iterations: {G.gap_last_error()}")
+    assert info.status == G.GAP_ENONFINITE
+    assert "non-finite" in G.gap_last_error()
+    s.p.fill_(float("nan"))
+    with pytest.raises(G.GapError) as ei:
+        s.solve(omega=1.8, eps=1e-12, warm_start=True, iteration=iteration)
+    assert ei.value.status == G.GAP_ENONFINITE
+    p1, info1 = s.solve(omega=1.8, eps=1e-12, iteration=iteration)
+    assert info1.status == G.GAP_OK and info1.iterations == info0.iterations
+    assert torch.equal(p1, p0)
+    s.close()
