@@ -151,6 +151,23 @@ gap_status gap_default_opts(gap_solver_opts *opts);
 gap_status create_gap_grid(const gap_geom *geom, const gap_dimples *dimples, int32_t max_cond,
                            gap_grid_t *out);
 
+/* create_gap_grid with a general texture field h_Text(theta, z) of Eq 2.3 in place of the
+ * dimple list, for any layout (grooves, pockets, measured surfaces).  The assembly needs the
+ * film at cell centres and at the faces, so the field comes sampled at three sets of points,
+ * each a device array of non-negative depths (m, the pocket depth added to h) that the call
+ * copies; the caller keeps ownership:
+ *   tex_c  [n_axial][n_theta]      at the cell centres (theta_i, z_j), theta_i = (i + 1/2) dtheta,
+ *                                  z_j = (j + 1/2) dz
+ *   tex_e  [n_axial][n_theta]      at the east faces (theta_i + dtheta / 2, z_j); column
+ *                                  n_theta - 1 is the face at theta = 2 pi (= 0)
+ *   tex_f  [n_axial + 1][n_theta]  at the axial faces (theta_i, f dz), f = 0 .. n_axial
+ *                                  (rows 0 and n_axial are the Dirichlet ends z = 0, L)
+ * The texture rides on the piston and adds no squeeze term.  Synchronizes the device.
+ * Errors: as create_gap_grid; GAP_EINVAL also for NULL arrays and for a non-finite or
+ * negative depth (the message names the array and index). */
+gap_status create_gap_grid_field(const gap_geom *geom, const double *tex_c, const double *tex_e,
+                                 const double *tex_f, int32_t max_cond, gap_grid_t *out);
+
 /* Release a handle and all its device memory (waits for its pending work).  NULL is a
  * no-op. */
 gap_status destroy_gap_grid(gap_grid_t grid);

@@ -896,6 +896,42 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     return GAP_OK;
 }
 
+gap_status create_gap_grid_field(const gap_geom* geom, const double* tex_c, const double* tex_e, const double* tex_f,
+                                 int32_t max_cond, gap_grid_t* out)
+{
+    if (!out) return fail(GAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!tex_c || !tex_e || !tex_f) return fail(GAP_EINVAL, "tex_c, tex_e and tex_f must be non-NULL");
+    gap_grid_t g = nullptr;
+    gap_status st = create_gap_grid(geom, nullptr, max_cond, &g);
+    if (st != GAP_OK) return st;
+    const size_t n = g->n, nf = (size_t)(g->nz + 1) * g->nt;
+    const TablesDev t = g->tables();
+    hipError_t e = hipMemcpy((double*)t.tex_c, tex_c, n * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy((double*)t.tex_e, tex_e, n * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy((double*)t.tex_f, tex_f, nf * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+        release(g);
+        return fail(GAP_EDEVICE, "copying the texture field: %s", hipGetErrorString(e));
+    }
+    // a depth must be finite and >= 0 (a pocket in the piston surface): checked once, here
+    std::vector<double> host(2 * n + nf);
+    e = hipMemcpy(host.data(), t.tex_c, host.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        release(g);
+        return fail(GAP_EDEVICE, "reading the texture field back: %s", hipGetErrorString(e));
+    }
+    for (size_t k = 0; k < host.size(); ++k)
+        if (!is_finite(host[k]) || host[k] < 0.0) {
+            const char* which = k < n ? "tex_c" : (k < 2 * n ? "tex_e" : "tex_f");
+            const size_t at = k < n ? k : (k < 2 * n ? k - n : k - 2 * n);
+            release(g);
+            return fail(GAP_EINVAL, "%s[%zu] = %g: texture depths must be finite and >= 0", which, at, host[k]);
+        }
+    *out = g;
+    return GAP_OK;
+}
+
 gap_status destroy_gap_grid(gap_grid_t g)
 {
     if (!g) return GAP_OK;

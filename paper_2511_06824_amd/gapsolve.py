@@ -106,6 +106,7 @@ _SIGNATURES = {
     "gap_default_opts": [ctypes.POINTER(gap_solver_opts)],
     "create_gap_grid": [ctypes.POINTER(gap_geom), ctypes.POINTER(gap_dimples), ctypes.c_int32,
                         ctypes.POINTER(_P)],
+    "create_gap_grid_field": [ctypes.POINTER(gap_geom), _P, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)],
     "destroy_gap_grid": [_P],
     "assemble_joint_system": [_P, _D8, _D8, _D8, ctypes.c_int32, _P],
     "solve_joint_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(gap_solve_info), _P],
@@ -208,6 +209,14 @@ def create_gap_grid(geom, dimples, max_cond):
     h = ctypes.c_void_p()
     _check(load().create_gap_grid(ctypes.byref(geom), ctypes.byref(dimples) if dimples is not None else None,
                                   int(max_cond), ctypes.byref(h)))
+    return h
+
+
+def create_gap_grid_field(geom, tex_c_ptr, tex_e_ptr, tex_f_ptr, max_cond):
+    h = ctypes.c_void_p()
+    _check(load().create_gap_grid_field(ctypes.byref(geom), ctypes.c_void_p(int(tex_c_ptr)),
+                                        ctypes.c_void_p(int(tex_e_ptr)), ctypes.c_void_p(int(tex_f_ptr)),
+                                        int(max_cond), ctypes.byref(h)))
     return h
 
 

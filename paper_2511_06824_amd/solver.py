@@ -17,7 +17,7 @@ class JointGapSolver:
     J (4 x 8), all float64 on `device`."""
 
     def __init__(self, R, clearance, length, mu, U, V, p_in, p_out, n_theta, n_axial,
-                 dimples=None, max_cond=9, device="cuda:0"):
+                 dimples=None, max_cond=9, device="cuda:0", texture=None):
         if not torch.cuda.is_available():
             raise RuntimeError("JointGapSolver needs a HIP GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
@@ -29,7 +29,21 @@ class JointGapSolver:
         if dimples is not None and len(dimples[0]) > 0:
             dm = G.make_dimples(*dimples)
         with torch.cuda.device(self.device):
-            self.handle = G.create_gap_grid(self.geom, dm, self.max_cond)
+            if texture is not None:
+                # a sampled texture field: (centres, east faces, axial faces), see create_gap_grid_field
+                if dm is not None:
+                    raise ValueError("give either dimples or a texture field, not both")
+                shapes = [(self.n_axial, self.n_theta), (self.n_axial, self.n_theta),
+                          (self.n_axial + 1, self.n_theta)]
+                planes = [torch.as_tensor(t, dtype=torch.float64).to(self.device).contiguous() for t in texture]
+                for t, shp in zip(planes, shapes):
+                    if tuple(t.shape) != shp:
+                        raise ValueError(f"texture plane of shape {tuple(t.shape)}, expected {shp}")
+                torch.cuda.synchronize(self.device)     # the library copies the planes on its own stream
+                self.handle = G.create_gap_grid_field(self.geom, planes[0].data_ptr(), planes[1].data_ptr(),
+                                                      planes[2].data_ptr(), self.max_cond)
+            else:
+                self.handle = G.create_gap_grid(self.geom, dm, self.max_cond)
         self.p = torch.zeros(self.max_cond * self.n, dtype=torch.float64, device=self.device)
         self.F = torch.zeros(self.max_cond * 4, dtype=torch.float64, device=self.device)
         self.J = torch.zeros(32, dtype=torch.float64, device=self.device)

@@ -18,6 +18,11 @@ Workloads (all FP64, SI units):
   drawn as an (8, 20) array, m-major.
 * random dimples: count U{0..200}, centres uniform in theta and in z in [0.2 L, 0.8 L],
   same footprint radius, depth U(5, 15) um.
+* pocket arrays (a texture that is not made of caps, passed as a sampled field): 60
+  pockets around the circumference by 10 ("short") or 20 ("long") rows along the gap,
+  20 um deep, flat-bottomed with half-cosine edge ramps so that the depth is continuous;
+  the rows start 2 mm from the inlet end at a 1 mm pitch, a pocket spans half of each
+  pitch in both directions.
 """
 
 from dataclasses import dataclass, field
@@ -100,6 +105,47 @@ def random_dimples(rng, L=LENGTH, max_count=200):
     zc = rng.uniform(0.2 * L, 0.8 * L, count)
     depth = rng.uniform(5e-6, 15e-6, count)
     return th, zc, np.full(count, DIMPLE_RADIUS), depth
+
+
+def _plateau(x, half, ramp):
+    """1 for |x| <= half - ramp, 0 for |x| >= half, a half-cosine in between."""
+    a = np.abs(x)
+    t = np.clip((a - (half - ramp)) / ramp, 0.0, 1.0)
+    return 0.5 * (1.0 + np.cos(np.pi * t))
+
+
+def pocket_texture(kind="short", depth=20e-6, n_circ=60, L=LENGTH):
+    """Depth function h_text(theta, z) of a pocket array ("short": 60 x 10 pockets,
+    "long": 60 x 20), see the module docstring.  Returns a callable of numpy arrays."""
+    n_ax = {"short": 10, "long": 20}[kind]
+    pitch_t = 2.0 * np.pi / n_circ
+    pitch_z = 1e-3
+    z0 = 2e-3
+    half_t, half_z = 0.25 * pitch_t, 0.25 * pitch_z
+    ramp_t, ramp_z = 0.3 * half_t, 0.3 * half_z
+
+    def tex(theta, z):
+        theta, z = np.broadcast_arrays(np.asarray(theta, dtype=float), np.asarray(z, dtype=float))
+        # offset from the nearest pocket centre, in theta (centres at (k + 1/2) pitch,
+        # periodic) and in z (within the rows)
+        dt = np.mod(theta, pitch_t) - 0.5 * pitch_t
+        m = np.clip(np.floor((z - z0) / pitch_z), 0, n_ax - 1)
+        dz = z - (z0 + (m + 0.5) * pitch_z)
+        return depth * _plateau(dt, half_t, ramp_t) * _plateau(dz, half_z, ramp_z)
+
+    return tex
+
+
+def texture_samples(tex, n_theta, n_axial, L=LENGTH):
+    """The depth function sampled where the assembly needs the film: cell centres
+    [n_axial, n_theta], east faces [n_axial, n_theta] and axial faces [n_axial + 1, n_theta]."""
+    dth, dz = 2.0 * np.pi / n_theta, L / n_axial
+    i = np.arange(n_theta)
+    th_c, th_e = (i + 0.5) * dth, (i + 1.0) * dth
+    z_c = (np.arange(n_axial) + 0.5) * dz
+    z_f = np.arange(n_axial + 1) * dz
+    return (tex(th_c[None, :], z_c[:, None]), tex(th_e[None, :], z_c[:, None]),
+            tex(th_c[None, :], z_f[:, None]))
 
 
 def textured_case(n_theta, n_axial, seed, **kw):
