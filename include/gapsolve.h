@@ -199,6 +199,27 @@ gap_status solve_joint_pcg(gap_grid_t grid, const gap_solver_opts *opts, double 
 gap_status integrate_force_moment(gap_grid_t grid, const double *p, int32_t cavitation,
                                   double p_cav, double *F, void *stream);
 
+/* integrate_force_moment without a handle, for callers that cannot allocate device memory
+ * (work recorded under stream capture, serving loops or harnesses that forbid hipMalloc).
+ * It allocates nothing: its partial sums and its cos / sin table live in a fixed device
+ * array of the library (384 KiB per GPU, held until the process ends), so it needs
+ * 2 n_theta + 4 * (row chunks) <= 49152 doubles, where the row chunks number at most
+ * 2048 + n_cond; larger grids are rejected with GAP_EINVAL.
+ *   geom        grid, fluid and boundary data (validated as for create_gap_grid)
+ *   n_cond      1 .. 9 pressure fields
+ *   e           host, n_cond x 4 doubles: (e1, e2, e3, e4) of each field's film (Eq 2.3)
+ *   tex_c       device, n doubles: texture depth h_Text at the cell centres, or NULL (smooth)
+ *   p           device, n_cond x n doubles (condition-major)
+ *   cavitation, p_cav, F (device, n_cond x 4) as for integrate_force_moment.
+ * The result equals integrate_force_moment's for the same film up to the rounding of the
+ * cos / sin table (formed on the device here).  Every call on one GPU shares that GPU's
+ * scratch array, so calls that overlap on one GPU (different streams or host threads) race;
+ * calls ordered on one stream do not.  Errors: GAP_EINVAL, GAP_ECONTACT (|e| >= clearance at
+ * a gap end), GAP_EDEVICE. */
+gap_status integrate_force_moment_noalloc(const gap_geom *geom, int32_t n_cond, const double *e,
+                                          const double *tex_c, const double *p, int32_t cavitation,
+                                          double p_cav, double *F, void *stream);
+
 /* The forces of integrate_force_moment split into the normal-pressure part and the
  * viscous-shear part (the paper reports them separately, Sec 4.3), with the axial force and
  * the torque of the shear: F (device, n_cond x 10 doubles) per condition

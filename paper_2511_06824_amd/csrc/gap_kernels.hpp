@@ -186,7 +186,7 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, Chu
             else if (j == nz - 1) dpdz = (g.p_out - peff(p[gi - nt], cav, p_cav)) / (1.5 * g.dz);
             else dpdz = (peff(p[gi + nt], cav, p_cav) - peff(p[gi - nt], cav, p_cav)) / (2.0 * g.dz);
             const double cs = tb.cos_c[i], sn = tb.sin_c[i];
-            const double h = film_h(g, e, cs, sn, zj, tb.tex_c[gi]);
+            const double h = film_h(g, e, cs, sn, zj, tb.tex_c ? tb.tex_c[gi] : 0.0);
             const double tt = -0.5 * h * dpdx + g.mu * g.U / h;
             const double tz = -0.5 * h * dpdz + g.mu * g.V / h;
             if (NV == 4) {
@@ -211,6 +211,18 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_forces(GeomDev g, CondDev cd, Chu
     block_sum<NV>(acc);
     if (threadIdx.x == 0)
         for (int q = 0; q < NV; ++q) partial[q * cm.total + blockIdx.x] = acc[q];
+}
+
+// cos and sin of the cell-centre angles theta_i = (i + 1/2) dtheta, i < nt, formed on the
+// device (the handle-free force integration has no host-built table).
+__global__ __launch_bounds__(GAP_BLOCK) void k_trig_centres(int nt, double dth, double* __restrict__ cs,
+                                                            double* __restrict__ sn)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const double th = (i + 0.5) * dth;
+    cs[i] = cos(th);
+    sn[i] = sin(th);
 }
 
 __device__ __forceinline__ double cond_sum(const double* part, const ChunkMap& cm, int c)

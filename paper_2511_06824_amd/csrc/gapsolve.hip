@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -709,6 +710,27 @@ gap_status finish_solve(gap_grid_t g, int n_cond, gap_solve_info* info)
     return result;
 }
 
+// The geometry as the kernels see it.
+GeomDev geom_dev(const gap_geom& geom)
+{
+    GeomDev d{};
+    d.R = geom.R;
+    d.Rc = geom.R + geom.clearance;
+    d.c2R = geom.clearance * (2.0 * geom.R + geom.clearance);
+    d.L = geom.length;
+    d.mu = geom.mu;
+    d.U = geom.U;
+    d.V = geom.V;
+    d.p_in = geom.p_in;
+    d.p_out = geom.p_out;
+    d.nt = geom.n_theta;
+    d.nz = geom.n_axial;
+    d.dth = 2.0 * M_PI / d.nt;
+    d.dz = geom.length / d.nz;
+    d.dx = geom.R * d.dth;
+    return d;
+}
+
 gap_status validate_geom(const gap_geom* g)
 {
     if (!g) return fail(GAP_EINVAL, "geom is NULL");
@@ -780,21 +802,8 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     g->n = (size_t)g->nt * g->nz;
     g->max_cond = max_cond;
     g->max_op = (max_cond == GAP_MAX_COND) ? 5 : 1;
-    GeomDev& d = g->gd;
-    d.R = geom->R;
-    d.Rc = geom->R + geom->clearance;
-    d.c2R = geom->clearance * (2.0 * geom->R + geom->clearance);
-    d.L = geom->length;
-    d.mu = geom->mu;
-    d.U = geom->U;
-    d.V = geom->V;
-    d.p_in = geom->p_in;
-    d.p_out = geom->p_out;
-    d.dth = 2.0 * M_PI / g->nt;
-    d.dz = geom->length / g->nz;
-    d.dx = geom->R * d.dth;
-    d.nt = g->nt;
-    d.nz = g->nz;
+    g->gd = geom_dev(*geom);
+    const GeomDev& d = g->gd;
 
     const size_t n = g->n, nt = g->nt;
     const ChunkMap cm_max = make_chunks(g->nz, 1);
@@ -1323,6 +1332,92 @@ gap_status integrate_force_moment_split(gap_grid_t g, const double* p, int32_t c
     hipLaunchKernelGGL(k_forces_finalize, dim3(1), dim3(GAP_BLOCK), 0, st, cm, g->n_cond, 10, g->gd.dx * g->gd.dz,
                        (const double*)g->partial, F);
     HIPLAUNCHCHK("split force integration");
+    return GAP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device scratch of integrate_force_moment_noalloc: the cos / sin table of the cell centres
+// (2 n_theta doubles) followed by the per-chunk partial sums (4 per row chunk).  Each GPU holds
+// its own copy for the life of the process.  In host code `scratch` is only a stand-in for the
+// symbol: every use goes through the device address that hipGetSymbolAddress returns.
+constexpr size_t kScratchDoubles = 49152;   // 384 KiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per device.
+gap_status scratch_address(double** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GAP_EDEVICE, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(GAP_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gap_status integrate_force_moment_noalloc(const gap_geom* geom, int32_t n_cond, const double* e, const double* tex_c,
+                                          const double* p, int32_t cavitation, double p_cav, double* F, void* stream)
+{
+    gap_status st = validate_geom(geom);
+    if (st != GAP_OK) return st;
+    if (n_cond < 1 || n_cond > GAP_MAX_COND) return fail(GAP_EINVAL, "n_cond = %d outside [1, %d]", n_cond, GAP_MAX_COND);
+    if (!e || !p || !F) return fail(GAP_EINVAL, "e, p and F must be non-NULL");
+    if (cavitation != GAP_CAVITATION_NONE && cavitation != GAP_CAVITATION_CLAMP)
+        return fail(GAP_EINVAL, "unknown cavitation mode");
+    if (!is_finite(p_cav)) return fail(GAP_EINVAL, "p_cav must be finite");
+    CondDev cd{};
+    for (int c = 0; c < n_cond; ++c) {
+        for (int q = 0; q < 4; ++q) {
+            if (!is_finite(e[4 * c + q])) return fail(GAP_EINVAL, "e of condition %d is not finite", c);
+            cd.e[c][q] = e[4 * c + q];
+        }
+        const double c0 = std::hypot(cd.e[c][0], cd.e[c][1]);
+        const double c1 = std::hypot(cd.e[c][2], cd.e[c][3]);
+        if (c0 >= geom->clearance || c1 >= geom->clearance)
+            return fail(GAP_ECONTACT, "condition %d: |e| at a gap end (%.6g, %.6g) >= clearance %.6g", c, c0, c1,
+                        geom->clearance);
+    }
+    cd.n_cond = n_cond;
+    const int nt = geom->n_theta;
+    const ChunkMap cm = make_chunks(geom->n_axial, n_cond);
+    const size_t need = 2 * (size_t)nt + 4 * (size_t)cm.total;
+    if (need > kScratchDoubles)
+        return fail(GAP_EINVAL, "n_theta = %d, n_axial = %d, %d conditions need %zu scratch doubles, the limit is %zu",
+                    nt, geom->n_axial, n_cond, need, kScratchDoubles);
+    double* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != GAP_OK) return st;
+    const GeomDev gd = geom_dev(*geom);
+    TablesDev tb{};
+    tb.cos_c = ws;
+    tb.sin_c = ws + nt;
+    tb.tex_c = tex_c;
+    double* part = ws + 2 * nt;
+    hipStream_t hs = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_trig_centres, dim3((nt + GAP_BLOCK - 1) / GAP_BLOCK), dim3(GAP_BLOCK), 0, hs, nt, gd.dth, ws,
+                       ws + nt);
+    hipLaunchKernelGGL((k_forces<4>), dim3(cm.total), dim3(GAP_BLOCK), 0, hs, gd, cd, cm, tb, p, cavitation, p_cav,
+                       part);
+    hipLaunchKernelGGL(k_forces_finalize, dim3(1), dim3(GAP_BLOCK), 0, hs, cm, n_cond, 4, gd.dx * gd.dz,
+                       (const double*)part, F);
+    HIPLAUNCHCHK("handle-free force integration");
     return GAP_OK;
 }
 

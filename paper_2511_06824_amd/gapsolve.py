@@ -112,6 +112,8 @@ _SIGNATURES = {
     "solve_joint_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(gap_solve_info), _P],
     "integrate_force_moment": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
     "integrate_force_moment_split": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
+    "integrate_force_moment_noalloc": [ctypes.POINTER(gap_geom), ctypes.c_int32, _D8, _P, _P, ctypes.c_int32,
+                                       ctypes.c_double, _P, _P],
     "rebuild_pressure_field": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
     "jacobian_fd": [_P, _P, _P, _P],
     "gap_read_system": [_P, ctypes.c_int32, _P, _P, _P, _P],
@@ -247,6 +249,16 @@ def integrate_force_moment(handle, p_ptr, cavitation, p_cav, F_ptr, stream=None)
 def integrate_force_moment_split(handle, p_ptr, cavitation, p_cav, F_ptr, stream=None):
     _check(load().integrate_force_moment_split(handle, ctypes.c_void_p(int(p_ptr)), int(cavitation), float(p_cav),
                                                ctypes.c_void_p(int(F_ptr)), _stream(stream)))
+
+
+def integrate_force_moment_noalloc(geom, e, tex_c_ptr, p_ptr, cavitation, p_cav, F_ptr, stream=None):
+    """e: n_cond rows of (e1, e2, e3, e4); tex_c_ptr: device address or None (smooth)."""
+    rows = [list(map(float, row)) for row in e]
+    flat = [v for row in rows for v in row]
+    _check(load().integrate_force_moment_noalloc(ctypes.byref(geom), len(rows), _darr(flat, 4 * len(rows)),
+                                                 ctypes.c_void_p(int(tex_c_ptr) if tex_c_ptr else 0),
+                                                 ctypes.c_void_p(int(p_ptr)), int(cavitation), float(p_cav),
+                                                 ctypes.c_void_p(int(F_ptr)), _stream(stream)))
 
 
 def rebuild_pressure_field(handle, p_ptr, cavitation, p_cav, out_ptr, stream=None):
