@@ -29,9 +29,11 @@ def kernel_bytes(n, n_cond, n_op):
     """Algorithmic HBM bytes of one launch of each iteration kernel: every vector operand is
     read or written once per condition-DOF; the face conductances (kx, kz: 16 B per
     operator-DOF) once per distinct operator.  k_pcg_a reads z, u_prev and writes u; k_pcg_b
-    reads u, p, r and writes p, r, z; the one-launch k_pcg_f reads z, u_prev, r and writes
-    u, r, z, and reads and writes p on every other launch (7 operands on average)."""
-    vec = {"k_pcg_a": 3, "k_pcg_b": 6, "k_pcg_f": 7}
+    reads u, p, r and writes p, r, z; the whole-ring one-launch k_pcg_f reads z, u_prev, r and
+    writes u, r, z, and reads and writes p on every other launch (7 operands on average); the
+    strip kernel k_pcg_w recomputes z, so it reads r, u_prev and writes u, r, plus p on every
+    other launch (5 operands on average)."""
+    vec = {"k_pcg_a": 3, "k_pcg_b": 6, "k_pcg_f": 7, "k_pcg_w": 5}
     return {k: 8 * v * n * n_cond + 16 * n * n_op for k, v in vec.items()}
 
 
@@ -163,7 +165,7 @@ def kernel_source_digest():
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("gap_pcg.hpp", "gap_pcg1.hpp", "gap_device.hpp"):
+    for f in ("gap_pcg.hpp", "gap_pcg1.hpp", "gap_pcgw.hpp", "gap_device.hpp"):
         with open(os.path.join(ROOT, "paper_2511_06824_amd", "csrc", f)) as fh:
             for line in fh:
                 code = re.sub(r"//.*", "", line).split()
@@ -192,32 +194,44 @@ def _round(d):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.5, 0.8, 1.0, 1.2)):
+SERVE_COUNTS = {0.5: 48, 0.8: 96, 1.0: 96, 1.2: 48}   # requests per load
+SERVE_BULK = (2048, 1024)        # requests of this many cells or more run in the bulk lane
+SERVE_TARGETS = (2, 1)           # strip-kernel workgroups per CU: bulk lane, fast lane
+
+
+def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=48, targets=SERVE_TARGETS):
     """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
-    128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server (HBM-budget
-    admission, continuous batching, smallest request first under a work cap of one joint
-    2048x1024 system per step) is
-    measured first with all requests queued at t = 0 (its capacity); then arrivals run at
-    each load x that capacity, against the same requests solved one at a time in arrival
-    order as joint solves, and (at load 0.8) as plain one-condition-at-a-time solves."""
+    128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server runs two
+    lanes over one HBM budget: 2048x1024 requests in a bulk batch, one after another in arrival
+    order (its launches chunked to `targets[0]` workgroups per CU), the smaller ones in a fast
+    batch whose every step advances all of them, on a second stream and host thread, beside
+    the bulk launches.  Its capacity is measured first, with `capacity_count` requests queued
+    at t = 0; then arrivals run at each load x that capacity (counts[load] requests), against
+    the same requests solved one at a time in arrival order as joint solves, and (at load 0.8)
+    as plain one-condition-at-a-time solves."""
     import numpy as np
     import synth
-    from paper_2511_06824_amd.serve import BatchBackend, GapServer, Request, WallClock, latency_stats, run_fifo
+    from paper_2511_06824_amd.serve import BatchBackend, LaneServer, Request, WallClock, latency_stats, run_fifo
+    counts = counts or SERVE_COUNTS
 
     def make(arrivals):
         rng = np.random.default_rng(seed)
         return [Request(rid=k, case=synth.served_request(rng, seed * 1000 + k), arrival=float(arrivals[k]))
-                for k in range(count)]
+                for k in range(len(arrivals))]
 
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    work_cap = 9 * 2048 * 1024               # one joint 2048 x 1024 system per step
+    bulk_work = 9 * SERVE_BULK[0] * SERVE_BULK[1]
+    streams = (torch.cuda.Stream(dev), torch.cuda.Stream(dev))
 
     def batched(reqs):
-        be = BatchBackend(iterations_per_step=32)
-        done = GapServer(be, budget_bytes=budget, work_cap=work_cap).run(reqs)
-        be.close()
-        return done
+        bulk = BatchBackend(iterations_per_step=32, stream=streams[0], wg_per_cu=targets[0])
+        fast = BatchBackend(iterations_per_step=32, stream=streams[1], wg_per_cu=targets[1])
+        try:
+            return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work).run(reqs)
+        finally:
+            bulk.close()
+            fast.close()
 
     def plain_fifo(reqs):
         clock = WallClock()
@@ -230,28 +244,34 @@ def run_serving(torch, JointGapSolver, dev, count=24, seed=0, loads=(0.5, 0.8, 1
             done.append(r)
         return done
 
-    run_fifo(make(np.zeros(count))[:3])          # warm-up: kernels and graphs of every size
-    batched(make(np.zeros(count))[:3])
-    backlog = batched(make(np.zeros(count)))
-    capacity = count / max(r.finished for r in backlog)
-    fifo_back = run_fifo(make(np.zeros(count)))
-    fifo_capacity = count / max(r.finished for r in fifo_back)
+    warm = make(np.zeros(10))                   # warm-up: kernels and graphs of every size
+    run_fifo(warm)
+    batched(make(np.zeros(10)))
+    backlog = batched(make(np.zeros(capacity_count)))
+    capacity = capacity_count / max(r.finished for r in backlog)
+    fifo_back = run_fifo(make(np.zeros(capacity_count)))
+    fifo_capacity = capacity_count / max(r.finished for r in fifo_back)
     print(f"bench: served stream capacity batched {capacity:.3f}/s, one at a time {fifo_capacity:.3f}/s",
           file=sys.stderr, flush=True)
     runs = []
-    for load in loads:
+    for load, count in sorted(counts.items()):
         rate = load * capacity
         arrivals = synth.poisson_arrivals(np.random.default_rng(seed + 1), rate, count)
         b = latency_stats(batched(make(arrivals)))
         f = latency_stats(run_fifo(make(arrivals)))
-        run = {"load": load, "arrival_rate_per_s": round(rate, 3), "batched": _round(b), "one_at_a_time_joint": _round(f)}
+        run = {"load": load, "requests": count, "arrival_rate_per_s": round(rate, 3), "batched": _round(b),
+               "one_at_a_time_joint": _round(f)}
         if load == 0.8:
-            run["one_at_a_time_plain"] = _round(latency_stats(plain_fifo(make(arrivals))))
-        print(f"bench: served stream at {load} x capacity: batched p50 {b['p50_s']:.3f} s p99 {b['p99_s']:.3f} s, "
-              f"one at a time p50 {f['p50_s']:.3f} s p99 {f['p99_s']:.3f} s", file=sys.stderr, flush=True)
+            run["one_at_a_time_plain"] = _round(latency_stats(plain_fifo(make(arrivals[:48]))))
+            run["one_at_a_time_plain"]["note"] = "the first 48 requests of the stream"
+        print(f"bench: served stream at {load} x capacity ({count} requests): batched p50 {b['p50_s']:.3f} s "
+              f"p99 {b['p99_s']:.3f} s, one at a time p50 {f['p50_s']:.3f} s p99 {f['p99_s']:.3f} s",
+              file=sys.stderr, flush=True)
         runs.append(run)
-    return {"requests": count, "capacity_batched_per_s": round(capacity, 3),
-            "capacity_one_at_a_time_joint_per_s": round(fifo_capacity, 3), "work_cap_dofs": work_cap,
+    return {"capacity_requests": capacity_count, "capacity_batched_per_s": round(capacity, 3),
+            "capacity_one_at_a_time_joint_per_s": round(fifo_capacity, 3),
+            "lanes": {"bulk_cells_min": list(SERVE_BULK), "wg_per_cu_bulk": targets[0], "wg_per_cu_fast": targets[1],
+                      "iterations_per_step": 32},
             "hbm_budget_bytes": budget, "runs": runs}
 
 
@@ -370,6 +390,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default PCG kernel configuration")
+    ap.add_argument("--strip-config", default=None,
+                    help="Q,W: strip kernel with Q columns per lane and W workgroups per CU, instead of tuning it")
     ap.add_argument("--no-study", action="store_true", help="skip the preconditioner / omega study")
     ap.add_argument("--no-dynamics", action="store_true", help="skip the general-iteration time steps")
     ap.add_argument("--no-two-launch", action="store_true", help="skip the two-launch iteration comparison")
@@ -415,7 +437,12 @@ def main():
 
     # autotuner: kernel shape and row chunking, timed on this system (outside the timed region)
     tune = None
-    if not args.no_tune:
+    if args.strip_config:
+        q, w = (int(x) for x in args.strip_config.split(","))
+        tune = {"config": solver.set_strip_config(q, w), "us_per_iteration": None, "seconds": 0.0,
+                "given": args.strip_config}
+        print(f"bench: strip configuration given {tune['config']}", file=sys.stderr, flush=True)
+    elif not args.no_tune:
         solver.assemble(case.e, case.edot, case.delta, 9)
         torch.cuda.synchronize()
         tt0 = time.perf_counter()
@@ -447,6 +474,71 @@ def main():
     per_cond = {"solves_per_s": round(1.0 / (time.perf_counter() - tp0), 5), "iterations": info_pc.iterations,
                 "scalars": "per condition, synchronized stopping test (Eq 3.9)"}
     print(f"bench: per-condition scalars {per_cond}", file=sys.stderr, flush=True)
+
+    # the accuracy the pressure gate needs: the same step at eps 1e-12 (the stored exact solution
+    # of this workload is met to 1e-9 there; at the configured 1e-10 the error is larger)
+    opts_gate = solver.options(omega=case.omega, eps=1e-12)
+    solver.step(case.e, case.edot, case.delta, opts_gate)
+    torch.cuda.synchronize()
+    tq0 = time.perf_counter()
+    _, _, info_q = solver.step(case.e, case.edot, case.delta, opts_gate)
+    torch.cuda.synchronize()
+    gate_eps = {"eps": 1e-12, "solves_per_s": round(1.0 / (time.perf_counter() - tq0), 5),
+                "iterations": info_q.iterations, "true_rel_residual": info_q.true_rel_residual}
+    print(f"bench: at the gate accuracy {gate_eps}", file=sys.stderr, flush=True)
+
+    # the Neumann order picked by time to solution (orders 1 .. 3 of the series of Eq 3.4, each
+    # with its own tuned strip configuration); the headline stays at order 1 (Eq 3.4)
+    neumann = None
+    if not args.no_tune:
+        cfg_keep = G.gap_get_pcg_config(solver.handle)
+        solver.assemble(case.e, case.edot, case.delta, 9)
+        best_m, secs_m = solver.tune_neumann(opts, max_order=3)
+        opts_m = solver.options(omega=case.omega, eps=case.eps, neumann=best_m)
+        solver.step(case.e, case.edot, case.delta, opts_m)
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(2):
+            _, _, info_m = solver.step(case.e, case.edot, case.delta, opts_m)
+        torch.cuda.synchronize()
+        neumann = {"order": best_m, "solves_per_s": round(2.0 / (time.perf_counter() - tm0), 5),
+                   "iterations": info_m.iterations, "true_rel_residual": info_m.true_rel_residual,
+                   "pcg_seconds_by_order": [round(x, 4) for x in secs_m],
+                   "config": {k: v for k, v in solver.pcg_config.items() if k.endswith("_w")}}
+        print(f"bench: Neumann order tuned {neumann}", file=sys.stderr, flush=True)
+        G.gap_set_pcg_config(solver.handle, cfg_keep)
+
+    # the whole-ring one-launch iteration (z stored), tuned on its own, graph-replayed
+    ring_one = None
+    if not args.no_two_launch:
+        opts1 = solver.options(omega=case.omega, eps=case.eps, iteration=G.GAP_ITERATION_ONE_LAUNCH)
+        solver.assemble(case.e, case.edot, case.delta, 9)
+        cfg1, us1 = solver.tune(opts1, iterations=20) if not args.no_tune else (solver.pcg_config, None)
+        solver.step(case.e, case.edot, case.delta, opts1)
+        torch.cuda.synchronize()
+        t10 = time.perf_counter()
+        for _ in range(2):
+            _, _, info1 = solver.step(case.e, case.edot, case.delta, opts1)
+        torch.cuda.synchronize()
+        ring_one = {"graph_solves_per_s": round(2.0 / (time.perf_counter() - t10), 5),
+                    "iterations": info1.iterations, "tuned_us_per_iteration": us1 and round(us1, 2),
+                    "kernels": "k_pcg_f",
+                    "config": {k: v for k, v in cfg1.items() if k[-1] == "f"}}
+        # its launches timed by HIP events (one in the timing period) over one more solve
+        G.gap_kernel_timing(solver.handle, args.timing_period)
+        solver.step(case.e, case.edot, case.delta, solver.options(omega=case.omega, eps=case.eps,
+                                                                   iteration=G.GAP_ITERATION_ONE_LAUNCH, graph=False))
+        torch.cuda.synchronize()
+        cnt1, ms1 = G.gap_kernel_stats(solver.handle, G.GAP_KERNEL_PCG_ONE)
+        G.gap_kernel_timing(solver.handle, 0)
+        if cnt1:
+            b1 = kernel_bytes(n, n_cond, n_op)["k_pcg_f"]
+            a1 = b1 / (1e-3 * ms1 / cnt1) / 1e9
+            ring_one["roofline"] = {"bound": "hbm", "achieved": round(a1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(a1 / HBM_PEAK_GBS, 4), "kernel": "k_pcg_f",
+                                    "bytes_per_launch": b1, "avg_launch_us": round(1e3 * ms1 / cnt1, 2),
+                                    "traffic": recorded_traffic("k_pcg_f")}
+        print(f"bench: whole-ring one-launch iteration {ring_one}", file=sys.stderr, flush=True)
 
     # the two-launch iteration (Table 1 as printed), tuned on its own, graph-replayed
     two_launch = None
@@ -612,13 +704,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_theta": case.n_theta, "n_axial": case.n_axial,
                    "n_cond": n_cond, "dimples": case.n_dimples, "omega": case.omega, "eps": case.eps,
-                   "precond": "ASSOR-II (Neumann order 1)", "scalars": "global", "iteration": "one launch",
+                   "precond": "ASSOR-II (Neumann order 1)", "scalars": "global",
+                   "iteration": "one launch per iteration on wavefront strips (k_pcg_w)",
                    "seed": args.seed},
         "gdof_iter_per_s": round(gdof, 3), "iterations": mean_iters,
         "median_ms_per_step": round(1e3 * sorted(step_s)[len(step_s) // 2], 3),
         "true_rel_residual": max(true_rel),
         "graph_solves_per_s": round(graph_solves_per_s, 5),
         "pcg_config": solver.pcg_config, "tune": tune, "per_condition_scalars": per_cond,
+        "at_gate_eps": gate_eps, "neumann_tuned": neumann, "whole_ring_one_launch": ring_one,
         "two_launch_iteration": two_launch, "spectrum": spectrum, "other_seeds": seeds, "strategies": strategies, "paper_meshes": meshes,
         "timed_region": f"plain launches with a HIP event pair around one PCG kernel launch in {args.timing_period}",
         "t_pcg_ms_per_solve": 1e3 * t_pcg / args.steps,

@@ -63,7 +63,7 @@ enum { GAP_PRECOND_JACOBI = 0, GAP_PRECOND_ASSOR1 = 1, GAP_PRECOND_ASSOR2 = 2 };
 enum { GAP_SCALARS_GLOBAL = 0, GAP_SCALARS_PER_COND = 1 };
 enum { GAP_STRATEGY_SYNC = 0, GAP_STRATEGY_ASYNC = 1 };
 enum { GAP_CAVITATION_NONE = 0, GAP_CAVITATION_CLAMP = 1 };
-enum { GAP_ITERATION_TWO_LAUNCH = 0, GAP_ITERATION_ONE_LAUNCH = 1 };
+enum { GAP_ITERATION_TWO_LAUNCH = 0, GAP_ITERATION_ONE_LAUNCH = 1, GAP_ITERATION_STRIPS = 2 };
 #define GAP_MAX_COND 9
 
 /* Gap geometry, fluid and boundary data (Eq 2.3; Table 8 lists the paper's pump).
@@ -75,7 +75,8 @@ enum { GAP_ITERATION_TWO_LAUNCH = 0, GAP_ITERATION_ONE_LAUNCH = 1 };
  *              axial (any sign)
  *   p_in       Dirichlet pressure at z = 0 (south boundary, Sec 2.1)
  *   p_out      Dirichlet pressure at z = L (north boundary)
- *   n_theta    cells around the circumference, 3 <= n_theta <= 2048 (one workgroup holds a ring)
+ *   n_theta    cells around the circumference, 3 <= n_theta <= 16384 (the iteration kinds
+ *              whose workgroups hold whole rings need n_theta <= 2048)
  *   n_axial    cells along the gap, 2 <= n_axial <= 65536                                */
 typedef struct {
     double R, clearance, length, mu, U, V, p_in, p_out;
@@ -98,7 +99,10 @@ typedef struct {
  *   max_iter     iteration cap, >= 1
  *   precond      GAP_PRECOND_ASSOR2 (Eq 3.4, the paper's "ASSOR"), _ASSOR1 (Eq 3.2) or
  *                _JACOBI (Eq 2.8)
- *   neumann      Neumann order of the ASSOR II inverse; 1 is Eq 3.4 (only 1 is supported)
+ *   neumann      Neumann order M of the ASSOR II inverse: the series of (I + w D^-1 L)^-1 and
+ *                of its transpose truncated after M terms; 1 is Eq 3.4.  1, 2 or 3 with
+ *                GAP_ITERATION_STRIPS and GAP_PRECOND_ASSOR2 (order 3 runs with one column
+ *                per lane); 1 otherwise.  All requests of one batch use the same order.
  *   scalars      GAP_SCALARS_GLOBAL: one alpha/beta for the joint system (CG on A_G);
  *                GAP_SCALARS_PER_COND: one recurrence per condition
  *   strategy     GAP_STRATEGY_SYNC: stop when ||r_G|| / ||S_G|| <= eps (Eq 3.9);
@@ -115,13 +119,24 @@ typedef struct {
  *                (u and u^T A u; then alpha and the updates).  GAP_ITERATION_ONE_LAUNCH:
  *                one launch per iteration, with u^T A u = z^T A z + 2 beta z^T A u_prev +
  *                beta^2 u_prev^T A u_prev from sums the previous launch forms (A is
- *                symmetric).  The iterates agree up to rounding.  All requests of one
- *                batch (gap_batch_*) use the same kind.                                */
+ *                symmetric); each workgroup holds whole rings (n_theta <= 2048).
+ *                GAP_ITERATION_STRIPS: the one-launch scheme with each wavefront marching a
+ *                strip of columns (neighbours by lane shifts, no LDS rows), z_j recomputed
+ *                from r_j instead of stored (fewer bytes per iteration), any n_theta.  The
+ *                three kinds give the same iterates up to rounding.  All requests of one
+ *                batch (gap_batch_*) use the same kind.
+ *   eps_adjoint  stopping tolerance of the adjoint systems of jacobian_adjoint and
+ *                solve_with_adjoint (each on ||r_i|| / ||g_i||, Eq 3.10), >= 0; 0: eps.  The
+ *                adjoint Jacobian is a product lambda_i^T b_k with no differencing, so its
+ *                error follows the adjoint residual without the 1/delta amplification that
+ *                forward differences put on the forces; a looser tolerance than the base
+ *                solve's suffices for a given Jacobian accuracy.                         */
 typedef struct {
     double omega, eps;
     int32_t max_iter, precond, neumann, scalars, warm_start, check_every, graph, strategy;
     int32_t iteration;
     int32_t reserved;
+    double eps_adjoint;
 } gap_solver_opts;
 
 /* Result of a solve.  iterations counts completed Table 1 iterations (SpMV + update);
@@ -138,8 +153,8 @@ typedef struct {
 } gap_solve_info;
 
 /* Fill *opts with the defaults: omega 1.6, eps 1e-10, max_iter 100000, ASSOR II,
- * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1, SYNC strategy, one-launch
- * iteration.  Returns GAP_EINVAL if NULL. */
+ * neumann 1, GLOBAL scalars, cold start, check_every 32, graph 1, SYNC strategy, strip
+ * iteration (GAP_ITERATION_STRIPS), eps_adjoint 0 (= eps).  Returns GAP_EINVAL if NULL. */
 gap_status gap_default_opts(gap_solver_opts *opts);
 
 /* Create a handle for one gap (Eq 2.3 geometry, Sec 2.1 grid) that can hold up to
@@ -325,6 +340,19 @@ gap_status general_iteration_step(gap_grid_t grid, const gap_solver_opts *opts, 
  * "not assembled").  Errors: GAP_EINVAL (NULL grid, non-finite value). */
 gap_status set_operating_point(gap_grid_t grid, double U, double V, double p_in, double p_out);
 
+/* Autotuner of the ASSOR II Neumann order (Sec 3.1: the series of Eq 3.4 truncated after M
+ * terms in each factor; M = 1 is Eq 3.4) for the strip iteration: for M = 1 .. max_order
+ * (<= 3) it tunes the kernel configuration as gap_tune_pcg does, then times one complete
+ * solve of the assembled system with opts (after a warm one), and keeps the configuration of
+ * the fastest order on the handle.  *best receives that order (set opts->neumann to it for
+ * the solves that follow) and seconds (NULL or max_order doubles) the time of each order's
+ * solve.  opts must select GAP_PRECOND_ASSOR2 and GAP_ITERATION_STRIPS.  Overwrites p and
+ * the Krylov state, synchronizes stream, resets the counters of gap_kernel_stats.  Errors:
+ * GAP_EINVAL, GAP_ESTATE (nothing assembled), GAP_ENOCONV / GAP_ENONFINITE from a solve,
+ * GAP_EDEVICE. */
+gap_status gap_tune_neumann(gap_grid_t grid, const gap_solver_opts *opts, double *p, int32_t max_order,
+                            int32_t *best, double *seconds, void *stream);
+
 /* Copy the assembled system of condition k to caller device buffers (inspection and
  * testing): kx (n doubles, east-face conductances h^3/(12 mu) dz/dx), kz
  * ((n_axial + 1) * n_theta doubles, axial-face conductances h^3/(12 mu) dx/dz, doubled on
@@ -349,7 +377,8 @@ enum {
     GAP_KERNEL_PCG_A = 0,  /* u = z + beta u; u^T A u; beta and the stopping test (Table 1 steps 9, 3, 6) */
     GAP_KERNEL_PCG_B = 1,  /* alpha; p, r update; z = M^-1 r (ASSOR II sweeps); r^T z, r^T r (steps 4-8) */
     GAP_KERNEL_PCG_ONE = 2, /* one-launch iteration: all of steps 3-9 */
-    GAP_KERNEL_COUNT = 3
+    GAP_KERNEL_PCG_STRIPS = 3, /* one-launch iteration on wavefront strips, z recomputed */
+    GAP_KERNEL_COUNT = 4
 };
 gap_status gap_kernel_timing(gap_grid_t grid, int32_t enable);
 gap_status gap_kernel_stats(gap_grid_t grid, int32_t kernel, int64_t *launches, double *total_ms);
@@ -394,6 +423,12 @@ typedef struct {
     int32_t cols_per_thread_f;
     int32_t wg_per_cu_f;
     int32_t occupancy_f;        /* output */
+    int32_t cols_per_lane_w;    /* W (strip iteration): ring columns per lane, 1 or 2; a
+                                   wavefront's strip spans 64 x cols_per_lane_w columns and owns
+                                   all but 6 on either side */
+    int32_t wg_per_cu_w;        /* W: row chunking target, >= 1 */
+    int32_t occupancy_w;        /* output: W workgroups (4 wavefronts each) that fit on one CU */
+    int32_t strips_w;           /* output: strips per ring */
 } gap_pcg_config;
 
 /* Read the configuration the next solve_joint_pcg of this handle uses.
@@ -435,6 +470,13 @@ gap_status gap_grid_bytes(const gap_geom *geom, int32_t max_cond, int64_t *bytes
 
 /* Create an empty batch.  Errors: GAP_EINVAL, GAP_ENOMEM, GAP_EDEVICE. */
 gap_status gap_batch_create(gap_batch_t *out);
+
+/* Workgroups per CU the strip kernel's row chunking of the requests added from now on targets
+ * (wg_per_cu >= 1; 0 restores the default, as many as fit).  A batch that targets fewer than
+ * fit leaves room on every CU for the launches of another batch on another stream, so two
+ * batches (say one for large and one for small requests) overlap on the device.  Results
+ * depend on the target only through the summation order.  Errors: GAP_EINVAL. */
+gap_status gap_batch_set_target(gap_batch_t batch, int32_t wg_per_cu);
 
 /* Destroy a batch (the grid handles of its requests are not touched).  NULL is a no-op. */
 gap_status gap_batch_destroy(gap_batch_t batch);

@@ -88,8 +88,12 @@ struct PcgDev {
     int chunks_a, rows_a;       // row chunks per condition of the A launch
     int chunks_b, rows_b;       // row chunks per condition of the B launches
     double omega, eps;
+    double eps_c[GAP_MAXC];     // per-condition tolerance of the asynchronized test (Eq 3.10)
     int max_iter, per_cond, warm, precond;   // precond: 0 Jacobi, 1 ASSOR I, 2 ASSOR II
     int async;                  // 1: each condition stops at its own test (Eq 3.10) and is frozen
+    // strip iteration (gap_pcgw.hpp): strips per ring and strip groups (workgroups) per row
+    // chunk; chunks_b counts row chunks x groups, rows_b the rows of a row chunk
+    int n_strips, strip_groups;
 };
 
 // A launch covers one or more joint systems ("requests"), each described by a PcgDev in
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_a(const PcgDev* __restrict__ reqs
     double dn = 0.0, dp = 0.0, rr = 0.0, ss = 0.0;
     for (int k = 0; k < a.n_cond; ++k) {
         const double sk = sums[3][k] > 0.0 ? sums[3][k] : 1.0;
-        const bool act = !a.async || sqrt(sums[2][k] / sk) > a.eps;
+        const bool act = !a.async || sqrt(sums[2][k] / sk) > a.eps_c[k];
         if (act) {
             active |= 1u << k;
             dn += sums[0][k];

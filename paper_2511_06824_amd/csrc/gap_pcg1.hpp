@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT, (Q >= 4 ? 2 : 4)) void k_pcg_f(const PcgDev* __
         double rr = 0.0, ss = 0.0;
         for (int k = 0; k < a.n_cond; ++k) {
             const double sk = sums[5][k] > 0.0 ? sums[5][k] : 1.0;
-            const bool act = !a.async || (((was_active >> k) & 1) && sqrt(sums[1][k] / sk) > a.eps);
+            const bool act = !a.async || (((was_active >> k) & 1) && sqrt(sums[1][k] / sk) > a.eps_c[k]);
             if (act) active |= 1u << k;
             rr += sums[1][k];
             ss += sums[5][k];

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -14,6 +15,7 @@
 #include "gap_kernels.hpp"
 #include "gap_pcg.hpp"
 #include "gap_pcg1.hpp"
+#include "gap_pcgw.hpp"
 #include "gap_adjoint.hpp"
 
 namespace {
@@ -55,7 +57,8 @@ bool is_finite(double x) { return std::isfinite(x); }
     } while (0)
 
 constexpr int kTargetChunks = 2048;
-constexpr int kMaxThetaCells = 2048;
+constexpr int kMaxThetaCells = 16384;
+constexpr int kMaxRingCells = 2048;     // kernels whose workgroups hold whole rings
 constexpr int kMaxAxialCells = 65536;
 
 ChunkMap make_chunks(int nz, int n_cond)
@@ -73,6 +76,8 @@ ChunkMap make_chunks(int nz, int n_cond)
 // thread (thread t handles columns t, t + NT, ...), NT * Q >= n_theta.
 struct PcgShape {
     int NT = 512, Q = 4;
+    int pk = -1;    // strip kernel: the preconditioner compiled in (-1: read from each request)
+    int M = 1;      // strip kernel: the Neumann order of ASSOR II
 };
 
 // Every instantiated shape.
@@ -100,7 +105,7 @@ std::vector<PcgShape> pcg_candidates(int nt)
 }
 
 // Kernels of the PCG iteration, by the `which` argument of the launch helpers.
-enum { kPcgA = 0, kPcgB = 1, kPcgInit = 2, kPcgOne = 3, kPcgOneInit = 4 };
+enum { kPcgA = 0, kPcgB = 1, kPcgInit = 2, kPcgOne = 3, kPcgOneInit = 4, kPcgStrip = 5, kPcgStripInit = 6 };
 
 // Dynamic LDS: A (u row, double-buffered); B and its init (u and y rows, two rows of the
 // first ASSOR sweep); the one-launch kernel and its init (those four, two z rows and a ring
@@ -133,12 +138,16 @@ void pcg_chunks(int nz, int nt, int n_cond, int slots, int& chunks, int& rows)
 // Packed work entry of a PCG launch: request << 24 | chunk << 4 | condition.
 inline int pcg_entry(int req, int k, int c) { return (req << 24) | (k << 4) | c; }
 
-// Work groups of one request: per chunk row, the conditions that share an operator.
-void pcg_groups(int req, int chunks, int n_cond, const int* op, std::vector<std::vector<int>>& groups)
+// Work groups of one request: per run of `span` consecutive chunk slots, the conditions that
+// share an operator.  span = 1 for the whole-ring kernels; the strip kernel passes its strip
+// groups per row chunk, so that the workgroups of one row chunk, whose strips read each
+// other's edge columns, land on one XCD with the conditions that share their operator.
+void pcg_groups(int req, int chunks, int n_cond, const int* op, std::vector<std::vector<int>>& groups, int span = 1)
 {
-    for (int k = 0; k < chunks; ++k) {
+    for (int k0 = 0; k0 < chunks; k0 += span) {
         std::vector<std::vector<int>> by_op(GAP_MAXC);
-        for (int c = 0; c < n_cond; ++c) by_op[op[c]].push_back(pcg_entry(req, k, c));
+        for (int k = k0; k < std::min(k0 + span, chunks); ++k)
+            for (int c = 0; c < n_cond; ++c) by_op[op[c]].push_back(pcg_entry(req, k, c));
         for (auto& gcl : by_op)
             if (!gcl.empty()) groups.push_back(gcl);
     }
@@ -168,6 +177,121 @@ std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
     for (int x = 0; x < X; ++x)
         for (size_t m = 0; m < lists[x].size(); ++m) table[m * X + x] = lists[x][m];
     return table;
+}
+
+// ---- strip kernel (gap_pcgw.hpp): shape = (kStripThreads, Q columns per lane) ----------
+constexpr int kStripMaxQ = 2;
+constexpr int kStripDefaultQ = 2;
+constexpr int kMinStripRows = 16;      // a row chunk recomputes 7 halo rows
+
+bool strip_q_known(int Q) { return Q >= 1 && Q <= kStripMaxQ; }
+
+// Columns per lane the strip kernel runs with for the configured Q and Neumann order M: order
+// 3 has one column per lane only.
+inline int strip_q(int Q, int M) { return M >= 3 ? 1 : Q; }
+
+// Strips per ring and strip groups (workgroups of kStripWaves strips) per row chunk, for Q
+// columns per lane and Neumann order M.
+void strip_layout(int nt, int Q, int M, int& strips, int& groups)
+{
+    const int w = strip_owned_max(Q, M);
+    strips = (nt + w - 1) / w;
+    groups = (strips + kStripWaves - 1) / kStripWaves;
+}
+
+// Row chunks of a strip launch: about `slots` workgroups in all (occupancy x CUs, a single
+// round), at least kMinStripRows rows per chunk, at most kMaxChunks partial-sum slots per
+// request and at most n_axial per condition (the partial arrays hold that many).
+void strip_chunks(int nz, int nt, int n_cond, int Q, int M, int slots, PcgDev& a)
+{
+    int strips = 1, groups = 1;
+    strip_layout(nt, Q, M, strips, groups);
+    int per = slots / (n_cond * groups);
+    per = std::min(per, std::max(1, nz / kMinStripRows));
+    per = std::min(per, std::max(1, nz / groups));
+    per = std::min(per, std::max(1, kMaxChunks / (n_cond * groups)));
+    if (per < 1) per = 1;
+    const int rows = (nz + per - 1) / per;
+    const int chunks = (nz + rows - 1) / rows;
+    a.n_strips = strips;
+    a.strip_groups = groups;
+    a.rows_b = a.rows_a = rows;
+    a.chunks_b = a.chunks_a = chunks * groups;
+}
+
+// The strip kernels of Q columns per lane: the initial residual (preconditioner read from
+// the request) for each Neumann order, and the iteration for each preconditioner, fixed or
+// read from the request; ASSOR II with Neumann orders 1 .. kStripMaxNeumann.
+template <int Q>
+const void* strip_fn(bool init, int pk, int M)
+{
+    // two columns per lane at order 3 would spill most of its registers: not instantiated
+    if (Q >= 2 && M >= 3) return nullptr;
+    if (init) {
+        switch (M) {
+        case 1: return (const void*)k_pcg_w<Q, -1, 1, true>;
+        case 2: return (const void*)k_pcg_w<Q, -1, 2, true>;
+        case 3: return (const void*)k_pcg_w<(Q < 2 ? Q : 1), -1, 3, true>;
+        default: return nullptr;
+        }
+    }
+    if (pk == 2) {
+        switch (M) {
+        case 1: return (const void*)k_pcg_w<Q, 2, 1, false>;
+        case 2: return (const void*)k_pcg_w<Q, 2, 2, false>;
+        case 3: return (const void*)k_pcg_w<(Q < 2 ? Q : 1), 2, 3, false>;
+        default: return nullptr;
+        }
+    }
+    if (M != 1) return nullptr;
+    switch (pk) {
+    case 0: return (const void*)k_pcg_w<Q, 0, 1, false>;
+    case 1: return (const void*)k_pcg_w<Q, 1, 1, false>;
+    default: return (const void*)k_pcg_w<Q, -1, 1, false>;
+    }
+}
+
+template <int Q>
+hipError_t strip_prepare_t(int M, int* occupancy)
+{
+    // the occupancy of the ASSOR II iteration of order M and of its initial residual
+    int occ = 1 << 20;
+    for (int init = 0; init < 2; ++init) {
+        int nb = 0;
+        const void* fn = strip_fn<Q>(init != 0, 2, M);
+        if (!fn) return hipErrorInvalidValue;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStripThreads, 0);
+        if (e != hipSuccess) return e;
+        occ = std::min(occ, nb > 0 ? nb : 1);
+    }
+    *occupancy = occ;
+    return hipSuccess;
+}
+
+// Workgroups of the strip kernel of order M (and its initial residual) that fit on one CU.
+hipError_t strip_prepare(int Q, int M, int* occupancy)
+{
+    switch (Q) {
+    case 1: return strip_prepare_t<1>(M, occupancy);
+    case 2: return strip_prepare_t<2>(M, occupancy);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// pk: the preconditioner of every request in the launch (0, 1, 2), or -1 if they differ;
+// M: their Neumann order.
+hipError_t launch_strip(int Q, int pk, int M, bool init, const PcgDev* reqs, const int* work, int blocks,
+                        hipStream_t st, int par)
+{
+    const void* fn = nullptr;
+    switch (Q) {
+    case 1: fn = strip_fn<1>(init, pk, M); break;
+    case 2: fn = strip_fn<2>(init, pk, M); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {(void*)&reqs, (void*)&work, (void*)&par};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kStripThreads), args, 0, st);
 }
 
 template <int NT, int Q>
@@ -230,6 +354,8 @@ hipError_t pcg_prepare(PcgShape sh, int which, int nt, int* occupancy)
 hipError_t launch_pcg(PcgShape sh, int which, int lds_nt, const PcgDev* reqs, const int* work, int blocks,
                       hipStream_t st, int par = 0)
 {
+    if (which == kPcgStrip || which == kPcgStripInit)
+        return launch_strip(sh.Q, sh.pk, sh.M, which == kPcgStripInit, reqs, work, blocks, st, par);
 #define GAP_SHAPE_CASE(nt_, q_) \
     if (sh.NT == nt_ && sh.Q == q_) return launch_pcg_t<nt_, q_>(which, lds_nt, reqs, work, blocks, st, par);
     GAP_PCG_SHAPES(GAP_SHAPE_CASE)
@@ -237,11 +363,11 @@ hipError_t launch_pcg(PcgShape sh, int which, int lds_nt, const PcgDev* reqs, co
     return hipErrorInvalidValue;
 }
 
-// Capture `iters` iterations into a graph: A, B launch pairs, or (one_launch) launches of
-// the one-launch kernel with parities par0, par0 ^ 1, ... on work_b.
+// Capture `iters` iterations into a graph: A, B launch pairs, or (one_which = kPcgOne or
+// kPcgStrip) launches of that one-launch kernel with parities par0, par0 ^ 1, ... on work_b.
 hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh_a, PcgShape sh_b, int lds_nt, const PcgDev* reqs,
                          const int* work_a,
-                         int blocks_a, const int* work_b, int blocks_b, hipGraphExec_t* exec, bool one_launch = false,
+                         int blocks_a, const int* work_b, int blocks_b, hipGraphExec_t* exec, int one_which = 0,
                          int par0 = 0)
 {
     hipGraph_t graph = nullptr;
@@ -249,8 +375,8 @@ hipError_t capture_block(hipStream_t cap, int iters, PcgShape sh_a, PcgShape sh_
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int it = 0; it < iters && le == hipSuccess; ++it) {
-        if (one_launch) {
-            le = launch_pcg(sh_b, kPcgOne, lds_nt, reqs, work_b, blocks_b, cap, (par0 + it) & 1);
+        if (one_which) {
+            le = launch_pcg(sh_b, one_which, lds_nt, reqs, work_b, blocks_b, cap, (par0 + it) & 1);
             continue;
         }
         le = launch_pcg(sh_a, kPcgA, lds_nt, reqs, work_a, blocks_a, cap);
@@ -309,6 +435,10 @@ struct gap_grid_s {
     int wg_a = 1, wg_b = 1;                                  // workgroups per CU the row chunking targets
     PcgShape shape_f{};                                      // the one-launch kernel (and its init)
     int occ_f = 1, wg_f = 1;
+    PcgShape shape_w{kStripThreads, kStripDefaultQ};         // the strip kernel (and its init)
+    int occ_w = 1, wg_w = 1;
+    int occ_wm[kStripMaxQ + 1][kStripMaxNeumann + 1] = {};  // strip occupancy by (Q, Neumann order), 0: not asked yet
+    bool rings_ok = true;                                    // n_theta fits the whole-ring kernels
     int lds_max = 65536;                                     // bytes of LDS one workgroup may use
     int minv_kind = -1;
     double minv_omega = 0.0;
@@ -454,6 +584,8 @@ void fill_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o)
     a.nz = g->nz;
     a.omega = o->omega;
     a.eps = o->eps;
+    for (int k = 0; k < GAP_MAXC; ++k)          // a caller's per-condition tolerances stay
+        if (!(a.eps_c[k] > 0.0)) a.eps_c[k] = o->eps;
     a.max_iter = o->max_iter;
     a.precond = o->precond;
 }
@@ -461,9 +593,22 @@ void fill_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o)
 gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_t st)
 {
     const int check_every = o->check_every ? o->check_every : 32;
-    const bool one = o->iteration == GAP_ITERATION_ONE_LAUNCH;
+    const bool strip = o->iteration == GAP_ITERATION_STRIPS;
+    const bool one = o->iteration != GAP_ITERATION_TWO_LAUNCH;
+    const int one_which = strip ? kPcgStrip : (one ? kPcgOne : 0);
+    const int kernel_one = strip ? GAP_KERNEL_PCG_STRIPS : GAP_KERNEL_PCG_ONE;
     fill_pcg(g, a, o);
-    if (one) {
+    a.n_strips = a.strip_groups = 1;
+    if (strip) {
+        const int M = o->neumann, Q = strip_q(g->shape_w.Q, M);
+        if (!g->occ_wm[Q][M]) {
+            int occ = 1;
+            const hipError_t oe = strip_prepare(Q, M, &occ);
+            if (oe != hipSuccess) return fail(GAP_EDEVICE, "preparing the strip kernel: %s", hipGetErrorString(oe));
+            g->occ_wm[Q][M] = occ;
+        }
+        strip_chunks(g->nz, g->nt, a.n_cond, Q, M, std::min(g->wg_w, g->occ_wm[Q][M]) * g->cus, a);
+    } else if (one) {
         // one launch per iteration on the B chunking fields
         pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_f * g->cus, a.chunks_b, a.rows_b);
         a.chunks_a = a.chunks_b;
@@ -472,12 +617,17 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_a * g->cus, a.chunks_a, a.rows_a);
         pcg_chunks(g->nz, g->nt, a.n_cond, g->wg_b * g->cus, a.chunks_b, a.rows_b);
     }
-    const PcgShape sh_b = one ? g->shape_f : g->shape_b;
+    PcgShape sh_b = strip ? g->shape_w : (one ? g->shape_f : g->shape_b);
+    if (strip) {
+        sh_b.pk = o->precond;
+        sh_b.M = o->neumann;
+        sh_b.Q = strip_q(sh_b.Q, sh_b.M);
+    }
 
     // schedule tables for this (iteration kind, kernel shapes, n_cond, chunk counts, operator
     // map); graphs are cached by table, so the shapes belong to the key
-    std::vector<int> key = {one ? 1 : 0, one ? 0 : g->shape_a.NT, one ? 0 : g->shape_a.Q, sh_b.NT, sh_b.Q, a.n_cond,
-                            a.chunks_a, a.chunks_b};
+    std::vector<int> key = {o->iteration, one ? 0 : g->shape_a.NT, one ? 0 : g->shape_a.Q, sh_b.NT, sh_b.Q, sh_b.pk,
+                            sh_b.M, a.n_cond, a.chunks_a, a.chunks_b};
     for (int c = 0; c < a.n_cond; ++c) key.push_back(a.op[c]);
     gap_grid_s::Sched* sch = nullptr;
     for (auto& e : g->scheds)
@@ -485,7 +635,7 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     if (!sch) {
         std::vector<std::vector<int>> ga, gb;
         if (!one) pcg_groups(0, a.chunks_a, a.n_cond, a.op, ga);
-        pcg_groups(0, a.chunks_b, a.n_cond, a.op, gb);
+        pcg_groups(0, a.chunks_b, a.n_cond, a.op, gb, strip ? a.strip_groups : 1);
         const std::vector<int> ta = pcg_schedule(ga), tb = pcg_schedule(gb);
         gap_grid_s::Sched e;
         e.key = key;
@@ -517,7 +667,8 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     *g->req_host = a;
     HIPCHK(hipMemcpyAsync(g->req_dev, g->req_host, sizeof(PcgDev), hipMemcpyHostToDevice, st));
 
-    hipError_t le = launch_pcg(sh_b, one ? kPcgOneInit : kPcgInit, g->nt, g->req_dev, work_b, sch->blocks_b, st);
+    hipError_t le = launch_pcg(sh_b, strip ? kPcgStripInit : (one ? kPcgOneInit : kPcgInit), g->nt, g->req_dev, work_b,
+                               sch->blocks_b, st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
 
     // One block = check_every iterations; after each block the host reads the device record.
@@ -528,9 +679,9 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
     auto enqueue_block = [&](hipStream_t s, int iters, bool closing) -> hipError_t {
         for (int it = 0; it < iters + (closing ? 1 : 0); ++it) {
             if (one) {
-                timing_mark(g, GAP_KERNEL_PCG_ONE, true, s);
-                hipError_t e1 = launch_pcg(sh_b, kPcgOne, g->nt, g->req_dev, work_b, sch->blocks_b, s, (int)(launched & 1));
-                timing_mark(g, GAP_KERNEL_PCG_ONE, false, s);
+                timing_mark(g, kernel_one, true, s);
+                hipError_t e1 = launch_pcg(sh_b, one_which, g->nt, g->req_dev, work_b, sch->blocks_b, s, (int)(launched & 1));
+                timing_mark(g, kernel_one, false, s);
                 ++launched;
                 if (e1 != hipSuccess) return e1;
                 continue;
@@ -562,7 +713,7 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
         hipGraphExec_t exec = nullptr;
         hipError_t ce = capture_block(g->cap_stream, check_every, g->shape_a, sh_b, g->nt, g->req_dev, work_a,
-                                      sch->blocks_a, work_b, sch->blocks_b, &exec, one, par0);
+                                      sch->blocks_a, work_b, sch->blocks_b, &exec, one_which, par0);
         if (ce != hipSuccess) return fail(GAP_EDEVICE, "capturing the PCG block: %s", hipGetErrorString(ce));
         if (g->graphs.size() >= 4) {
             (void)hipGraphExecDestroy(g->graphs.front().exec);
@@ -655,20 +806,38 @@ hipError_t use_shape_f(gap_grid_t g, PcgShape sf, int wg_f)
     return hipSuccess;
 }
 
-gap_status validate_opts(const gap_solver_opts* o)
+// Switch the handle's strip kernel to Q columns per lane; wg_w as for use_shape.
+hipError_t use_shape_w(gap_grid_t g, int Q, int wg_w)
+{
+    int occ = 1;
+    const hipError_t e = strip_prepare(Q, 1, &occ);
+    if (e != hipSuccess) return e;
+    g->shape_w = PcgShape{kStripThreads, Q};
+    g->occ_w = occ;
+    g->wg_w = wg_w > 0 ? wg_w : occ;
+    return hipSuccess;
+}
+
+gap_status validate_opts(gap_grid_t g, const gap_solver_opts* o)
 {
     if (!o) return fail(GAP_EINVAL, "opts is NULL");
+    if (!g->rings_ok && o->iteration != GAP_ITERATION_STRIPS)
+        return fail(GAP_EINVAL, "n_theta = %d > %d needs iteration = GAP_ITERATION_STRIPS", g->nt, kMaxRingCells);
     if (!is_finite(o->omega) || !(o->omega > 0.0 && o->omega < 2.0)) return fail(GAP_EINVAL, "omega must lie in (0, 2)");
     if (!is_finite(o->eps) || !(o->eps > 0.0)) return fail(GAP_EINVAL, "eps must be > 0");
+    if (!is_finite(o->eps_adjoint) || o->eps_adjoint < 0.0) return fail(GAP_EINVAL, "eps_adjoint must be >= 0");
     if (o->max_iter < 1) return fail(GAP_EINVAL, "max_iter must be >= 1");
     if (o->precond < GAP_PRECOND_JACOBI || o->precond > GAP_PRECOND_ASSOR2) return fail(GAP_EINVAL, "unknown precond");
-    if (o->precond == GAP_PRECOND_ASSOR2 && o->neumann != 1) return fail(GAP_EINVAL, "neumann must be 1");
+    if (o->neumann < 1 || o->neumann > kStripMaxNeumann) return fail(GAP_EINVAL, "neumann must lie in [1, %d]", kStripMaxNeumann);
+    if (o->neumann != 1 && (o->precond != GAP_PRECOND_ASSOR2 || o->iteration != GAP_ITERATION_STRIPS))
+        return fail(GAP_EINVAL, "Neumann orders above 1 need precond = GAP_PRECOND_ASSOR2 and iteration = GAP_ITERATION_STRIPS");
     if (o->scalars != GAP_SCALARS_GLOBAL && o->scalars != GAP_SCALARS_PER_COND)
         return fail(GAP_EINVAL, "unknown scalars mode");
     if (o->check_every < 0) return fail(GAP_EINVAL, "check_every must be >= 0");
     if (o->strategy != GAP_STRATEGY_SYNC && o->strategy != GAP_STRATEGY_ASYNC)
         return fail(GAP_EINVAL, "unknown strategy");
-    if (o->iteration != GAP_ITERATION_TWO_LAUNCH && o->iteration != GAP_ITERATION_ONE_LAUNCH)
+    if (o->iteration != GAP_ITERATION_TWO_LAUNCH && o->iteration != GAP_ITERATION_ONE_LAUNCH &&
+        o->iteration != GAP_ITERATION_STRIPS)
         return fail(GAP_EINVAL, "unknown iteration kind");
     return GAP_OK;
 }
@@ -766,7 +935,9 @@ gap_status gap_default_opts(gap_solver_opts* o)
     o->check_every = 32;
     o->graph = 1;
     o->strategy = GAP_STRATEGY_SYNC;
-    o->iteration = GAP_ITERATION_ONE_LAUNCH;
+    o->iteration = GAP_ITERATION_STRIPS;
+    o->reserved = 0;
+    o->eps_adjoint = 0.0;
     return GAP_OK;
 }
 
@@ -826,20 +997,30 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
             g->lds_max = lds;
-        g->shape_a = g->shape_b = g->shape_f = pcg_candidates(g->nt)[0];
-        const size_t need = pcg_lds_bytes(kPcgOne, g->shape_f.NT * g->shape_f.Q) + 2048;
-        if (need > (size_t)g->lds_max) {
-            release(g);
-            return fail(GAP_EINVAL, "n_theta = %d needs %zu bytes of LDS per workgroup, the device allows %d",
-                        geom->n_theta, need, g->lds_max);
+        g->rings_ok = g->nt <= kMaxRingCells;
+        if (g->rings_ok) {
+            g->shape_a = g->shape_b = g->shape_f = pcg_candidates(g->nt)[0];
+            const size_t need = pcg_lds_bytes(kPcgOne, g->shape_f.NT * g->shape_f.Q) + 2048;
+            if (need > (size_t)g->lds_max) {
+                release(g);
+                return fail(GAP_EINVAL, "n_theta = %d needs %zu bytes of LDS per workgroup, the device allows %d",
+                            geom->n_theta, need, g->lds_max);
+            }
         }
     }
-    // PCG partial sums: at most one slot per row of every condition
-    const size_t max_pcg = (size_t)max_cond * g->nz;
+    // PCG partial sums: at most one slot per row of every condition, or per strip group of
+    // the narrowest strips when a ring has more of those than rows
+    int strips1 = 1, groups1 = 1;
+    strip_layout(g->nt, 1, kStripMaxNeumann, strips1, groups1);
+    const size_t max_pcg = (size_t)max_cond * std::max(g->nz, groups1);
     g->pcg_part_stride = max_pcg;
     {
-        hipError_t pe = use_shape(g, g->shape_a, g->shape_b, 0, 0);
-        if (pe == hipSuccess) pe = use_shape_f(g, g->shape_f, 0);
+        hipError_t pe = hipSuccess;
+        if (g->rings_ok) {
+            pe = use_shape(g, g->shape_a, g->shape_b, 0, 0);
+            if (pe == hipSuccess) pe = use_shape_f(g, g->shape_f, 0);
+        }
+        if (pe == hipSuccess) pe = use_shape_w(g, kStripDefaultQ, 0);
         if (pe != hipSuccess) {
             release(g);
             return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(pe));
@@ -1003,7 +1184,7 @@ gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, ga
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
     GAP_NOT_IN_BATCH(g, "solve_joint_pcg");
     if (!p) return fail(GAP_EINVAL, "p is NULL");
-    gap_status vs = validate_opts(o);
+    gap_status vs = validate_opts(g, o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "solve_joint_pcg before assemble_joint_system");
     hipStream_t st = (hipStream_t)stream;
@@ -1058,7 +1239,7 @@ gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
     GAP_NOT_IN_BATCH(g, "jacobian_adjoint");
     if (!p0 || !J) return fail(GAP_EINVAL, "p0 and J must be non-NULL");
-    gap_status vs = validate_opts(o);
+    gap_status vs = validate_opts(g, o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "jacobian_adjoint before assemble_joint_system");
     if (cavitation != GAP_CAVITATION_NONE && cavitation != GAP_CAVITATION_CLAMP)
@@ -1086,6 +1267,7 @@ gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double
     // A lambda_i = g_i on the operator of condition 0: one recurrence per right-hand side,
     // each stopped by its own relative residual.
     gap_solver_opts oa = *o;
+    if (o->eps_adjoint > 0.0) oa.eps = o->eps_adjoint;
     oa.scalars = GAP_SCALARS_PER_COND;
     oa.strategy = GAP_STRATEGY_ASYNC;
     oa.warm_start = 0;
@@ -1125,7 +1307,7 @@ gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
     GAP_NOT_IN_BATCH(g, "solve_with_adjoint");
     if (!p0 || !J) return fail(GAP_EINVAL, "p0 and J must be non-NULL");
-    gap_status vs = validate_opts(o);
+    gap_status vs = validate_opts(g, o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "solve_with_adjoint before assemble_joint_system");
     if (w)
@@ -1162,6 +1344,7 @@ gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0
     a.S = g->adj_rhs;
     a.p = g->adj_lam;
     for (int c = 0; c < GAP_MAXC; ++c) a.op[c] = 0;
+    for (int c = 1; c < n_sys; ++c) a.eps_c[c] = o->eps_adjoint;   // 0: the base system's eps
     a.n_cond = n_sys;
     a.per_cond = 1;
     a.async = 1;
@@ -1529,6 +1712,11 @@ gap_status gap_get_pcg_config(gap_grid_t g, gap_pcg_config* cfg)
     cfg->cols_per_thread_f = g->shape_f.Q;
     cfg->wg_per_cu_f = g->wg_f;
     cfg->occupancy_f = g->occ_f;
+    cfg->cols_per_lane_w = g->shape_w.Q;
+    cfg->wg_per_cu_w = g->wg_w;
+    cfg->occupancy_w = g->occ_w;
+    int groups = 1;
+    strip_layout(g->nt, g->shape_w.Q, 1, cfg->strips_w, groups);
     return GAP_OK;
 }
 
@@ -1560,8 +1748,10 @@ gap_status tune_run(gap_grid_t g, const gap_solver_opts* t, double* p, void* str
     g->timing = false;
     g->timing_period = period;
     if (s != GAP_OK && s != GAP_ENOCONV) return s;
-    const int ka = t->iteration == GAP_ITERATION_ONE_LAUNCH ? GAP_KERNEL_PCG_ONE : GAP_KERNEL_PCG_A;
-    const int kb = t->iteration == GAP_ITERATION_ONE_LAUNCH ? -1 : GAP_KERNEL_PCG_B;
+    const int ka = t->iteration == GAP_ITERATION_STRIPS     ? GAP_KERNEL_PCG_STRIPS
+                   : t->iteration == GAP_ITERATION_ONE_LAUNCH ? GAP_KERNEL_PCG_ONE
+                                                               : GAP_KERNEL_PCG_A;
+    const int kb = t->iteration == GAP_ITERATION_TWO_LAUNCH ? GAP_KERNEL_PCG_B : -1;
     if (!g->launches[ka] || (kb >= 0 && !g->launches[kb])) return fail(GAP_EDEVICE, "the tuning run recorded no launches");
     *us_a = 1e3 * g->total_ms[ka] / (double)g->launches[ka];
     *us_b = kb >= 0 ? 1e3 * g->total_ms[kb] / (double)g->launches[kb] : 0.0;
@@ -1574,28 +1764,38 @@ gap_status gap_set_pcg_config(gap_grid_t g, const gap_pcg_config* cfg)
 {
     if (!g) return fail(GAP_EINVAL, "grid is NULL");
     GAP_NOT_IN_BATCH(g, "gap_set_pcg_config");
-    PcgShape sa = pcg_candidates(g->nt)[0], sb = sa, sf = sa;
-    int wa = 0, wb = 0, wf = 0;
+    PcgShape sa = g->rings_ok ? pcg_candidates(g->nt)[0] : PcgShape{}, sb = sa, sf = sa;
+    int wa = 0, wb = 0, wf = 0, qw = kStripDefaultQ, ww = 0;
     if (cfg) {
-        sa.NT = cfg->threads_a;
-        sa.Q = cfg->cols_per_thread_a;
-        sb.NT = cfg->threads_b;
-        sb.Q = cfg->cols_per_thread_b;
-        sf.NT = cfg->threads_f;
-        sf.Q = cfg->cols_per_thread_f;
-        gap_status cs = check_shape(g, sa);
-        if (cs == GAP_OK) cs = check_shape(g, sb);
-        if (cs == GAP_OK) cs = check_shape(g, sf);
-        if (cs != GAP_OK) return cs;
-        const int w[3] = {cfg->wg_per_cu_a, cfg->wg_per_cu_b, cfg->wg_per_cu_f};
-        for (int k = 0; k < 3; ++k)
+        if (g->rings_ok) {
+            sa.NT = cfg->threads_a;
+            sa.Q = cfg->cols_per_thread_a;
+            sb.NT = cfg->threads_b;
+            sb.Q = cfg->cols_per_thread_b;
+            sf.NT = cfg->threads_f;
+            sf.Q = cfg->cols_per_thread_f;
+            gap_status cs = check_shape(g, sa);
+            if (cs == GAP_OK) cs = check_shape(g, sb);
+            if (cs == GAP_OK) cs = check_shape(g, sf);
+            if (cs != GAP_OK) return cs;
+        }
+        if (!strip_q_known(cfg->cols_per_lane_w))
+            return fail(GAP_EINVAL, "cols_per_lane_w = %d outside [1, %d]", cfg->cols_per_lane_w, kStripMaxQ);
+        const int w[4] = {cfg->wg_per_cu_a, cfg->wg_per_cu_b, cfg->wg_per_cu_f, cfg->wg_per_cu_w};
+        for (int k = g->rings_ok ? 0 : 3; k < 4; ++k)
             if (w[k] < 1 || w[k] > 8) return fail(GAP_EINVAL, "wg_per_cu must lie in [1, 8]");
         wa = w[0];
         wb = w[1];
         wf = w[2];
+        qw = cfg->cols_per_lane_w;
+        ww = w[3];
     }
-    hipError_t e = use_shape(g, sa, sb, wa, wb);
-    if (e == hipSuccess) e = use_shape_f(g, sf, wf);
+    hipError_t e = hipSuccess;
+    if (g->rings_ok) {
+        e = use_shape(g, sa, sb, wa, wb);
+        if (e == hipSuccess) e = use_shape_f(g, sf, wf);
+    }
+    if (e == hipSuccess) e = use_shape_w(g, qw, ww);
     if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
     return GAP_OK;
 }
@@ -1606,7 +1806,7 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     if (!g || !o || !p) return fail(GAP_EINVAL, "grid, opts and p must be non-NULL");
     GAP_NOT_IN_BATCH(g, "gap_tune_pcg");
     if (iterations < 2 || iterations > 10000) return fail(GAP_EINVAL, "iterations must lie in [2, 10000]");
-    gap_status vs = validate_opts(o);
+    gap_status vs = validate_opts(g, o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "gap_tune_pcg before assemble_joint_system");
     // a fixed number of iterations, no stopping test, plain launches timed by events
@@ -1618,8 +1818,9 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     t.warm_start = 0;
     t.strategy = GAP_STRATEGY_SYNC;
     const bool timing = g->timing;
-    const PcgShape orig_a = g->shape_a, orig_b = g->shape_b, orig_f = g->shape_f;    // restored if tuning fails
-    const int orig_wa = g->wg_a, orig_wb = g->wg_b, orig_wf = g->wg_f;
+    const PcgShape orig_a = g->shape_a, orig_b = g->shape_b, orig_f = g->shape_f, orig_w = g->shape_w;
+    const int orig_wa = g->wg_a, orig_wb = g->wg_b, orig_wf = g->wg_f, orig_ww = g->wg_w;   // restored if tuning fails
+    const bool strip = o->iteration == GAP_ITERATION_STRIPS;
     const bool one = o->iteration == GAP_ITERATION_ONE_LAUNCH;
     struct Pick {
         PcgShape sh;
@@ -1627,14 +1828,23 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
         double us = 0.0;
         bool have = false;
     } pa, pb, da, db;   // best and default, per kernel
-    const PcgShape def = pcg_candidates(g->nt)[0];
+    std::vector<PcgShape> cands;
+    if (strip) {
+        for (int q = 1; q <= kStripMaxQ; ++q) cands.push_back(PcgShape{kStripThreads, q});
+    } else {
+        cands = pcg_candidates(g->nt);
+    }
+    const PcgShape def = strip ? PcgShape{kStripThreads, kStripDefaultQ} : cands[0];
     gap_status result = GAP_OK;
-    for (const PcgShape sh : pcg_candidates(g->nt)) {
+    for (const PcgShape sh : cands) {
         if (result != GAP_OK) break;
-        if (pcg_lds_bytes(one ? kPcgOne : kPcgB, sh.NT * sh.Q) + 2048 > (size_t)g->lds_max) continue;
+        if (!strip && pcg_lds_bytes(one ? kPcgOne : kPcgB, sh.NT * sh.Q) + 2048 > (size_t)g->lds_max) continue;
         int occ[3];
         bool ok = true;
-        if (one) {
+        if (strip) {
+            ok = strip_q(sh.Q, o->neumann) == sh.Q && strip_prepare(sh.Q, o->neumann, &occ[0]) == hipSuccess;
+            occ[1] = occ[2] = occ[0];
+        } else if (one) {
             for (int k = 0; k < 2 && ok; ++k) ok = pcg_prepare(sh, k ? kPcgOneInit : kPcgOne, g->nt, &occ[k]) == hipSuccess;
             occ[0] = std::min(occ[0], occ[1]);
             occ[1] = occ[2] = occ[0];
@@ -1647,7 +1857,7 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
         // one-launch kernel is timed as "A".
         for (int w = 1; w <= std::max(occ[0], ob) && result == GAP_OK; ++w) {
             const int wa = std::min(w, occ[0]), wb = std::min(w, ob);
-            const hipError_t pe = one ? use_shape_f(g, sh, wa) : use_shape(g, sh, sh, wa, wb);
+            const hipError_t pe = strip ? use_shape_w(g, sh.Q, wa) : one ? use_shape_f(g, sh, wa) : use_shape(g, sh, sh, wa, wb);
             if (pe != hipSuccess) {
                 result = fail(GAP_EDEVICE, "preparing the PCG kernels");
                 break;
@@ -1661,7 +1871,7 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
             }
             if (result != GAP_OK) break;
             if (!pa.have || ta < pa.us) pa = {sh, wa, ta, true};
-            if (!pb.have || tb < pb.us || one) pb = {sh, wb, tb, true};
+            if (!pb.have || tb < pb.us || one || strip) pb = {sh, wb, tb, true};
             const bool is_def = sh.NT == def.NT && sh.Q == def.Q;
             if (is_def && wa == occ[0]) da = {sh, wa, ta, true};
             if (is_def && wb == ob) db = {sh, wb, tb, true};
@@ -1669,20 +1879,63 @@ gap_status gap_tune_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, int32
     }
     g->timing = timing;
     if (result != GAP_OK || !pa.have || !pb.have) {
-        (void)use_shape(g, orig_a, orig_b, orig_wa, orig_wb);
-        (void)use_shape_f(g, orig_f, orig_wf);
+        if (g->rings_ok) {
+            (void)use_shape(g, orig_a, orig_b, orig_wa, orig_wb);
+            (void)use_shape_f(g, orig_f, orig_wf);
+        }
+        (void)use_shape_w(g, orig_w.Q, orig_ww);
         return result != GAP_OK ? result : fail(GAP_EDEVICE, "no kernel shape could be prepared");
     }
     // keep the default unless the best is at least 1 % faster (stable choice on near-ties)
     if (da.have && da.us <= 1.01 * pa.us) pa = da;
     if (db.have && db.us <= 1.01 * pb.us) pb = db;
     // the kernels of the other iteration kind keep their configuration
-    hipError_t e = one ? use_shape_f(g, pa.sh, pa.wg) : use_shape(g, pa.sh, pb.sh, pa.wg, pb.wg);
+    hipError_t e = strip ? use_shape_w(g, pa.sh.Q, pa.wg)
+                   : one ? use_shape_f(g, pa.sh, pa.wg) : use_shape(g, pa.sh, pb.sh, pa.wg, pb.wg);
     if (e != hipSuccess) return fail(GAP_EDEVICE, "preparing the PCG kernels: %s", hipGetErrorString(e));
     gap_pcg_config win{};
     gap_get_pcg_config(g, &win);
     if (best) *best = win;
     if (us_per_iteration) *us_per_iteration = pa.us + pb.us;
+    return GAP_OK;
+}
+
+gap_status gap_tune_neumann(gap_grid_t g, const gap_solver_opts* o, double* p, int32_t max_order, int32_t* best,
+                            double* seconds, void* stream)
+{
+    if (!g || !o || !p || !best) return fail(GAP_EINVAL, "grid, opts, p and best must be non-NULL");
+    GAP_NOT_IN_BATCH(g, "gap_tune_neumann");
+    if (max_order < 1 || max_order > kStripMaxNeumann)
+        return fail(GAP_EINVAL, "max_order must lie in [1, %d]", kStripMaxNeumann);
+    if (o->precond != GAP_PRECOND_ASSOR2 || o->iteration != GAP_ITERATION_STRIPS)
+        return fail(GAP_EINVAL, "the Neumann order is tuned for precond = GAP_PRECOND_ASSOR2, iteration = GAP_ITERATION_STRIPS");
+    if (!g->assembled) return fail(GAP_ESTATE, "gap_tune_neumann before assemble_joint_system");
+    gap_solver_opts t = *o;
+    t.warm_start = 0;
+    gap_pcg_config cfgs[kStripMaxNeumann + 1];
+    double secs[kStripMaxNeumann + 1] = {0.0};
+    int pick = 0;
+    for (int m = 1; m <= max_order; ++m) {
+        t.neumann = m;
+        gap_status vs = validate_opts(g, &t);
+        if (vs != GAP_OK) return vs;
+        // the strip kernel's configuration for this order, then one warm and one timed solve
+        gap_status ts = gap_tune_pcg(g, &t, p, 20, &cfgs[m], nullptr, stream);
+        if (ts != GAP_OK) return ts;
+        ts = solve_joint_pcg(g, &t, p, nullptr, stream);
+        if (ts != GAP_OK && ts != GAP_ENOCONV) return ts;
+        const auto t0 = std::chrono::steady_clock::now();
+        ts = solve_joint_pcg(g, &t, p, nullptr, stream);       // synchronizes the stream
+        const auto t1 = std::chrono::steady_clock::now();
+        if (ts != GAP_OK) return ts;
+        secs[m] = std::chrono::duration<double>(t1 - t0).count();
+        if (!pick || secs[m] < secs[pick]) pick = m;
+    }
+    gap_status cs = gap_set_pcg_config(g, &cfgs[pick]);
+    if (cs != GAP_OK) return cs;
+    *best = pick;
+    if (seconds)
+        for (int m = 1; m <= max_order; ++m) seconds[m - 1] = secs[m];
     return GAP_OK;
 }
 
@@ -1732,11 +1985,16 @@ struct gap_batch_s {
     size_t init_cap = 0;
     int occ_a = 1, occ_b = 1, occ_f = 1, cus = 256;
     PcgShape shape = pcg_candidates(2048)[0];            // the shape of the largest ring
+    PcgShape shape_w{kStripThreads, kStripDefaultQ};         // the strip kernel's shape
+    int occ_w = 1;
     int mode = GAP_ITERATION_ONE_LAUNCH;                     // iteration kind of the requests (set by the first)
+    int neumann = 1;                                         // their Neumann order (set by the first)
+    int wg_target = 0;                                       // strip chunking target (workgroups per CU), 0: occupancy
     long launches = 0;                                       // one-launch kernel launches so far
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
-    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0, exec_par0 = 0;
+    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0, exec_par0 = 0, exec_pk = -1;
+    int pk = -1;                                             // preconditioner common to the scheduled requests, or -1
     const int* exec_work = nullptr;
     int next_id = 1;
 };
@@ -1789,7 +2047,9 @@ gap_status gap_grid_bytes(const gap_geom* geom, int32_t max_cond, int64_t* bytes
     d += max_op * n + max_op * (n + nt);                     // face conductances
     d += 7 * (int64_t)max_cond * n;                          // S, r (2), u (2), z (2)
     d += 10 * (int64_t)std::max(cm1.total, cm9.total);       // force partials
-    d += 15 * (int64_t)max_cond * nz;                        // PCG partials
+    int strips1 = 1, groups1 = 1;
+    strip_layout((int)nt, 1, kStripMaxNeumann, strips1, groups1);
+    d += 15 * (int64_t)max_cond * std::max<int64_t>(nz, groups1);   // PCG partials
     d += (int64_t)max_cond * n;                              // the caller's pressure field
     *bytes = d * (int64_t)sizeof(double) + 4096;
     return GAP_OK;
@@ -1826,6 +2086,11 @@ gap_status gap_batch_create(gap_batch_t* out)
         batch_release(b);
         return fail(GAP_EDEVICE, "creating the batch: %s", hipGetErrorString(e));
     }
+    if (e == hipSuccess) e = strip_prepare(b->shape_w.Q, 1, &b->occ_w);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return fail(GAP_EDEVICE, "creating the batch: %s", hipGetErrorString(e));
+    }
     b->occ_b = std::min(occ_b, occ_i);
     b->occ_f = std::min(occ_f, occ_fi);
     *out = b;
@@ -1844,14 +2109,18 @@ gap_status gap_batch_destroy(gap_batch_t b)
 gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, double* p, int32_t* id, void* stream)
 {
     if (!b || !g || !p || !id) return fail(GAP_EINVAL, "batch, grid, p and id must be non-NULL");
-    gap_status vs = validate_opts(o);
+    gap_status vs = validate_opts(g, o);
     if (vs != GAP_OK) return vs;
     if (!g->assembled) return fail(GAP_ESTATE, "gap_batch_add needs an assembled grid");
     if (g->batch) return fail(GAP_EINVAL, "this grid is already in a batch");
+    if (!b->reqs.empty() && o->iteration == b->mode && o->neumann != b->neumann)
+        return fail(GAP_EINVAL, "the requests of a batch share one Neumann order (the batch runs order %d)", b->neumann);
     if (!b->reqs.empty() && o->iteration != b->mode)
         return fail(GAP_EINVAL, "the requests of a batch share one iteration kind (the batch runs %s launches)",
-                    b->mode == GAP_ITERATION_ONE_LAUNCH ? "one-launch" : "two-launch");
-    const bool one = o->iteration == GAP_ITERATION_ONE_LAUNCH;
+                    b->mode == GAP_ITERATION_STRIPS ? "strip" : b->mode == GAP_ITERATION_ONE_LAUNCH ? "one-launch"
+                                                                                                 : "two-launch");
+    const bool strip = o->iteration == GAP_ITERATION_STRIPS;
+    const bool one = o->iteration != GAP_ITERATION_TWO_LAUNCH;
     int slot = -1;
     std::vector<bool> used(gap_batch_s::kCap, false);
     for (const auto& r : b->reqs) used[r.slot] = true;
@@ -1876,7 +2145,15 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     fill_pcg(g, a, o);
     // chunking depends only on the request and the batch kernel shape, so a request gets
     // the same reduction order (bitwise the same result) alone and in any mix
-    if (one) {
+    a.n_strips = a.strip_groups = 1;
+    if (strip) {
+        int occ = 1;
+        const int Qb = strip_q(b->shape_w.Q, o->neumann);
+        const hipError_t oe = strip_prepare(Qb, o->neumann, &occ);
+        if (oe != hipSuccess) return fail(GAP_EDEVICE, "preparing the strip kernel: %s", hipGetErrorString(oe));
+        const int wg = b->wg_target > 0 ? std::min(b->wg_target, occ) : occ;
+        strip_chunks(g->nz, g->nt, a.n_cond, Qb, o->neumann, wg * b->cus, a);
+    } else if (one) {
         pcg_chunks(g->nz, g->nt, a.n_cond, b->occ_f * b->cus, a.chunks_b, a.rows_b);
         a.chunks_a = a.chunks_b;
         a.rows_a = a.rows_b;
@@ -1890,13 +2167,16 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     HIPCHK(hipMemcpyAsync(b->reqs_dev + slot, b->reqs_host + slot, sizeof(PcgDev), hipMemcpyHostToDevice, st));
 
     std::vector<std::vector<int>> gb;
-    pcg_groups(slot, a.chunks_b, a.n_cond, a.op, gb);
+    pcg_groups(slot, a.chunks_b, a.n_cond, a.op, gb, strip ? a.strip_groups : 1);
     const std::vector<int> tb = pcg_schedule(gb);
     gap_status es = ensure_ints(&b->init_work, &b->init_cap, tb.size());
     if (es != GAP_OK) return es;
     HIPCHK(hipMemcpyAsync(b->init_work, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    hipError_t le = launch_pcg(b->shape, one ? kPcgOneInit : kPcgInit, kBatchShape, b->reqs_dev, b->init_work,
-                               (int)tb.size(), st);
+    PcgShape sh_init = strip ? b->shape_w : b->shape;
+    sh_init.M = o->neumann;
+    if (strip) sh_init.Q = strip_q(sh_init.Q, sh_init.M);
+    hipError_t le = launch_pcg(sh_init, strip ? kPcgStripInit : (one ? kPcgOneInit : kPcgInit), kBatchShape,
+                               b->reqs_dev, b->init_work, (int)tb.size(), st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
     HIPCHK(hipStreamSynchronize(st));
 
@@ -1905,6 +2185,7 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     r.slot = slot;
     r.g = g;
     b->mode = o->iteration;
+    b->neumann = o->neumann;
     g->batch = b;
     b->reqs.push_back(r);
     b->dirty = true;
@@ -1917,15 +2198,19 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
     if (!b) return fail(GAP_EINVAL, "batch is NULL");
     if (iterations < 1) return fail(GAP_EINVAL, "iterations must be >= 1");
     hipStream_t st = (hipStream_t)stream;
-    const bool one = b->mode == GAP_ITERATION_ONE_LAUNCH;
+    const bool strip = b->mode == GAP_ITERATION_STRIPS;
+    const bool one = b->mode != GAP_ITERATION_TWO_LAUNCH;
+    const int one_which = strip ? kPcgStrip : (one ? kPcgOne : 0);
     if (b->dirty) {
         std::vector<std::vector<int>> ga, gb;
+        b->pk = -2;                                  // the preconditioner common to the scheduled requests
         for (auto& r : b->reqs) {
             r.scheduled = !(r.done || r.held);
             if (!r.scheduled) continue;
             PcgDev& a = b->reqs_host[r.slot];
+            b->pk = (b->pk == -2 || b->pk == a.precond) ? a.precond : -1;
             if (!one) pcg_groups(r.slot, a.chunks_a, a.n_cond, a.op, ga);
-            pcg_groups(r.slot, a.chunks_b, a.n_cond, a.op, gb);
+            pcg_groups(r.slot, a.chunks_b, a.n_cond, a.op, gb, strip ? a.strip_groups : 1);
             if (one) {
                 // the request's next iteration has the parity of its own launch count
                 const int off = (int)((r.f_count ^ b->launches) & 1);
@@ -1947,18 +2232,25 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
         b->blocks_b = (int)tb.size();
         b->dirty = false;
     }
+    PcgShape sh_one = strip ? b->shape_w : b->shape;
+    if (strip) {
+        sh_one.pk = b->pk >= 0 ? b->pk : -1;
+        sh_one.M = b->neumann;
+        sh_one.Q = strip_q(sh_one.Q, sh_one.M);
+    }
     if ((one ? b->blocks_b : b->blocks_a) > 0) {
         const int* wa = b->work;
         const int* wb = b->work + b->blocks_a;
         const int par0 = one ? (int)(b->launches & 1) : 0;
         if (use_graph) {
             if (!b->exec || b->exec_iters != iterations || b->exec_blocks_a != b->blocks_a ||
-                b->exec_blocks_b != b->blocks_b || b->exec_work != b->work || b->exec_par0 != par0) {
+                b->exec_blocks_b != b->blocks_b || b->exec_work != b->work || b->exec_par0 != par0 ||
+                b->exec_pk != sh_one.pk) {
                 if (b->exec) (void)hipGraphExecDestroy(b->exec);
                 b->exec = nullptr;
                 if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, b->shape, kBatchShape, b->reqs_dev, wa,
-                                              b->blocks_a, wb, b->blocks_b, &b->exec, one, par0);
+                hipError_t ce = capture_block(b->cap_stream, iterations, b->shape, sh_one, kBatchShape, b->reqs_dev, wa,
+                                              b->blocks_a, wb, b->blocks_b, &b->exec, one_which, par0);
                 if (ce != hipSuccess) {
                     b->exec = nullptr;
                     return fail(GAP_EDEVICE, "capturing the batch block: %s", hipGetErrorString(ce));
@@ -1968,13 +2260,14 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
                 b->exec_blocks_b = b->blocks_b;
                 b->exec_work = b->work;
                 b->exec_par0 = par0;
+                b->exec_pk = sh_one.pk;
             }
             HIPCHK(hipGraphLaunch(b->exec, st));
         } else {
             for (int it = 0; it < iterations; ++it) {
                 hipError_t le;
                 if (one) {
-                    le = launch_pcg(b->shape, kPcgOne, kBatchShape, b->reqs_dev, wb, b->blocks_b, st, (par0 + it) & 1);
+                    le = launch_pcg(sh_one, one_which, kBatchShape, b->reqs_dev, wb, b->blocks_b, st, (par0 + it) & 1);
                 } else {
                     le = launch_pcg(b->shape, kPcgA, kBatchShape, b->reqs_dev, wa, b->blocks_a, st);
                     if (le == hipSuccess) le = launch_pcg(b->shape, kPcgB, kBatchShape, b->reqs_dev, wb, b->blocks_b, st);
@@ -2002,6 +2295,14 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
         done += r.done ? 1 : 0;
     }
     if (n_done) *n_done = done;
+    return GAP_OK;
+}
+
+gap_status gap_batch_set_target(gap_batch_t b, int32_t wg_per_cu)
+{
+    if (!b) return fail(GAP_EINVAL, "batch is NULL");
+    if (wg_per_cu < 0 || wg_per_cu > 8) return fail(GAP_EINVAL, "wg_per_cu must lie in [0, 8]");
+    b->wg_target = wg_per_cu;
     return GAP_OK;
 }
 

@@ -32,10 +32,10 @@ GAP_SCALARS_GLOBAL, GAP_SCALARS_PER_COND = 0, 1
 GAP_STRATEGY_SYNC, GAP_STRATEGY_ASYNC = 0, 1
 GAP_CAVITATION_NONE, GAP_CAVITATION_CLAMP = 0, 1
 GAP_MAX_COND = 9
-GAP_ITERATION_TWO_LAUNCH, GAP_ITERATION_ONE_LAUNCH = 0, 1
-GAP_KERNEL_PCG_A, GAP_KERNEL_PCG_B, GAP_KERNEL_PCG_ONE = 0, 1, 2
-GAP_KERNEL_COUNT = 3
-KERNEL_NAMES = ["k_pcg_a", "k_pcg_b", "k_pcg_f"]
+GAP_ITERATION_TWO_LAUNCH, GAP_ITERATION_ONE_LAUNCH, GAP_ITERATION_STRIPS = 0, 1, 2
+GAP_KERNEL_PCG_A, GAP_KERNEL_PCG_B, GAP_KERNEL_PCG_ONE, GAP_KERNEL_PCG_STRIPS = 0, 1, 2, 3
+GAP_KERNEL_COUNT = 4
+KERNEL_NAMES = ["k_pcg_a", "k_pcg_b", "k_pcg_f", "k_pcg_w"]
 
 
 class gap_geom(ctypes.Structure):
@@ -55,7 +55,8 @@ class gap_solver_opts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("neumann", ctypes.c_int32), ("scalars", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("strategy", ctypes.c_int32), ("iteration", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("strategy", ctypes.c_int32), ("iteration", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eps_adjoint", ctypes.c_double)]
 
 
 class gap_solve_info(ctypes.Structure):
@@ -72,7 +73,9 @@ class gap_pcg_config(ctypes.Structure):
                 ("threads_b", ctypes.c_int32), ("cols_per_thread_b", ctypes.c_int32),
                 ("wg_per_cu_b", ctypes.c_int32), ("occupancy_b", ctypes.c_int32),
                 ("threads_f", ctypes.c_int32), ("cols_per_thread_f", ctypes.c_int32),
-                ("wg_per_cu_f", ctypes.c_int32), ("occupancy_f", ctypes.c_int32)]
+                ("wg_per_cu_f", ctypes.c_int32), ("occupancy_f", ctypes.c_int32),
+                ("cols_per_lane_w", ctypes.c_int32), ("wg_per_cu_w", ctypes.c_int32),
+                ("occupancy_w", ctypes.c_int32), ("strips_w", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -130,6 +133,7 @@ _SIGNATURES = {
     "gap_batch_step": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
     "gap_batch_poll": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "gap_batch_hold": [_P, ctypes.c_int32, ctypes.c_int32],
+    "gap_batch_set_target": [_P, ctypes.c_int32],
     "gap_batch_remove": [_P, ctypes.c_int32, ctypes.POINTER(gap_solve_info), _P],
     "gap_kernel_timing": [_P, ctypes.c_int32],
     "gap_get_pcg_config": [_P, ctypes.POINTER(gap_pcg_config)],
@@ -137,6 +141,8 @@ _SIGNATURES = {
     "gap_tune_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.POINTER(gap_pcg_config),
                      ctypes.POINTER(ctypes.c_double), _P],
     "gap_kernel_stats": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "gap_tune_neumann": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                         _D8, _P],
     "gap_pcg_history": [_P, ctypes.c_int32],
     "gap_get_pcg_history": [_P, _D8, _D8, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
 }
@@ -391,6 +397,10 @@ def gap_batch_step(batch, iterations, use_graph=True, stream=None):
     return nd.value
 
 
+def gap_batch_set_target(batch, wg_per_cu):
+    _check(load().gap_batch_set_target(batch, int(wg_per_cu)))
+
+
 def gap_batch_hold(batch, bid, hold):
     _check(load().gap_batch_hold(batch, int(bid), int(bool(hold))))
 
@@ -409,3 +419,12 @@ def gap_batch_remove(batch, rid, stream=None, raise_on_error=True):
     if raise_on_error:
         _check(st, info)
     return st, info
+
+
+def gap_tune_neumann(handle, opts, p_ptr, max_order=3, stream=None):
+    """Returns (best Neumann order, [seconds per solve of orders 1 .. max_order])."""
+    best = ctypes.c_int32()
+    secs = (ctypes.c_double * int(max_order))()
+    _check(load().gap_tune_neumann(handle, ctypes.byref(opts), ctypes.c_void_p(int(p_ptr)), int(max_order),
+                                   ctypes.byref(best), secs, _stream(stream)))
+    return best.value, list(secs)

@@ -1,10 +1,10 @@
 """Profiling driver: short joint solves on the 2048 x 1024 textured workload, with the
-two-launch iteration (Table 1 as printed: k_pcg_a, k_pcg_b) and the one-launch iteration
-(k_pcg_f), plus a plain device copy of known size, for hardware-counter runs (rocprofv3
---pmc / --kernel-trace).
+two-launch iteration (Table 1 as printed: k_pcg_a, k_pcg_b), the whole-ring one-launch
+iteration (k_pcg_f) and the strip iteration (k_pcg_w), plus a plain device copy of known
+size, for hardware-counter runs (rocprofv3 --pmc / --kernel-trace).
 
     python3 paper_2511_06824_amd/profile_pcg.py [--iterations N] [--copy-mib M] [--no-tune]
-                                                [--iteration one|two|both]
+                                                [--iteration strips|one|two|all]
     python3 paper_2511_06824_amd/profile_pcg.py --summarize FETCH_CSV WRITE_CSV
 
 The copy (a device-to-device copy, M MiB read and M MiB written) calibrates what the
@@ -12,7 +12,7 @@ FETCH_SIZE / WRITE_SIZE counters read per byte actually moved.  --summarize read
 counter-collection CSVs of such runs (no GPU needed) and prints the calibrated bytes per
 launch of each iteration kernel in the steady state: a solve's first launch (j = 0, no
 u_prev yet) and its closing launch (which only reads the partials and stops) are left out,
-and the one-launch kernel is averaged over odd and even iterations separately, since p
+and the one-launch kernels are averaged over odd and even iterations separately, since p
 moves on odd iterations only.
 """
 
@@ -56,7 +56,7 @@ def summarize(fetch_csv, write_csv, copy_mib=1024):
         if not f or len(f) != len(w):
             continue
         short = name.split("(")[0].replace("void ", "").replace(" ", "")
-        if short.startswith("k_pcg_f"):
+        if short.startswith("k_pcg_f") or short.startswith("k_pcg_w"):
             groups = [("odd j", f[0::2], w[0::2]), ("even j", f[1::2], w[1::2])]
             tot = []
             for label, ff, ww in groups:
@@ -80,7 +80,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="joint_textured_2048x1024")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--iteration", choices=["one", "two", "both"], default="both")
+    ap.add_argument("--iteration", choices=["strips", "one", "two", "all"], default="all")
+    ap.add_argument("--strip-config", default=None,
+                    help="Q,W: the strip kernel's columns per lane and workgroups per CU (instead of tuning it)")
     args = ap.parse_args()
 
     import torch
@@ -101,9 +103,16 @@ def main():
     s = JointGapSolver.from_case(case, max_cond=9, device=dev)
     s.assemble(case.e, case.edot, case.delta, 9)
     kinds = {"two": [G.GAP_ITERATION_TWO_LAUNCH], "one": [G.GAP_ITERATION_ONE_LAUNCH],
-             "both": [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH]}[args.iteration]
+             "strips": [G.GAP_ITERATION_STRIPS],
+             "all": [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                     G.GAP_ITERATION_STRIPS]}[args.iteration]
+    if args.strip_config:
+        q, w = (int(x) for x in args.strip_config.split(","))
+        print(f"profile: strip configuration {s.set_strip_config(q, w)}", flush=True)
     for it in kinds:
-        if not args.no_tune:
+        if it == G.GAP_ITERATION_STRIPS and args.strip_config:
+            pass
+        elif not args.no_tune:
             cfg, _ = s.tune(iterations=20, omega=case.omega, iteration=it)   # the configuration the benchmark times
             print(f"profile: iteration kind {it}, PCG kernel configuration {cfg}", flush=True)
         _, info = s.solve(omega=case.omega, eps=1e-30, max_iter=args.iterations, check_every=args.iterations,

@@ -17,11 +17,19 @@ one always advances) and holds the rest on the device (``gap_batch_hold``):
   * "oldest": arrival order; large requests run one after another and small ones fill what
     the cap leaves beside them.
 
-The admission and scheduling logic (``AdmissionController``, ``GapServer``) is independent
-of the device: ``BatchBackend`` drives the HIP library, tests may substitute a fake backend
-with its own clock.
+Two lanes (``LaneServer``): bulk requests, those whose own launches fill the GPU, run in a
+batch of their own, one after another in arrival order; the others share the steps of a
+second batch.  Each lane has its own stream and host thread, so the small requests iterate at
+the pace of their own short launches, concurrently with the bulk launches (which are chunked
+to leave room on every CU for them, ``gap_batch_set_target``), and never wait for a bulk
+request to finish.  Both lanes draw on one HBM budget.
+
+The admission and scheduling logic (``AdmissionController``, ``GapServer``, ``LaneServer``)
+is independent of the device: ``BatchBackend`` drives the HIP library, tests may substitute
+a fake backend with its own clock.
 """
 
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import Any, List, Optional
@@ -30,28 +38,35 @@ import numpy as np
 
 
 class AdmissionController:
-    """Admits requests while their summed device footprint stays within a byte budget."""
+    """Admits requests while their summed device footprint stays within a byte budget (safe
+    to share between the lanes' threads)."""
 
     def __init__(self, budget_bytes, max_active=128):
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.used = 0
         self.active = 0
+        self.peak = 0
+        self._lock = threading.Lock()
 
     def fits(self, nbytes):
-        return self.active < self.max_active and self.used + nbytes <= self.budget
+        with self._lock:
+            return self.active < self.max_active and self.used + nbytes <= self.budget
 
     def admit(self, nbytes):
-        if not self.fits(nbytes):
-            return False
-        self.used += nbytes
-        self.active += 1
-        return True
+        with self._lock:
+            if not (self.active < self.max_active and self.used + nbytes <= self.budget):
+                return False
+            self.used += nbytes
+            self.active += 1
+            self.peak = max(self.peak, self.used)
+            return True
 
     def release(self, nbytes):
-        self.used -= nbytes
-        self.active -= 1
-        assert self.used >= 0 and self.active >= 0
+        with self._lock:
+            self.used -= nbytes
+            self.active -= 1
+            assert self.used >= 0 and self.active >= 0
 
 
 @dataclass
@@ -92,18 +107,25 @@ class WallClock:
 
 
 class BatchBackend:
-    """Drives the HIP library: one JointGapSolver handle per request, one gap_batch."""
+    """Drives the HIP library: one JointGapSolver handle per request, one gap_batch.
 
-    def __init__(self, device="cuda:0", iterations_per_step=32, use_graph=True, keep_pressure=False):
+    ``stream``: the stream every call of this backend runs on (default: the current stream of
+    the thread that creates it); ``wg_per_cu``: the strip kernel's chunking target for the
+    requests of this batch (0: the kernel's occupancy)."""
+
+    def __init__(self, device="cuda:0", iterations_per_step=32, use_graph=True, keep_pressure=False,
+                 stream=None, wg_per_cu=0):
         import torch
         from . import gapsolve as G
         from .solver import JointGapSolver
         self.torch, self.G, self.Solver = torch, G, JointGapSolver
         self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.iters = int(iterations_per_step)
         self.use_graph = use_graph
         self.keep_pressure = keep_pressure
         self.batch = G.gap_batch_create()
+        G.gap_batch_set_target(self.batch, wg_per_cu)
         self.live = {}
 
     def footprint(self, case):
@@ -128,28 +150,29 @@ class BatchBackend:
 
     def start(self, req):
         case = req.case
-        s = self.Solver.from_case(case, max_cond=9, device=self.device)
-        s.assemble(case.e, case.edot, case.delta, 9)
-        opts = s.options(omega=case.omega, eps=case.eps)
-        stream = self.torch.cuda.current_stream(self.device).cuda_stream
-        bid = self.G.gap_batch_add(self.batch, s.handle, opts, s.p.data_ptr(), stream)
+        with self.torch.cuda.stream(self.stream):
+            s = self.Solver.from_case(case, max_cond=9, device=self.device)
+            s.assemble(case.e, case.edot, case.delta, 9)
+            opts = s.options(omega=case.omega, eps=case.eps)
+            bid = self.G.gap_batch_add(self.batch, s.handle, opts, s.p.data_ptr(), self.stream.cuda_stream)
         self.live[bid] = (s, req, opts)
 
     def step(self):
         """Advance every active request; return the requests finished in this step."""
-        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        stream = self.stream.cuda_stream
         self.G.gap_batch_step(self.batch, self.iters, self.use_graph, stream)
         out = []
-        for bid in self.G.gap_batch_poll(self.batch):
-            s, req, _ = self.live.pop(bid)
-            st, info = self.G.gap_batch_remove(self.batch, bid, stream, raise_on_error=False)
-            req.status, req.iterations = st, info.iterations
-            req.F = s.integrate().cpu().numpy().copy()
-            req.J = s.jacobian_fd().cpu().numpy().copy()
-            if self.keep_pressure:
-                req.p = s.pressure().cpu().numpy().copy()
-            s.close()
-            out.append(req)
+        with self.torch.cuda.stream(self.stream):
+            for bid in self.G.gap_batch_poll(self.batch):
+                s, req, _ = self.live.pop(bid)
+                st, info = self.G.gap_batch_remove(self.batch, bid, stream, raise_on_error=False)
+                req.status, req.iterations = st, info.iterations
+                req.F = s.integrate().cpu().numpy().copy()
+                req.J = s.jacobian_fd().cpu().numpy().copy()
+                if self.keep_pressure:
+                    req.p = s.pressure().cpu().numpy().copy()
+                s.close()
+                out.append(req)
         return out
 
     def idle(self):
@@ -166,11 +189,13 @@ class BatchBackend:
 class GapServer:
     """Event loop: admit by arrival order and budget, step the batch, retire finished work."""
 
-    def __init__(self, backend, budget_bytes, clock=None, work_cap=None, order="smallest"):
+    def __init__(self, backend, budget_bytes, clock=None, work_cap=None, order="smallest", admission=None,
+                 poll_s=5e-4):
         if order not in ("smallest", "oldest"):
             raise ValueError(f"unknown order {order!r}")
         self.backend = backend
-        self.admission = AdmissionController(budget_bytes)
+        self.admission = admission if admission is not None else AdmissionController(budget_bytes)
+        self.poll_s = poll_s                   # wait while another lane holds the memory a request needs
         self.clock = clock or WallClock()
         self.work_cap = work_cap
         self.order = order
@@ -208,7 +233,9 @@ class GapServer:
                 r.admitted = self.clock.now()
                 self.backend.start(r)
             if self.backend.idle():
-                if pending:
+                if queue:                      # only with a shared budget: another lane holds it
+                    self.clock.sleep_until(self.clock.now() + self.poll_s)
+                elif pending:
                     self.clock.sleep_until(pending[0].arrival)
                 continue
             if self.work_cap is not None:
@@ -218,6 +245,49 @@ class GapServer:
                 self.admission.release(r.nbytes)
                 done.append(r)
         return done
+
+
+class LaneServer:
+    """Two lanes over one HBM budget and one clock, each a GapServer with its own backend
+    (batch, stream) driven by its own thread.  Requests of work >= ``bulk_work`` (condition-
+    DOFs per iteration) go to the bulk lane, which runs them in arrival order, advancing
+    together only those that fit ``bulk_cap`` (default: bulk_work); the others go to the fast
+    lane, where every admitted request advances in every step."""
+
+    def __init__(self, bulk, fast, budget_bytes, bulk_work, clock=None, bulk_cap=None):
+        self.admission = AdmissionController(budget_bytes)
+        self.clock = clock or WallClock()
+        self.bulk_work = int(bulk_work)
+        self.lanes = {
+            "bulk": GapServer(bulk, budget_bytes, clock=self.clock, work_cap=bulk_cap or self.bulk_work,
+                              order="oldest", admission=self.admission),
+            "fast": GapServer(fast, budget_bytes, clock=self.clock, admission=self.admission),
+        }
+
+    def lane_of(self, req):
+        return "bulk" if self.lanes["bulk"].backend.work(req.case) >= self.bulk_work else "fast"
+
+    def run(self, requests: List[Request]):
+        parts = {"bulk": [], "fast": []}
+        for r in requests:
+            r.meta["lane"] = self.lane_of(r)
+            parts[r.meta["lane"]].append(r)
+        done, errors = {}, []
+
+        def drive(name):
+            try:
+                done[name] = self.lanes[name].run(parts[name])
+            except BaseException as exc:           # re-raised in the caller's thread
+                errors.append(exc)
+
+        threads = [threading.Thread(target=drive, args=(name,), name=f"lane-{name}") for name in parts if parts[name]]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+        return sorted((r for lane in done.values() for r in lane), key=lambda r: r.finished)
 
 
 def latency_stats(done):

@@ -86,9 +86,10 @@ class JointGapSolver:
     @staticmethod
     def options(omega=1.6, eps=1e-10, max_iter=100000, precond=G.GAP_PRECOND_ASSOR2, scalars=G.GAP_SCALARS_GLOBAL,
                 warm_start=False, check_every=0, neumann=1, graph=True, strategy=G.GAP_STRATEGY_SYNC,
-                iteration=G.GAP_ITERATION_ONE_LAUNCH):
+                iteration=G.GAP_ITERATION_STRIPS, eps_adjoint=0.0):
         o = G.gap_default_opts()
         o.omega, o.eps, o.max_iter = float(omega), float(eps), int(max_iter)
+        o.eps_adjoint = float(eps_adjoint)
         o.precond, o.scalars, o.neumann = int(precond), int(scalars), int(neumann)
         o.warm_start, o.check_every, o.graph = int(bool(warm_start)), int(check_every), int(bool(graph))
         o.strategy, o.iteration = int(strategy), int(iteration)
@@ -123,6 +124,14 @@ class JointGapSolver:
         cfg, us = G.gap_tune_pcg(self.handle, opts, self.p.data_ptr(), iterations, _stream(self.device))
         return cfg.as_dict(), us
 
+    def tune_neumann(self, opts=None, max_order=3, **kw):
+        """Pick the ASSOR II Neumann order by time to solution (each order with its own tuned
+        strip configuration, which stays on the handle for the winner).  Overwrites the pressure
+        field.  Returns (order, [seconds per solve of orders 1 .. max_order]); pass the order as
+        `neumann` to the solves that follow."""
+        opts = opts or self.options(**kw)
+        return G.gap_tune_neumann(self.handle, opts, self.p.data_ptr(), max_order, _stream(self.device))
+
     @property
     def pcg_config(self):
         return G.gap_get_pcg_config(self.handle).as_dict()
@@ -148,6 +157,15 @@ class JointGapSolver:
         cfg.wg_per_cu_b = cur.wg_per_cu_b if wg_per_cu_b is None else int(wg_per_cu_b)
         cfg.wg_per_cu_f = (cfg.wg_per_cu_b if wg_per_cu_b is not None else cur.wg_per_cu_f) \
             if wg_per_cu_f is None else int(wg_per_cu_f)
+        cfg.cols_per_lane_w, cfg.wg_per_cu_w = cur.cols_per_lane_w, cur.wg_per_cu_w
+        G.gap_set_pcg_config(self.handle, cfg)
+        return self.pcg_config
+
+    def set_strip_config(self, cols_per_lane, wg_per_cu):
+        """Select the strip kernel's columns per lane and row-chunking target; the other
+        kernels keep their configuration."""
+        cfg = G.gap_get_pcg_config(self.handle)
+        cfg.cols_per_lane_w, cfg.wg_per_cu_w = int(cols_per_lane), int(wg_per_cu)
         G.gap_set_pcg_config(self.handle, cfg)
         return self.pcg_config
 

@@ -52,7 +52,7 @@ def good_geom(**over):
 
 
 @pytest.mark.parametrize("over,msg", [
-    (dict(n_theta=2), "n_theta"), (dict(n_theta=2049), "n_theta"), (dict(n_axial=1), "n_axial"),
+    (dict(n_theta=2), "n_theta"), (dict(n_theta=16385), "n_theta"), (dict(n_axial=1), "n_axial"),
     (dict(R=-1.0), "R"), (dict(clearance=0.0), "clearance"), (dict(mu=float("nan")), "mu"),
     (dict(length=float("inf")), "length"), (dict(p_in=float("nan")), "finite")])
 def test_create_rejects_bad_geometry(over, msg):
@@ -122,3 +122,29 @@ def test_new_entry_points_reject_null_handles(lib):
     assert lib.general_iteration_step(None, ctypes.byref(opts), ctypes.byref(prm), None, P(8), e, e, F, None, None,
                                       None) == G.GAP_EINVAL
     assert "non-NULL" in G.gap_last_error() or "NULL" in G.gap_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the header's size and field offsets (a C program built
+    with gcc against include/gapsolve.h prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = [G.gap_geom, G.gap_dimples, G.gap_solver_opts, G.gap_solve_info, G.gap_pcg_config, G.gap_step_params]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gapsolve.h"', "int main(void) {"]
+    for st in structs:
+        lines.append(f'printf("{st.__name__} size %zu\\n", sizeof({st.__name__}));')
+        for name, _ in st._fields_:
+            lines.append(f'printf("{st.__name__} {name} %zu\\n", offsetof({st.__name__}, {name}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                                text=True).stdout.splitlines())
+    for st in structs:
+        assert int(got[f"{st.__name__} size"]) == ctypes.sizeof(st), st.__name__
+        for name, _ in st._fields_:
+            assert int(got[f"{st.__name__} {name}"]) == getattr(st, name).offset, (st.__name__, name)

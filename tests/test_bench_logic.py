@@ -27,6 +27,9 @@ def test_kernel_bytes_of_the_headline_workload():
     # the one-launch average is the mean of an odd (8 operands) and an even (6) launch
     odd, even = (8 * 8 * 9 + 80) * n, (6 * 8 * 9 + 80) * n
     assert b["k_pcg_f"] == (odd + even) // 2
+    # the strip kernel: r, u_prev read, u, r written (4 operands), p on odd launches (+2)
+    assert b["k_pcg_w"] == (5 * 8 * 9 + 16 * 5) * n == 922746880
+    assert b["k_pcg_w"] == ((6 * 8 * 9 + 80) * n + (4 * 8 * 9 + 80) * n) // 2
 
 
 def test_recorded_traffic_needs_the_current_kernel_sources(tmp_path, monkeypatch):

@@ -188,8 +188,9 @@ def test_adjoint_clamp_mode_is_finite_and_close_to_fd():
     assert block_err(J, Jc) < 5e-2
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                          G.GAP_ITERATION_STRIPS],
+                         ids=["two_launch", "one_launch", "strips"])
 @pytest.mark.parametrize("scalars,strategy", [("per_cond", "sync"), ("per_cond", "async"), ("global", "async")])
 def test_scalar_and_strategy_variants_follow_oracle(scalars, strategy, iteration):
     case = synth.textured_case(96, 48, 3)

@@ -37,8 +37,9 @@ def oracle_spectrum(case, n_cond, omega):
     return lo, hi
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                          G.GAP_ITERATION_STRIPS],
+                         ids=["two_launch", "one_launch", "strips"])
 @pytest.mark.parametrize("n_cond", [1, 9])
 def test_lanczos_extremes_match_the_oracle_spectrum(n_cond, iteration):
     case = synth.textured_case(24, 16, 4)

@@ -41,8 +41,9 @@ def test_linear_axial_profile_closed_form(ecc, U):
     assert err <= 1e-9
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                          G.GAP_ITERATION_STRIPS],
+                         ids=["two_launch", "one_launch", "strips"])
 def test_largest_axial_size_follows_the_oracle_recurrence(iteration):
     """n_axial = 65536 (the largest accepted) on a 16-cell ring, one condition: 100 iterations of
     the GPU recurrence against 100 iterations of the oracle's Table 1 PCG with ASSOR II."""
@@ -69,8 +70,9 @@ def test_largest_axial_size_follows_the_oracle_recurrence(iteration):
     np.testing.assert_allclose(Sg.ravel(), S, rtol=1e-11, atol=1e-11 * np.max(np.abs(S)))
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                          G.GAP_ITERATION_STRIPS],
+                         ids=["two_launch", "one_launch", "strips"])
 @pytest.mark.parametrize("scalars,strategy,eps,max_iter", [
     ("global", "sync", 1e-300, 7), ("global", "sync", 1e-300, 8),
     ("per_cond", "async", 3e-3, 1000), ("global", "async", 3e-3, 1000)],
@@ -111,6 +113,55 @@ def test_pressure_is_whole_after_a_stop_at_either_parity(scalars, strategy, eps,
     assert max(errs) <= 1e-8, errs
 
 
+def test_ring_wider_than_2048_cells_needs_strips_and_matches_the_exact_solution():
+    """n_theta = 2304: more columns than a whole-ring workgroup holds.  The strip iteration cuts
+    each ring into 20 strips; against the oracle's banded-Cholesky solution at eps 1e-13 the
+    pressure meets 1e-9 and the forces 1e-8 per pair; the whole-ring kinds refuse the grid."""
+    case = synth.textured_case(2304, 6, 7)
+    log(f"case: {case.label}, 9 conditions, strips on a ring of 2304 cells")
+    gap, tex = gap_of(case), texture_of(case)
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    for it in (G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH):
+        with pytest.raises(G.GapError) as ei:
+            s.solve(omega=1.6, eps=1e-10, iteration=it)
+        assert ei.value.status == G.GAP_EINVAL and "STRIPS" in str(ei.value)
+    cfg = s.pcg_config
+    assert cfg["strips_w"] == 20
+    p, info = s.solve(omega=1.6, eps=1e-13, iteration=G.GAP_ITERATION_STRIPS)
+    F = s.integrate().cpu().numpy()
+    p = p.reshape(9, -1).cpu().numpy()
+    conds = oracle.conditions(case.e, case.edot, case.delta)
+    for k in (0, 1, 5):
+        F_ref, p_ref = oracle.condition_forces(gap, *conds[k], tex)
+        perr = np.linalg.norm(p[k] - p_ref) / np.linalg.norm(p_ref)
+        ferr = max(np.linalg.norm(F[k, :2] - F_ref[:2]) / np.linalg.norm(F_ref[:2]),
+                   np.linalg.norm(F[k, 2:] - F_ref[2:]) / np.linalg.norm(F_ref[2:]))
+        log(f"  condition {k}: {info.iterations} iterations, pressure {perr:.1e}, forces {ferr:.1e}")
+        assert perr <= 1e-9 and ferr <= 1e-8
+    s.close()
+
+
+def test_widest_ring_follows_the_oracle_pcg():
+    """n_theta = 16384, the largest ring: 100 strip iterations against the oracle's Table 1 PCG
+    on the same system (the exact solve is out of reach at this bandwidth)."""
+    case = synth.textured_case(16384, 3, 8)
+    log(f"case: {case.label}, 1 condition, 100 strip iterations")
+    gap, tex = gap_of(case), texture_of(case)
+    A, S = oracle.assemble(gap, case.e, case.edot, tex)
+    p_ref, it_ref, hist = oracle.pcg(A, S, oracle.assor2_precond(A, 1.6), 1e-300, 100)
+    s = JointGapSolver.from_case(case, max_cond=1)
+    s.assemble(case.e, case.edot, None, 1)
+    p, info = s.solve(omega=1.6, eps=1e-300, max_iter=100, raise_on_error=False,
+                      iteration=G.GAP_ITERATION_STRIPS)
+    p = p.reshape(-1).cpu().numpy()
+    s.close()
+    perr = np.linalg.norm(p - p_ref) / np.linalg.norm(p_ref)
+    log(f"  pressure {perr:.1e}, recurrence residual {info.rel_residual:.3e} vs {hist[-1]:.3e}")
+    assert info.status == G.GAP_ENOCONV and info.iterations == 100 == it_ref
+    assert perr <= 1e-8 and abs(info.rel_residual - hist[-1]) <= 1e-6 * hist[-1]
+
+
 def test_empty_batch_steps_and_polls():
     log("case: empty batch")
     b = G.gap_batch_create()
@@ -121,8 +172,9 @@ def test_empty_batch_steps_and_polls():
     G.gap_batch_destroy(b)
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                          G.GAP_ITERATION_STRIPS],
+                         ids=["two_launch", "one_launch", "strips"])
 def test_non_finite_warm_start_reports_enonfinite_and_the_handle_recovers(iteration):
     """A warm-start field holding a NaN: r_0 = S - A p_0 is NaN near that cell, so the first
     reduction is not finite.  The solve stops with GAP_ENONFINITE (NaN arithmetic only, every

@@ -48,8 +48,9 @@ def sample_cells(nt, nz, rng, count=3000):
     return np.concatenate([i, edge_i, col_i]), np.concatenate([j, edge_j, col_j])
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                         ids=["two_launch", "one_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                          G.GAP_ITERATION_STRIPS],
+                         ids=["two_launch", "one_launch", "strips"])
 def test_joint_textured_2048x1024_full_size(iteration):
     case = synth.make_case("joint_textured_2048x1024", 0)
     log(f"case: {case.label}, 9 conditions, full size, iteration kind {iteration}")

@@ -81,15 +81,15 @@ def c3():
     s.close()
 
 
-@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_TWO_LAUNCH],
-                         ids=["one_launch", "two_launch"])
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_STRIPS, G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_TWO_LAUNCH],
+                         ids=["strips", "one_launch", "two_launch"])
 def test_joint_textured_2048x1024_against_exact_solution(c3, iteration):
     gold, case, s, W, rows, cols = c3
     log(f"case: {case.label}, 9 conditions, against the stored exact solution, iteration kind {iteration}")
     opts = s.options(omega=case.omega, eps=1e-13, iteration=iteration)
     cfg, _ = s.tune(opts, iterations=20)
     log(f"  launch configuration {cfg}")
-    sweep = (1e-10, 1e-11, 1e-12, 1e-13) if iteration == G.GAP_ITERATION_ONE_LAUNCH else (1e-13,)
+    sweep = (1e-10, 1e-11, 1e-12, 1e-13) if iteration == G.GAP_ITERATION_STRIPS else (1e-13,)
     for eps in sweep:
         opts = s.options(omega=case.omega, eps=eps, iteration=iteration)
         p, info = s.solve(opts)

@@ -25,8 +25,9 @@ from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
 P_TOL, F_TOL, J_TOL = 1e-9, 1e-8, 1e-5
 EPS_PARITY = 1e-13
 # both iteration kinds: Table 1 as printed (two launches) and the one-launch default
-ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                                     ids=["two_launch", "one_launch"])
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                                      G.GAP_ITERATION_STRIPS],
+                                     ids=["two_launch", "one_launch", "strips"])
 
 
 def log(msg):
@@ -146,6 +147,40 @@ def test_iteration_counts_follow_oracle_pcg(precond, name, iteration):
     p, F, J, info = gpu_case(case, 9, eps=1e-10, precond=precond, omega=1.6, iteration=iteration)
     assert abs(info.iterations - it_ref) <= 2, (info.iterations, it_ref)
     assert np.linalg.norm(p.ravel() - pG) / np.linalg.norm(pG) < 1e-8
+
+
+@pytest.mark.parametrize("m", [2, 3])
+@pytest.mark.parametrize("shape", [(96, 48), (300, 41)], ids=["96x48", "300x41"])
+def test_neumann_order_follows_oracle(shape, m):
+    """ASSOR II with the series of Eq 3.4 kept to order m in both factors (strip iteration):
+    the iteration count within 2 of the oracle's Table 1 PCG with assor2_precond(neumann=m) on
+    the same joint matrix, fewer iterations than order 1, and at eps 1e-13 the pressure and
+    forces of conditions 0, 1 and 5 against the exact (banded-Cholesky) solution."""
+    case = synth.textured_case(*shape, 3)
+    log(f"case: {case.label}, 9 conditions, Neumann order {m}")
+    gap, tex = gap_of(case), texture_of(case)
+    blocks, rhs = [], []
+    for ek, edk in oracle.conditions(case.e, case.edot, case.delta):
+        A, S = oracle.assemble(gap, ek, edk, tex)
+        blocks.append(A)
+        rhs.append(S)
+    Ms = [oracle.assor2_precond(A, 1.6, neumann=m) for A in blocks]
+    _, it_ref, _ = oracle.pcg_blocks(blocks, rhs, Ms, 1e-10, 100000, "global", "sync")
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    _, info1 = s.solve(omega=1.6, eps=1e-10, iteration=G.GAP_ITERATION_STRIPS)
+    _, info = s.solve(omega=1.6, eps=1e-10, neumann=m, iteration=G.GAP_ITERATION_STRIPS)
+    log(f"  iterations {info.iterations} (oracle {it_ref}; order 1: {info1.iterations})")
+    assert abs(info.iterations - it_ref) <= 2 and info.iterations < info1.iterations
+    p, info13 = s.solve(omega=1.6, eps=1e-13, neumann=m, iteration=G.GAP_ITERATION_STRIPS)
+    F = s.integrate().cpu().numpy()
+    p = p.reshape(9, -1).cpu().numpy()
+    s.close()
+    conds = oracle.conditions(case.e, case.edot, case.delta)
+    for k in (0, 1, 5):
+        F_ref, p_ref = oracle.condition_forces(gap, *conds[k], tex)
+        assert pressure_err(p[k:k + 1], p_ref[None]) <= P_TOL
+        assert force_err(F[k:k + 1], F_ref[None]) <= F_TOL
 
 
 @ITERATIONS

@@ -15,7 +15,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2511_06824_amd import gapsolve as G  # noqa: E402
-from paper_2511_06824_amd.serve import BatchBackend, GapServer, Request, latency_stats  # noqa: E402
+from paper_2511_06824_amd.serve import BatchBackend, GapServer, LaneServer, Request, latency_stats  # noqa: E402
 from paper_2511_06824_amd.solver import JointGapSolver  # noqa: E402
 
 
@@ -27,12 +27,13 @@ CASES = [synth.smooth_case(64, 32, 0), synth.textured_case(128, 64, 1), synth.sm
          synth.textured_case(256, 128, 3), synth.smooth_case(96, 48, 4, eps=1e-12)]
 
 
-ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                                     ids=["two_launch", "one_launch"])
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                                      G.GAP_ITERATION_STRIPS],
+                                     ids=["two_launch", "one_launch", "strips"])
 
 
 def batch_solve(cases, eps_override=None, iters=8, use_graph=True, iteration=G.GAP_ITERATION_ONE_LAUNCH,
-                join_every=0):
+                join_every=0, neumann=1):
     """Solve the cases together in one batch; returns pressures, infos by case index.
     join_every > 0: the cases join one at a time, one step of `iters` iterations apart."""
     b = G.gap_batch_create()
@@ -44,7 +45,7 @@ def batch_solve(cases, eps_override=None, iters=8, use_graph=True, iteration=G.G
     def add(c):
         s = JointGapSolver.from_case(c, max_cond=9)
         s.assemble(c.e, c.edot, c.delta, 9)
-        opts = s.options(omega=c.omega, eps=eps_override or c.eps, iteration=iteration)
+        opts = s.options(omega=c.omega, eps=eps_override or c.eps, iteration=iteration, neumann=neumann)
         ids.append(G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream))
         solvers.append((s, opts))
 
@@ -78,21 +79,63 @@ def test_results_alone_and_in_the_mix_are_bitwise_equal(iteration):
             assert np.array_equal(alone[2], other[2]), c.label
 
 
-def test_one_launch_batch_matches_a_solve_of_its_own():
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_STRIPS],
+                         ids=["one_launch", "strips"])
+def test_one_launch_batch_matches_a_solve_of_its_own(iteration):
     """A request in a one-launch batch, joining at an odd launch count, takes the iterations
     of the same grid solved by solve_joint_pcg (its chunking follows the batch shape, so the
     iterates agree up to the summation order)."""
     c = synth.textured_case(192, 64, 10)
-    log(f"case: {c.label}, batch vs own solve")
-    got = batch_solve([CASES[0], c], iters=5, join_every=1, eps_override=1e-12)[1]
+    log(f"case: {c.label}, batch vs own solve, iteration kind {iteration}")
+    got = batch_solve([CASES[0], c], iters=5, join_every=1, eps_override=1e-12, iteration=iteration)[1]
     s = JointGapSolver.from_case(c, max_cond=9)
     s.assemble(c.e, c.edot, c.delta, 9)
-    p, info = s.solve(omega=c.omega, eps=1e-12)
+    p, info = s.solve(omega=c.omega, eps=1e-12, iteration=iteration)
     p = p.cpu().numpy()
     s.close()
     assert abs(info.iterations - got[1]) <= 1
     for k in range(9):
         assert np.linalg.norm(got[0][k] - p[k]) <= 1e-10 * np.linalg.norm(p[k])
+
+
+def test_neumann_order_batch_matches_own_solves_and_refuses_another_order():
+    """Requests at Neumann order 2 in one strip batch, joining at odd launch counts, take the
+    iterations of their own solves at that order; a request at another order is refused."""
+    cases = [synth.textured_case(192, 64, 10), synth.smooth_case(130, 77, 11)]
+    log("case: strip batch at Neumann order 2")
+    got = batch_solve(cases, iters=5, join_every=1, eps_override=1e-12, iteration=G.GAP_ITERATION_STRIPS,
+                      neumann=2)
+    for k, c in enumerate(cases):
+        s = JointGapSolver.from_case(c, max_cond=9)
+        s.assemble(c.e, c.edot, c.delta, 9)
+        p, info = s.solve(omega=c.omega, eps=1e-12, neumann=2, iteration=G.GAP_ITERATION_STRIPS)
+        p = p.cpu().numpy()
+        s.close()
+        log(f"  {c.label}: batch {got[k][1]} iterations, own solve {info.iterations}")
+        assert abs(info.iterations - got[k][1]) <= 1
+        for j in range(9):
+            assert np.linalg.norm(got[k][0][j] - p[j]) <= 1e-10 * np.linalg.norm(p[j])
+    b = G.gap_batch_create()
+    stream = torch.cuda.current_stream().cuda_stream
+    made = []
+    for k, m in enumerate((2, 1)):
+        c = synth.smooth_case(64, 32, 40 + k)
+        s = JointGapSolver.from_case(c, max_cond=9)
+        s.assemble(c.e, c.edot, c.delta, 9)
+        made.append(s)
+        opts = s.options(omega=c.omega, eps=c.eps, iteration=G.GAP_ITERATION_STRIPS, neumann=m)
+        if k == 0:
+            bid = G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
+        else:
+            with pytest.raises(G.GapError) as ei:
+                G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
+            assert ei.value.status == G.GAP_EINVAL
+    while not G.gap_batch_poll(b):
+        G.gap_batch_step(b, 16, True, stream)
+    G.gap_batch_remove(b, bid, stream)
+    for s in made:
+        s.close()
+    G.gap_batch_destroy(b)
 
 
 def test_batch_refuses_a_second_iteration_kind():
@@ -225,6 +268,47 @@ def test_server_with_work_cap_drains_a_mixed_stream():
     assert sorted(r.rid for r in done) == list(range(5)) and all(r.status == G.GAP_OK for r in done)
     by = {r.rid: r for r in done}
     assert by[0].finished <= by[2].finished                    # the two large ones in order
+
+
+def test_two_lanes_give_each_request_its_result_alone():
+    """Two lanes on two streams and threads (bulk: 256x128 and larger, chunked for 2
+    workgroups per CU; fast: the rest, 1 per CU), over a staggered stream: every request's
+    pressure, forces and FD Jacobian are bitwise those of the same request alone in a batch of
+    its lane's chunking target, and match a solve of its own to 1e-9."""
+    log("case: two-lane server, 7 requests 64x32 ... 512x256, targets 2 and 1")
+    sizes = [(512, 256), (64, 32), (128, 64), (256, 128), (96, 48), (512, 128), (200, 37)]
+    reqs = []
+    for k, (nt, nz) in enumerate(sizes):
+        c = (synth.textured_case(nt, nz, 20 + k, eps=1e-12) if k % 2
+             else synth.smooth_case(nt, nz, 20 + k, eps=1e-12))
+        reqs.append(Request(rid=k, case=c, arrival=0.004 * k))
+    bulk_work = 9 * 256 * 128
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    bulk = BatchBackend(iterations_per_step=16, stream=streams[0], wg_per_cu=2, keep_pressure=True)
+    fast = BatchBackend(iterations_per_step=16, stream=streams[1], wg_per_cu=1, keep_pressure=True)
+    budget = 4 * max(bulk.footprint(r.case) for r in reqs)
+    srv = LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work)
+    done = {r.rid: r for r in srv.run(reqs)}
+    bulk.close()
+    fast.close()
+    assert sorted(done) == list(range(len(sizes))) and all(r.status == G.GAP_OK for r in done.values())
+    assert {k for k, r in done.items() if r.meta["lane"] == "bulk"} == {0, 3, 5}
+    for k, r in done.items():
+        c = r.case
+        target = 2 if r.meta["lane"] == "bulk" else 1
+        be = BatchBackend(iterations_per_step=16, wg_per_cu=target, keep_pressure=True)
+        alone = GapServer(be, budget).run([Request(rid=k, case=c, arrival=0.0)])[0]
+        be.close()
+        assert alone.iterations == r.iterations, c.label
+        for a, b in ((alone.p, r.p), (alone.F, r.F), (alone.J, r.J)):
+            assert np.array_equal(a, b), c.label
+        s = JointGapSolver.from_case(c, max_cond=9)
+        s.assemble(c.e, c.edot, c.delta, 9)
+        p_own, _ = s.solve(omega=c.omega, eps=c.eps)
+        p_own = p_own.cpu().numpy()
+        s.close()
+        for m in range(9):
+            assert np.linalg.norm(r.p[m] - p_own[m]) <= 1e-9 * np.linalg.norm(p_own[m]), c.label
 
 
 def test_a_grid_in_a_batch_is_lent_to_it():

@@ -25,8 +25,9 @@ def solve_copy(s, **opt):
     return p.clone().cpu().numpy(), info.iterations, info.rel_residual
 
 
-ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                                     ids=["two_launch", "one_launch"])
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                                      G.GAP_ITERATION_STRIPS],
+                                     ids=["two_launch", "one_launch", "strips"])
 
 
 @ITERATIONS
@@ -66,8 +67,9 @@ def test_timing_hooks_do_not_change_results(iteration):
     G.gap_kernel_timing(s.handle, 0)
     n = [G.gap_kernel_stats(s.handle, k) for k in range(G.GAP_KERNEL_COUNT)]
     assert np.array_equal(p0, p1) and np.array_equal(p0, p2) and i0 == i1 == i2
-    timed = [G.GAP_KERNEL_PCG_A, G.GAP_KERNEL_PCG_B] if iteration == G.GAP_ITERATION_TWO_LAUNCH \
-        else [G.GAP_KERNEL_PCG_ONE]
+    timed = {G.GAP_ITERATION_TWO_LAUNCH: [G.GAP_KERNEL_PCG_A, G.GAP_KERNEL_PCG_B],
+             G.GAP_ITERATION_ONE_LAUNCH: [G.GAP_KERNEL_PCG_ONE],
+             G.GAP_ITERATION_STRIPS: [G.GAP_KERNEL_PCG_STRIPS]}[iteration]
     for k in range(G.GAP_KERNEL_COUNT):
         if k in timed:
             assert n[k][0] >= 2 * i0 and n[k][1] > 0
@@ -93,9 +95,9 @@ def test_timing_hooks_do_not_change_results(iteration):
 
 
 def test_one_launch_agrees_with_table1_iteration():
-    """The one-launch iteration takes Table 1's steps with alpha's denominator expanded: the
-    same iteration count (within one) and the same iterate up to rounding, on every
-    preconditioner and scalar / strategy variant."""
+    """Both one-launch iterations (whole rings; strips with z recomputed) take Table 1's steps
+    with alpha's denominator expanded: the same iteration count (within one) and the same
+    iterate up to rounding, on every preconditioner and scalar / strategy variant."""
     case = synth.textured_case(300, 96, 5)
     log(f"case: {case.label}, one-launch against two-launch")
     s = JointGapSolver.from_case(case, max_cond=9)
@@ -104,13 +106,14 @@ def test_one_launch_agrees_with_table1_iteration():
               dict(scalars=G.GAP_SCALARS_PER_COND), dict(strategy=G.GAP_STRATEGY_ASYNC),
               dict(scalars=G.GAP_SCALARS_PER_COND, strategy=G.GAP_STRATEGY_ASYNC)]:
         out = []
-        for it in (G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH):
+        for it in (G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_STRIPS):
             p, info = s.solve(eps=1e-12, omega=1.6, iteration=it, **v)
             out.append((p.clone().cpu().numpy().reshape(9, -1), info.iterations, info.rel_residual))
-        (p2, i2, r2), (p1, i1, r1) = out
-        d = max(np.linalg.norm(p1[k] - p2[k]) / np.linalg.norm(p2[k]) for k in range(9))
-        log(f"  {v}: iterations {i2} / {i1}, residual {r2:.2e} / {r1:.2e}, difference {d:.1e}")
-        assert abs(i1 - i2) <= 1 and r1 <= 1e-12 and d <= 1e-10
+        p2, i2, r2 = out[0]
+        for name, (p1, i1, r1) in zip(("one launch", "strips"), out[1:]):
+            d = max(np.linalg.norm(p1[k] - p2[k]) / np.linalg.norm(p2[k]) for k in range(9))
+            log(f"  {v}, {name}: iterations {i2} / {i1}, residual {r2:.2e} / {r1:.2e}, difference {d:.1e}")
+            assert abs(i1 - i2) <= 1 and r1 <= 1e-12 and d <= 1e-10
     s.close()
 
 

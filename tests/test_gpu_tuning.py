@@ -46,8 +46,9 @@ def reference(nt, nz, n_cond):
     return _ref[key]
 
 
-ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH],
-                                     ids=["two_launch", "one_launch"])
+ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G.GAP_ITERATION_ONE_LAUNCH,
+                                      G.GAP_ITERATION_STRIPS],
+                                     ids=["two_launch", "one_launch", "strips"])
 
 
 def check(s, case, n_cond, p_ref, F_ref, iteration=G.GAP_ITERATION_ONE_LAUNCH):
@@ -70,7 +71,17 @@ def test_every_configuration_matches_oracle(nt, nz, n_cond, iteration):
     for k in "abf":
         assert (cfg0[f"threads_{k}"], cfg0[f"cols_per_thread_{k}"]) == SHAPES[nt][0]
     configs = []
-    if iteration == G.GAP_ITERATION_TWO_LAUNCH:
+    if iteration == G.GAP_ITERATION_STRIPS:
+        assert cfg0["cols_per_lane_w"] == 2
+        for Q in (1, 2):
+            occ = s.set_strip_config(Q, 1)
+            for w in sorted({1, occ["occupancy_w"]}):
+                cfg = s.set_strip_config(Q, w)
+                log(f"case: {case.label} x{n_cond}, strips, config {cfg}")
+                perr, ferr, info = check(s, case, n_cond, p_ref, F_ref, iteration)
+                log(f"  iterations {info.iterations}, pressure {perr:.2e}, forces {ferr:.2e}")
+                assert perr <= P_TOL and ferr <= F_TOL
+    elif iteration == G.GAP_ITERATION_TWO_LAUNCH:
         for NT, Q in SHAPES[nt]:
             occ = s.set_pcg_config(NT, Q, 1, 1)
             for wa, wb in sorted({(1, 1), (occ["occupancy_a"], occ["occupancy_b"]), (1, occ["occupancy_b"])}):
@@ -106,6 +117,7 @@ def test_autotuner_choice_is_valid_and_matches_oracle(iteration):
     for k in "abf":
         assert (cfg[f"threads_{k}"], cfg[f"cols_per_thread_{k}"]) in SHAPES[300]
         assert 1 <= cfg[f"wg_per_cu_{k}"] <= cfg[f"occupancy_{k}"]
+    assert cfg["cols_per_lane_w"] in (1, 2) and 1 <= cfg["wg_per_cu_w"] <= cfg["occupancy_w"]
     assert us > 0.0 and s.pcg_config == cfg
     perr, ferr, _ = check(s, case, 9, p_ref, F_ref, iteration)   # the system survives tuning unchanged
     assert perr <= P_TOL and ferr <= F_TOL
@@ -134,8 +146,19 @@ def test_configuration_validation():
         s.set_pcg_config(512, 1, 1, 1, wg_per_cu_f=9)
     assert ei.value.status == G.GAP_EINVAL
     with pytest.raises(G.GapError) as ei:                                     # unknown iteration kind
-        s.solve(eps=1e-10, iteration=2)
+        s.solve(eps=1e-10, iteration=3)
     assert ei.value.status == G.GAP_EINVAL
+    for q, w in [(0, 1), (3, 1), (2, 0), (2, 9)]:                             # strip kernel
+        with pytest.raises(G.GapError) as ei:
+            s.set_strip_config(q, w)
+        assert ei.value.status == G.GAP_EINVAL
+    # Neumann orders above 1: ASSOR II on the strip iteration only, at most 3
+    for kw in [dict(neumann=2, iteration=G.GAP_ITERATION_ONE_LAUNCH),
+               dict(neumann=2, iteration=G.GAP_ITERATION_TWO_LAUNCH),
+               dict(neumann=2, precond=G.GAP_PRECOND_JACOBI), dict(neumann=4), dict(neumann=0)]:
+        with pytest.raises(G.GapError) as ei:
+            s.solve(eps=1e-10, **kw)
+        assert ei.value.status == G.GAP_EINVAL
     s.assemble(case.e, case.edot, None, 1)
     with pytest.raises(G.GapError) as ei:
         G.gap_tune_pcg(s.handle, s.options(), s.p.data_ptr(), 1)
@@ -157,9 +180,35 @@ def test_iteration_limited_solve_launches_no_idle_block(iteration):
     n = [G.gap_kernel_stats(s.handle, k)[0] for k in range(G.GAP_KERNEL_COUNT)]
     G.gap_kernel_timing(s.handle, 0)
     assert info.iterations == 40 and info.status == G.GAP_ENOCONV
-    assert n == ([41, 40, 0] if iteration == G.GAP_ITERATION_TWO_LAUNCH else [0, 0, 41])
+    assert n == {G.GAP_ITERATION_TWO_LAUNCH: [41, 40, 0, 0], G.GAP_ITERATION_ONE_LAUNCH: [0, 0, 41, 0],
+                 G.GAP_ITERATION_STRIPS: [0, 0, 0, 41]}[iteration]
     # the same iterate as an uninterrupted run of 40 iterations in one block (graph replay)
     p1 = s.p.clone()
     s.solve(check_every=40, **kw)
     assert torch.equal(p1, s.p)
     s.close()
+
+
+def test_neumann_tuner_picks_the_fastest_order_and_matches_oracle():
+    """gap_tune_neumann times a complete solve at each Neumann order 1 .. 3 (each with its own
+    tuned strip configuration) and keeps the fastest; the solve at that order matches the
+    exact solution."""
+    case = synth.textured_case(256, 128, 6)
+    log(f"case: {case.label}, Neumann-order tuner")
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, case.delta, 9)
+    best, secs = s.tune_neumann(s.options(omega=1.6, eps=1e-10), max_order=3)
+    log(f"  seconds per solve by order {secs}, best {best}")
+    assert best == int(np.argmin(secs)) + 1 and all(x > 0 for x in secs)
+    p, info = s.solve(omega=1.6, eps=1e-13, neumann=best)
+    p = p.reshape(9, -1).cpu().numpy()
+    for bad in (dict(iteration=G.GAP_ITERATION_ONE_LAUNCH), dict(precond=G.GAP_PRECOND_JACOBI)):
+        with pytest.raises(G.GapError) as ei:
+            G.gap_tune_neumann(s.handle, s.options(**bad), s.p.data_ptr(), 3)
+        assert ei.value.status == G.GAP_EINVAL
+    with pytest.raises(G.GapError) as ei:
+        G.gap_tune_neumann(s.handle, s.options(), s.p.data_ptr(), 4)
+    assert ei.value.status == G.GAP_EINVAL
+    s.close()
+    F_ref, p_ref = oracle.condition_forces(gap_of(case), case.e, case.edot, texture_of(case))
+    assert np.linalg.norm(p[0] - p_ref) <= P_TOL * np.linalg.norm(p_ref)

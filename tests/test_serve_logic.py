@@ -1,11 +1,12 @@
-"""Admission and scheduling logic of the serving loop, on the CPU with a fake backend
-(mock footprints and durations, virtual clock)."""
+"""Admission and scheduling logic of the serving loop, on the CPU with fake backends (mock
+footprints and durations; a virtual clock for one lane, short real sleeps for two lanes)."""
 
+import time
 from types import SimpleNamespace
 
 import pytest
 
-from paper_2511_06824_amd.serve import AdmissionController, GapServer, Request, latency_stats
+from paper_2511_06824_amd.serve import AdmissionController, GapServer, LaneServer, Request, latency_stats
 
 
 class FakeClock:
@@ -147,3 +148,82 @@ def test_smallest_first_lets_small_requests_pass_a_large_one():
     assert done[0].finished == 7.0
     with pytest.raises(ValueError):
         GapServer(be, budget_bytes=1, clock=clock, order="random")
+
+
+class SleepBackend:
+    """Real-time fake for the lane tests: every step sleeps step_s of wall time and advances
+    every active request (or the selected ones) by one step."""
+
+    def __init__(self, step_s):
+        self.step_s = step_s
+        self.live = []
+        self.started = []
+        self.selected = None
+        self.max_work = 0
+
+    def footprint(self, case):
+        return case.fake_bytes
+
+    @staticmethod
+    def work(case):
+        return case.fake_work
+
+    def start(self, req):
+        self.live.append([req, req.case.fake_steps])
+        self.started.append(req.rid)
+
+    def active(self):
+        return [x[0] for x in self.live]
+
+    def select(self, chosen):
+        self.selected = {r.rid for r in chosen}
+
+    def step(self):
+        time.sleep(self.step_s)
+        moving = [x for x in self.live if self.selected is None or x[0].rid in self.selected]
+        self.max_work = max(self.max_work, sum(self.work(x[0].case) for x in moving))
+        for x in moving:
+            x[1] -= 1
+        out = [x[0] for x in self.live if x[1] <= 0]
+        self.live = [x for x in self.live if x[1] > 0]
+        return out
+
+    def idle(self):
+        return not self.live
+
+
+def test_lanes_split_by_work_and_small_requests_do_not_wait_for_bulk_ones():
+    bulk, fast = SleepBackend(0.004), SleepBackend(0.001)
+    srv = LaneServer(bulk, fast, budget_bytes=1000, bulk_work=4)
+    rs = [req(0, 0.0, 100, 40, work=4), req(1, 0.0, 100, 40, work=4),
+          req(2, 0.02, 10, 3, work=1), req(3, 0.03, 10, 3, work=2), req(4, 0.05, 10, 2, work=1)]
+    done = {r.rid: r for r in srv.run(rs)}
+    assert sorted(done) == [0, 1, 2, 3, 4]
+    assert {r.meta["lane"] for r in rs if r.rid < 2} == {"bulk"}
+    assert {r.meta["lane"] for r in rs if r.rid >= 2} == {"fast"}
+    assert bulk.started == [0, 1] and fast.started == [2, 3, 4]
+    assert bulk.max_work == 4                      # bulk requests never advance together
+    assert done[1].finished > done[0].finished     # arrival order within the bulk lane
+    for k in (2, 3, 4):                            # the small ones finish while bulk work runs
+        assert done[k].finished < done[0].finished
+    assert srv.admission.used == 0 and srv.admission.active == 0
+
+
+def test_lanes_share_one_budget_and_wait_for_each_other():
+    bulk, fast = SleepBackend(0.002), SleepBackend(0.001)
+    srv = LaneServer(bulk, fast, budget_bytes=100, bulk_work=4)
+    # each request needs 60 of the 100 bytes: at most one is on the device at any time
+    rs = [req(0, 0.0, 60, 10, work=4), req(1, 0.001, 60, 5, work=1), req(2, 0.002, 60, 5, work=1)]
+    done = {r.rid: r for r in srv.run(rs)}
+    assert sorted(done) == [0, 1, 2]
+    assert srv.admission.peak <= 100
+    spans = sorted((r.admitted, r.finished) for r in done.values())
+    for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
+        assert a1 >= f0                            # never two on the device together
+
+
+def test_a_failing_lane_raises_in_the_caller():
+    bulk, fast = SleepBackend(0.001), SleepBackend(0.001)
+    srv = LaneServer(bulk, fast, budget_bytes=50, bulk_work=4)
+    with pytest.raises(ValueError):
+        srv.run([req(0, 0.0, 60, 2, work=4), req(1, 0.0, 10, 2, work=1)])
