@@ -211,7 +211,8 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     as plain one-condition-at-a-time solves."""
     import numpy as np
     import synth
-    from paper_2511_06824_amd.serve import BatchBackend, LaneServer, Request, WallClock, latency_stats, run_fifo
+    from paper_2511_06824_amd.serve import (BatchBackend, HandlePool, LaneServer, Request, WallClock, latency_stats,
+                                            run_fifo)
     counts = counts or SERVE_COUNTS
 
     def make(arrivals):
@@ -223,15 +224,16 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     budget = int(0.8 * free)
     bulk_work = 9 * SERVE_BULK[0] * SERVE_BULK[1]
     streams = (torch.cuda.Stream(dev), torch.cuda.Stream(dev))
+    # both servers keep their handles (and the batches their graphs) across the runs below
+    bulk = BatchBackend(iterations_per_step=32, stream=streams[0], wg_per_cu=targets[0])
+    fast = BatchBackend(iterations_per_step=32, stream=streams[1], wg_per_cu=targets[1])
+    fifo_pool = HandlePool(dev)
 
     def batched(reqs):
-        bulk = BatchBackend(iterations_per_step=32, stream=streams[0], wg_per_cu=targets[0])
-        fast = BatchBackend(iterations_per_step=32, stream=streams[1], wg_per_cu=targets[1])
-        try:
-            return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work).run(reqs)
-        finally:
-            bulk.close()
-            fast.close()
+        return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work).run(reqs)
+
+    def fifo(reqs):
+        return run_fifo(reqs, pool=fifo_pool)
 
     def plain_fifo(reqs):
         clock = WallClock()
@@ -244,12 +246,11 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
             done.append(r)
         return done
 
-    warm = make(np.zeros(10))                   # warm-up: kernels and graphs of every size
-    run_fifo(warm)
-    batched(make(np.zeros(10)))
+    fifo(make(np.zeros(12)))                    # warm-up: kernels, graphs and handles of every size
+    batched(make(np.zeros(12)))
     backlog = batched(make(np.zeros(capacity_count)))
     capacity = capacity_count / max(r.finished for r in backlog)
-    fifo_back = run_fifo(make(np.zeros(capacity_count)))
+    fifo_back = fifo(make(np.zeros(capacity_count)))
     fifo_capacity = capacity_count / max(r.finished for r in fifo_back)
     print(f"bench: served stream capacity batched {capacity:.3f}/s, one at a time {fifo_capacity:.3f}/s",
           file=sys.stderr, flush=True)
@@ -258,7 +259,7 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
         rate = load * capacity
         arrivals = synth.poisson_arrivals(np.random.default_rng(seed + 1), rate, count)
         b = latency_stats(batched(make(arrivals)))
-        f = latency_stats(run_fifo(make(arrivals)))
+        f = latency_stats(fifo(make(arrivals)))
         run = {"load": load, "requests": count, "arrival_rate_per_s": round(rate, 3), "batched": _round(b),
                "one_at_a_time_joint": _round(f)}
         if load == 0.8:
@@ -268,7 +269,13 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
               f"p99 {b['p99_s']:.3f} s, one at a time p50 {f['p50_s']:.3f} s p99 {f['p99_s']:.3f} s",
               file=sys.stderr, flush=True)
         runs.append(run)
-    return {"capacity_requests": capacity_count, "capacity_batched_per_s": round(capacity, 3),
+    handles = {"batched_created": bulk.pool.created + fast.pool.created,
+               "batched_reused": bulk.pool.reused + fast.pool.reused,
+               "one_at_a_time_created": fifo_pool.created, "one_at_a_time_reused": fifo_pool.reused}
+    bulk.close()
+    fast.close()
+    fifo_pool.close()
+    return {"capacity_requests": capacity_count, "capacity_batched_per_s": round(capacity, 3), "handles": handles,
             "capacity_one_at_a_time_joint_per_s": round(fifo_capacity, 3),
             "lanes": {"bulk_cells_min": list(SERVE_BULK), "wg_per_cu_bulk": targets[0], "wg_per_cu_fast": targets[1],
                       "iterations_per_step": 32},
@@ -322,38 +329,24 @@ def run_precond_study(JointGapSolver, dev):
     return {"workload": "joint_smooth_512x256", "eps": case.eps, "summary": summ, "rows": rows}
 
 
-def run_adjoint_vs_fd(torch, JointGapSolver, dev):
+ADJOINT_EPS = 1e-7     # stopping tolerance of the adjoint systems in the FD / adjoint comparison
+
+
+def run_adjoint_vs_fd(torch, G, JointGapSolver, dev, eps_adjoint=ADJOINT_EPS):
     """Cost of the 4 x 8 Jacobian on the 1024 x 512 textured workload: the 9-condition
-    forward-difference solve against one base solve plus the 4 adjoint solves."""
+    forward-difference solve (Eq 2.13-2.14) against the joint solve of the base system with
+    its 4 adjoint systems, and against the base solve followed by the 4 adjoint systems.  The
+    base systems stop at the workload's eps, the adjoint systems at `eps_adjoint` (the
+    Jacobian is a product with lambda, no difference quotient).  Each launch scheme (strips;
+    whole-ring one launch) is tuned on the 9-condition system and timed for every path;
+    fd_over_adjoint compares the fastest FD with the fastest joint adjoint."""
+    import numpy as np
     import synth
     case = synth.make_case("adjoint_textured_1024x512", 0)
     s = JointGapSolver.from_case(case, max_cond=9, device=dev)
-    opts = s.options(omega=case.omega, eps=case.eps)
-    s.assemble(case.e, case.edot, case.delta, 9)
-    s.tune(opts, iterations=20)                  # one configuration for both paths
-
-    def fd():
-        s.assemble(case.e, case.edot, case.delta, 9)
-        _, info = s.solve(opts)
-        s.integrate()
-        s.jacobian_fd()
-        return info.iterations
-
-    def adj_seq():
-        s.assemble(case.e, case.edot, None, 1)
-        _, info = s.solve(opts)
-        s.integrate()
-        _, ainfo = s.jacobian_adjoint(opts)
-        return info.iterations, ainfo.iterations
-
-    def adj_joint():
-        s.assemble(case.e, case.edot, None, 1)
-        _, _, info = s.solve_with_adjoint(opts)
-        s.integrate()
-        return info.iterations
 
     def timed(fn, reps=3):
-        best = None
+        best, r = None, None
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -363,18 +356,60 @@ def run_adjoint_vs_fd(torch, JointGapSolver, dev):
             best = dt if best is None else min(best, dt)
         return best, r
 
-    fd(), adj_seq(), adj_joint()
-    t_fd, it_fd = timed(fd)
-    t_seq, it_seq = timed(adj_seq)
-    t_joint, it_joint = timed(adj_joint)
+    def blocks(J):
+        return [J[0:2, 0:4], J[0:2, 4:8], J[2:4, 0:4], J[2:4, 4:8]]
+
+    kinds = {}
+    for name, kind in (("strips", G.GAP_ITERATION_STRIPS), ("one_launch", G.GAP_ITERATION_ONE_LAUNCH)):
+        opts = s.options(omega=case.omega, eps=case.eps, iteration=kind, eps_adjoint=eps_adjoint)
+        tight = s.options(omega=case.omega, eps=case.eps, iteration=kind)
+        s.assemble(case.e, case.edot, case.delta, 9)
+        s.tune(opts, iterations=20)
+
+        def fd():
+            s.assemble(case.e, case.edot, case.delta, 9)
+            _, info = s.solve(opts)
+            s.integrate()
+            s.jacobian_fd()
+            return info.iterations
+
+        def adj_joint(o):
+            s.assemble(case.e, case.edot, None, 1)
+            _, J, info = s.solve_with_adjoint(o)
+            s.integrate()
+            return info.iterations, J
+
+        def adj_seq():
+            s.assemble(case.e, case.edot, None, 1)
+            _, info = s.solve(opts)
+            s.integrate()
+            _, ainfo = s.jacobian_adjoint(opts)
+            return info.iterations, ainfo.iterations
+
+        fd(), adj_joint(opts), adj_seq()
+        t_fd, it_fd = timed(fd)
+        t_joint, (it_joint, J_loose) = timed(lambda: adj_joint(opts))
+        t_tight, (it_tight, J_tight) = timed(lambda: adj_joint(tight))
+        t_seq, it_seq = timed(adj_seq)
+        J_loose, J_tight = J_loose.cpu().numpy(), J_tight.cpu().numpy()
+        dJ = max(np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(blocks(J_loose), blocks(J_tight)))
+        kinds[name] = {"fd_seconds": round(t_fd, 5), "fd_iterations": it_fd,
+                       "adjoint_seconds": round(t_joint, 5), "adjoint_iterations": it_joint,
+                       "adjoint_all_at_eps_seconds": round(t_tight, 5), "adjoint_all_at_eps_iterations": it_tight,
+                       "adjoint_after_base_seconds": round(t_seq, 5),
+                       "adjoint_after_base_iterations": {"base": it_seq[0], "adjoint": it_seq[1]},
+                       "jacobian_vs_all_at_eps": float(f"{dJ:.3e}"),
+                       "config": {k: v for k, v in s.pcg_config.items() if k[-1] in ("w" if name == "strips" else "f")}}
+        print(f"bench: adjoint vs FD, {name}: {kinds[name]}", file=sys.stderr, flush=True)
     s.close()
+    fd_best = min(kinds.values(), key=lambda k: k["fd_seconds"])
+    adj_best = min(kinds.values(), key=lambda k: k["adjoint_seconds"])
     return {"workload": "adjoint_textured_1024x512", "timing": "best of 3, wall clock incl. assembly and forces",
-            "fd_seconds": round(t_fd, 5), "fd_iterations": it_fd,
-            "adjoint_seconds": round(t_joint, 5), "adjoint_iterations": it_joint,
-            "adjoint_method": "base + 4 adjoint systems in one joint solve (per-system stopping test)",
-            "adjoint_after_base_seconds": round(t_seq, 5),
-            "adjoint_after_base_iterations": {"base": it_seq[0], "adjoint": it_seq[1]},
-            "fd_over_adjoint": round(t_fd / t_joint, 3)}
+            "eps": case.eps, "eps_adjoint": eps_adjoint,
+            "adjoint_method": "base + 4 adjoint systems in one joint solve (per-system recurrence and stopping test)",
+            "by_iteration_kind": kinds,
+            "fd_seconds": fd_best["fd_seconds"], "adjoint_seconds": adj_best["adjoint_seconds"],
+            "fd_over_adjoint": round(fd_best["fd_seconds"] / adj_best["adjoint_seconds"], 3)}
 
 
 def main():
@@ -678,7 +713,7 @@ def main():
         serving = run_serving(torch, JointGapSolver, dev)
     adjoint = None
     if not args.no_adjoint:
-        adjoint = run_adjoint_vs_fd(torch, JointGapSolver, dev)
+        adjoint = run_adjoint_vs_fd(torch, G, JointGapSolver, dev)
 
     study = None
     if not args.no_study:

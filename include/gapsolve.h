@@ -187,6 +187,16 @@ gap_status create_gap_grid_field(const gap_geom *geom, const double *tex_c, cons
  * no-op. */
 gap_status destroy_gap_grid(gap_grid_t grid);
 
+/* Replace the texture of an existing handle by a dimple list (as create_gap_grid; count 0 or
+ * NULL: smooth), for reusing one handle across requests of the same geometry and grid: no
+ * device memory is allocated or freed (beyond growing the handle's parameter buffer past a
+ * multiple of 256 dimples) and no device-wide synchronization happens, so it may run beside
+ * work and graph captures of other threads.  Clears the texture planes and evaluates the
+ * caps on `stream`, then synchronizes that stream.  The next solve needs a new
+ * assemble_joint_system.  Errors: GAP_EINVAL (NULL grid, bad dimple), GAP_ESTATE (the grid
+ * is in a batch), GAP_ENOMEM, GAP_EDEVICE. */
+gap_status set_gap_dimples(gap_grid_t grid, const gap_dimples *dimples, void *stream);
+
 /* Step I (Sec 3.2; Eq 2.3-2.7, 2.17-2.19): assemble the n_cond (1 or 9, <= max_cond)
  * systems for base state e[4] (m), edot[4] (m/s) and FD steps delta[8] (e1..e4,
  * edot1..edot4; may be NULL when n_cond = 1).  Rates enter only the source, so
@@ -423,9 +433,9 @@ typedef struct {
     int32_t cols_per_thread_f;
     int32_t wg_per_cu_f;
     int32_t occupancy_f;        /* output */
-    int32_t cols_per_lane_w;    /* W (strip iteration): ring columns per lane, 1 or 2; a
-                                   wavefront's strip spans 64 x cols_per_lane_w columns and owns
-                                   all but 6 on either side */
+    int32_t cols_per_lane_w;    /* W (strip iteration): ring columns per lane, 1; a
+                                   wavefront's strip spans 64 columns and owns all but
+                                   4M + 2 on either side (M the Neumann order) */
     int32_t wg_per_cu_w;        /* W: row chunking target, >= 1 */
     int32_t occupancy_w;        /* output: W workgroups (4 wavefronts each) that fit on one CU */
     int32_t strips_w;           /* output: strips per ring */

@@ -56,6 +56,8 @@
 // c * chunks + (row chunk) * groups + (strip group).
 #pragma once
 
+#include <type_traits>
+
 #include "gap_pcg.hpp"
 
 constexpr int kStripWaves = 4;                      // strips (wavefronts) per workgroup
@@ -84,6 +86,17 @@ __device__ __forceinline__ double dpp_shift(double x, double fill)
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// The same move with BOUND_CTRL set: the lane without a source reads 0, so no fill value has
+// to be placed in the destination first.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift0(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 __device__ __forceinline__ double read_lane(double x, int l)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(x);
@@ -98,7 +111,7 @@ template <int Q>
 __device__ __forceinline__ void west_of(const double (&x)[Q], double (&w)[Q])
 {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) w[q] = dpp_shift<0x138>(x[q], q > 0 ? read_lane(x[q - 1], 63) : 0.0);
+    for (int q = 0; q < Q; ++q) w[q] = q > 0 ? dpp_shift<0x138>(x[q], read_lane(x[q - 1], 63)) : dpp_shift0<0x138>(x[q]);
 }
 
 // Value one to the east (m + 1): lane l + 1, lane 0 of block q + 1 for lane 63 (0 at the east end).
@@ -106,7 +119,18 @@ template <int Q>
 __device__ __forceinline__ void east_of(const double (&x)[Q], double (&e)[Q])
 {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) e[q] = dpp_shift<0x130>(x[q], q < Q - 1 ? read_lane(x[q + 1], 0) : 0.0);
+    for (int q = 0; q < Q; ++q) e[q] = q < Q - 1 ? dpp_shift<0x130>(x[q], read_lane(x[q + 1], 0)) : dpp_shift0<0x130>(x[q]);
+}
+
+// Runs the row steps of phases PH .. P - 1 (fn(s, phase) each), advancing s; false once s has
+// passed s_last.  Unrolled at compile time, so each step sees its phase as a constant.
+template <int PH, int P, class Fn>
+__device__ __forceinline__ bool strip_steps(Fn& fn, int& s, int s_last)
+{
+    fn(s, std::integral_constant<int, PH>{});
+    if (++s > s_last) return false;
+    if constexpr (PH + 1 < P) return strip_steps<PH + 1, P>(fn, s, s_last);
+    else return true;
 }
 
 // PK: the preconditioner fixed at compile time (0 Jacobi, 1 ASSOR I, 2 ASSOR II), or -1 to
@@ -179,81 +203,78 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     constexpr int LB = 2 * M + 1;                // lag of the last stage
     const int s_begin = max(j0 - LB, 0);
     const int s_last = min(j1, nz - 1) + LB;
-    // register rings, index d = row s - d (faces: d = face s + 1 - d)
-    double R[M + 2][Q];                         // r_j (S for the initial residual)
-    double KX[LB + 1][Q];                       // east-face conductances
-    double DI[LB + 1][Q];                       // 1/D
-    double F[LB + 2][Q];                        // axial faces
-    double T[M][Q];                             // first-sweep terms t_k of row s - 1 (z_j)
-    double V[M + 1][Q];                         // v of rows s .. s - M (z_j)
-    double W[M][M + 1][Q];                      // W[k][e]: second-sweep term w_k of row s - k - e (z_j), k >= 1
-    double U[3][Q];                             // u_j of rows s - M, s - M - 1, s - M - 2
-    double UP[2][Q];                            // u_{j-1} (p_0 at the start) of rows s - M, s - M - 1
-    double TQ[M][Q];                            // first-sweep terms of row a - 1 (z_{j+1})
-    double VQ[M + 1][Q];                        // v' of rows a .. a - M
-    double WQ[M][M + 1][Q];                     // w'_k of row a - k - e
-    double RQ[M + 1][Q], AU[M + 1][Q];          // r_{j+1} and A u_j of rows a .. a - M
+    // Register rings.  Row step s runs in phase PH = (s - s_begin) mod P, and the value of the
+    // row d steps behind s (faces: face s + 1 - d) sits in slot (PH - d) mod P of its ring.
+    // The march is unrolled by P, so every slot index is a constant and the rings rotate by
+    // renaming instead of moves.  Loads land kAhead steps ahead (d = -kAhead) and 1/D of the
+    // next row one step ahead, so P exceeds the deepest read (faces, d = 2M + 2) by more
+    // than kAhead.  Rows outside the grid or before the chunk's first row hold zeros and
+    // 1/D = 0, which zeroes every term they would feed.
+    constexpr int P = 2 * M + 5;
+    constexpr int kAhead = Q == 1 ? 2 : 1;      // one column per lane: loads two steps ahead
+    double R[P][Q];                             // r_j (S for the initial residual)
+    double KX[P][Q];                            // east-face conductances
+    double DI[P][Q];                            // 1/D
+    double F[P][Q];                             // axial faces
+    double UP[P][Q];                            // loaded with step s: u_{j-1} (p_0 at the start) of row s - M
+    double PP[P][Q];                            // loaded with step s: p of row s - M - 1 (odd iterations)
+    double MV1[P][Q], MV3[P][Q];                // loaded with step s: ASSOR I diagonal of rows s - 1, s - 3
+    double V[P][Q];                             // v of row s - d (z_j)
+    double W[M][P][Q];                          // W[k]: second-sweep term w_k of row s - k - d (z_j), k >= 1
+    double U[P][Q];                             // u_j of row s - M - d
+    double VQ[P][Q];                            // v' of row a - d (z_{j+1})
+    double WQ[M][P][Q];                         // w'_k of row a - k - d
+    double RQ[P][Q], AU[P][Q];                  // r_{j+1} and A u_j of row a - d
+    double T[M][Q], TQ[M][Q];                   // first-sweep terms of the previous row (z_j, z_{j+1})
     double ZQ[Q];                               // z_{j+1} of row b - 1
-    double MV1[Q], MV3[Q];                      // ASSOR I diagonal of rows s - 1, s - 3 (M = 1)
-    double pp2[Q];                              // p of row a (odd iterations)
-    // loads of the next two row steps (a: step s + 1, b: step s + 2)
-    double ar[Q], akx[Q], af[Q], aup[Q], app[Q], amv[Q], amv3[Q];
-    double br[Q], bkx[Q], bf[Q], bup[Q], bpp[Q], bmv[Q], bmv3[Q];
-    double kwn[Q], din[Q], yn[Q];               // S1 of row s + 1 (loads two steps ahead)
+    double kwc[Q], yc[Q];                       // S1 of the current row: west conductance, D^-1 r
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
-        for (int d = 0; d < M + 2; ++d) R[d][q] = 0.0;
+        for (int d = 0; d < P; ++d) {
+            R[d][q] = KX[d][q] = DI[d][q] = F[d][q] = UP[d][q] = PP[d][q] = MV1[d][q] = MV3[d][q] = 0.0;
+            V[d][q] = U[d][q] = VQ[d][q] = RQ[d][q] = AU[d][q] = 0.0;
 #pragma unroll
-        for (int d = 0; d <= LB; ++d) KX[d][q] = DI[d][q] = 0.0;
-#pragma unroll
-        for (int d = 0; d <= LB + 1; ++d) F[d][q] = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            T[k][q] = TQ[k][q] = 0.0;
-#pragma unroll
-            for (int e = 0; e <= M; ++e) W[k][e][q] = WQ[k][e][q] = 0.0;
+            for (int k = 0; k < M; ++k) W[k][d][q] = WQ[k][d][q] = 0.0;
         }
 #pragma unroll
-        for (int e = 0; e <= M; ++e) V[e][q] = VQ[e][q] = RQ[e][q] = AU[e][q] = 0.0;
-        U[0][q] = U[1][q] = U[2][q] = UP[0][q] = UP[1][q] = 0.0;
-        ZQ[q] = MV1[q] = MV3[q] = pp2[q] = 0.0;
-        kwn[q] = din[q] = yn[q] = 0.0;
+        for (int k = 0; k < M; ++k) T[k][q] = TQ[k][q] = 0.0;
+        ZQ[q] = kwc[q] = yc[q] = 0.0;
     }
-    // loads of row step s: r, kx of row s; face s + 1; u_prev of row s - M; p of row s - M - 1;
-    // the ASSOR I diagonal of rows s - 1 and s - 3
-    auto issue = [&](int s, double (&nr)[Q], double (&nkx)[Q], double (&nf)[Q], double (&nup)[Q],
-                     double (&npp)[Q], double (&nmv)[Q], double (&nmv3)[Q]) {
+    // u_{j-1} is read from the second iteration on (beta = 0 before), p_0 on a warm start
+    const bool need_up = INIT ? a.warm != 0 : has_prev;
+    // loads of row step s into ring slot SL: r, kx of row s; face s + 1; u_prev of row s - M;
+    // p of row s - M - 1; the ASSOR I diagonal of rows s - 1 and s - 3
+    auto issue = [&](int s, auto SLc) {
+        constexpr int sl = decltype(SLc)::value;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            nr[q] = nkx[q] = nf[q] = nup[q] = npp[q] = nmv[q] = nmv3[q] = 0.0;
+            R[sl][q] = KX[sl][q] = F[sl][q] = UP[sl][q] = PP[sl][q] = MV1[sl][q] = MV3[sl][q] = 0.0;
             const unsigned gc = (unsigned)gcol[q];
             if (s < nz) {
                 const unsigned g = (unsigned)s * nt + gc;
-                nr[q] = rin[g];
-                nkx[q] = kx[g];
+                R[sl][q] = rin[g];
+                KX[sl][q] = kx[g];
             }
-            if (s + 1 <= nz) nf[q] = kz[(unsigned)(s + 1) * nt + gc];
-            if (s - M >= 0 && s - M < nz && spmv) nup[q] = __builtin_nontemporal_load(&uin[(unsigned)(s - M) * nt + gc]);
+            if (s + 1 <= nz) F[sl][q] = kz[(unsigned)(s + 1) * nt + gc];
+            if (s - M >= 0 && s - M < nz && need_up)
+                UP[sl][q] = __builtin_nontemporal_load(&uin[(unsigned)(s - M) * nt + gc]);
             if (odd && ownc[q] && s - M - 1 >= j0 && s - M - 1 < j1)
-                npp[q] = __builtin_nontemporal_load(&pp[(unsigned)(s - M - 1) * nt + gc]);
+                PP[sl][q] = __builtin_nontemporal_load(&pp[(unsigned)(s - M - 1) * nt + gc]);
             if (pk == 1) {
-                if (s - 1 >= 0 && s - 1 < nz) nmv[q] = mv[(unsigned)(s - 1) * nt + gc];
-                if (s - 3 >= 0 && s - 3 < nz) nmv3[q] = mv[(unsigned)(s - 3) * nt + gc];
+                if (s - 1 >= 0 && s - 1 < nz) MV1[sl][q] = mv[(unsigned)(s - 1) * nt + gc];
+                if (s - 3 >= 0 && s - 3 < nz) MV3[sl][q] = mv[(unsigned)(s - 3) * nt + gc];
             }
         }
     };
-    // one column per lane: loads two row steps ahead; more columns per lane: one step ahead
-    // (the registers of a second stage would spill).  The loads of the first steps go out
-    // before the reduction of the scalars, whose latency they overlap; they do not depend on
-    // alpha or beta.
-    constexpr int kAhead = Q == 1 ? 2 : 1;
+    // The loads of the first steps go out before the reduction of the scalars, whose latency
+    // they overlap; they do not depend on alpha or beta.
     if (has_strip) {
-        // face s_begin, the south face of the first row (it reaches F[1] at the first shift)
+        // face s_begin, the south face of the first row (d = 1 in phase 0)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) F[0][q] = kz[(unsigned)s_begin * nt + gcol[q]];
-        issue(s_begin, ar, akx, af, aup, app, amv, amv3);
-        if constexpr (kAhead == 2) issue(s_begin + 1, br, bkx, bf, bup, bpp, bmv, bmv3);
+        for (int q = 0; q < Q; ++q) F[P - 1][q] = kz[(unsigned)s_begin * nt + gcol[q]];
+        issue(s_begin, std::integral_constant<int, 0>{});
+        if constexpr (kAhead == 2) issue(s_begin + 1, std::integral_constant<int, 1>{});
     }
 
     // ---- scalars (as in the ring kernel) ------------------------------------------------
@@ -371,304 +392,260 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     const double scale = om * (2.0 - om);
     double acc_rz = 0.0, acc_rr = 0.0, acc_zaz = 0.0, acc_zau = 0.0, acc_uau = 0.0, acc_ss = 0.0;
 
-    if (has_strip) {
-        for (int s = s_begin; s <= s_last; ++s) {
-            // ---- shift the rings by one row, take the loads of this step ------------------
+    // S1 of row r, whose loads sit in slot SL (face r + 1 there, face r one slot before): the
+    // west conductance, 1/D (0 outside the grid) and y = D^-1 r
+    auto s1 = [&](int r, auto SLc) {
+        constexpr int sl = decltype(SLc)::value, sf = (sl + P - 1) % P;
+        west_of<Q>(KX[sl], kwc);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double D = ((KX[sl][q] + kwc[q]) + F[sf][q]) + F[sl][q];
+            DI[sl][q] = r < nz ? 1.0 / D : 0.0;
+            yc[q] = R[sl][q] * DI[sl][q];
+        }
+    };
+    // One row step in phase PH.  WRAP: the strip holds ring column 0 or n_theta - 1, whose
+    // periodic couplings split between L and L^T (Eq 3.5, 3.6); elsewhere the west coupling
+    // is in L and the east one in L^T, with no per-column tests.
+    auto step = [&](int s, auto PHc, auto WRc) {
+        constexpr int PH = decltype(PHc)::value;
+        constexpr bool WRAP = decltype(WRc)::value;
+        auto S = [](int d) constexpr { return ((PH - d) % P + P) % P; };
+        if (s + kAhead <= s_last) issue(s + kAhead, std::integral_constant<int, S(-kAhead)>{});
+        if constexpr (kAhead == 1) s1(s, std::integral_constant<int, S(0)>{});
+        const int ra = s - M - 1;               // row of S4, S5
+        const int rb = s - LB;                  // row of z_{j+1} and the faces
+        constexpr int DA = M + 1;               // ring index of row a
+
+        // ---- S2, S3: z_j and u_j of row s - M (Eq 3.5, 3.6 with M Neumann terms) --------
+        double un[Q];
+        if constexpr (INIT) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) un[q] = UP[S(0)][q];   // p_0 (zero on a cold start)
+        } else if (pk == 2) {
+            // first sweep on row s: v = y + t_1 + ... + t_M, t_k = w D^-1 (west, south and
+            // east-wrap couplings of t_{k-1})
+            double t[Q], v[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) t[q] = v[q] = yc[q];
+#pragma unroll
+            for (int k = 1; k <= M; ++k) {
+                double tw[Q], te[Q];
+                west_of<Q>(t, tw);
+                if constexpr (WRAP) east_of<Q>(t, te);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    double lo;
+                    if constexpr (WRAP)
+                        lo = (gcol[q] > 0 ? kwc[q] * tw[q] : 0.0) + (gcol[q] == nt - 1 ? KX[S(0)][q] * te[q] : 0.0);
+                    else
+                        lo = kwc[q] * tw[q];
+                    lo += F[S(1)][q] * T[k - 1][q];
+                    const double nt_ = om * DI[S(0)][q] * lo;
+                    T[k - 1][q] = t[q];         // t_{k-1} of row s, the south neighbour next step
+                    t[q] = nt_;
+                    v[q] += nt_;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) V[S(0)][q] = v[q];
+            // second sweep: w_k of row s - k from w_{k-1} of rows s - k + 1 (north) and
+            // s - k (east, west wrap); z = w(2-w)(v + w_1 + ... + w_M) on row s - M
+            double wl[Q];                       // w_M of row s - M
+#pragma unroll
+            for (int k = 1; k <= M; ++k) {
+                double here[Q], he[Q], hw[Q], kwk[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) here[q] = k == 1 ? V[S(1)][q] : W[k - 1][S(1)][q];
+                east_of<Q>(here, he);
+                if constexpr (WRAP) {
+                    west_of<Q>(here, hw);
+                    west_of<Q>(KX[S(k)], kwk);
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    double hi = F[S(k)][q] * (k == 1 ? V[S(0)][q] : W[k - 1][S(0)][q]);
+                    if constexpr (WRAP) {
+                        if (gcol[q] < nt - 1) hi += KX[S(k)][q] * he[q];
+                        if (gcol[q] == 0) hi += kwk[q] * hw[q];
+                    } else {
+                        hi += KX[S(k)][q] * he[q];
+                    }
+                    const double w = om * DI[S(k)][q] * hi;
+                    if (k < M) W[k][S(0)][q] = w;
+                    else wl[q] = w;
+                }
+            }
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
+                double zs = V[S(M)][q];
 #pragma unroll
-                for (int d = M + 1; d > 0; --d) R[d][q] = R[d - 1][q];
-#pragma unroll
-                for (int d = LB; d > 0; --d) {
-                    KX[d][q] = KX[d - 1][q];
-                    DI[d][q] = DI[d - 1][q];
-                }
-#pragma unroll
-                for (int d = LB + 1; d > 0; --d) F[d][q] = F[d - 1][q];
-#pragma unroll
-                for (int e = M; e > 0; --e) {
-                    V[e][q] = V[e - 1][q];
-                    VQ[e][q] = VQ[e - 1][q];
-                    RQ[e][q] = RQ[e - 1][q];
-                    AU[e][q] = AU[e - 1][q];
-                }
-#pragma unroll
-                for (int k = 1; k < M; ++k) {
-#pragma unroll
-                    for (int e = M - k; e > 0; --e) {
-                        W[k][e][q] = W[k][e - 1][q];
-                        WQ[k][e][q] = WQ[k][e - 1][q];
-                    }
-                }
-                U[2][q] = U[1][q];
-                U[1][q] = U[0][q];
-                UP[1][q] = UP[0][q];
-                R[0][q] = ar[q];
-                KX[0][q] = akx[q];
-                F[0][q] = af[q];
-                UP[0][q] = aup[q];
-                pp2[q] = app[q];
-                MV1[q] = amv[q];
-                MV3[q] = amv3[q];
-                if constexpr (kAhead == 2) {
-                    ar[q] = br[q];
-                    akx[q] = bkx[q];
-                    af[q] = bf[q];
-                    aup[q] = bup[q];
-                    app[q] = bpp[q];
-                    amv[q] = bmv[q];
-                    amv3[q] = bmv3[q];
-                }
+                for (int k = 1; k < M; ++k) zs += W[k][S(M - k)][q];
+                zs += wl[q];
+                const double zj = scale * zs;
+                un[q] = zj + beta * UP[S(0)][q];        // u_{j-1} reads 0 while beta = 0
             }
-            if constexpr (kAhead == 2) {
-                if (s + 2 <= s_last) issue(s + 2, br, bkx, bf, bup, bpp, bmv, bmv3);
-            } else {
-                if (s + 1 <= s_last) issue(s + 1, ar, akx, af, aup, app, amv, amv3);
+        } else {
+            // Jacobi (Eq 2.8) or ASSOR I: z_j = diag r_j of row s - 1 (M = 1)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const double zj = (pk == 0 ? DI[S(1)][q] : MV1[S(0)][q]) * R[S(1)][q];
+                un[q] = zj + beta * UP[S(0)][q];
             }
-            const int ra = s - M - 1;               // row of S4, S5
-            const int rb = s - LB;                  // row of z_{j+1} and the faces
-            const bool row0 = s < nz;
-            const bool rowz = s - M >= 0 && s - M < nz;
-            const bool rowa = ra >= 0 && ra < nz;
-            const bool rowb = rb >= 0 && rb < nz;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) U[S(0)][q] = un[q];
 
-            // ---- S1: 1/D and y of row s (with loads two steps ahead, formed in the previous
-            // step, off the dependency chain of this one) ------------------------------------
-            double kw0[Q], y0[Q];
-            if (kAhead == 1 || s == s_begin) {
-                west_of<Q>(KX[0], kw0);
+        // ---- S4: A u_j, r_{j+1}, y' of row a (rows outside the grid: u = 0 there, so the
+        // Dirichlet faces of the end rows drop out of the products) ------------------------
+        double yq[Q], kwa[Q];
+        west_of<Q>(KX[S(DA)], kwa);
+        {
+            double ue[Q], uw[Q];
+            east_of<Q>(U[S(1)], ue);
+            west_of<Q>(U[S(1)], uw);
+            const bool own_a = ra >= j0 && ra < j1;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    y0[q] = 0.0;
-                    DI[0][q] = 0.0;
-                    if (row0) {
-                        const double D = ((KX[0][q] + kw0[q]) + F[1][q]) + F[0][q];
-                        DI[0][q] = 1.0 / D;
-                        y0[q] = R[0][q] * DI[0][q];
-                    }
+            for (int q = 0; q < Q; ++q) {
+                double r1v = R[S(DA)][q];
+                AU[S(0)][q] = 0.0;
+                if (spmv) {
+                    const double D = ((KX[S(DA)][q] + kwa[q]) + F[S(DA + 1)][q]) + F[S(DA)][q];
+                    double v = D * U[S(1)][q] - KX[S(DA)][q] * ue[q] - kwa[q] * uw[q];
+                    v -= F[S(DA + 1)][q] * U[S(2)][q];
+                    v -= F[S(DA)][q] * U[S(0)][q];
+                    AU[S(0)][q] = v;
+                    r1v -= alpha * v;
                 }
-            } else {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    kw0[q] = kwn[q];
-                    DI[0][q] = din[q];
-                    y0[q] = yn[q];
+                RQ[S(0)][q] = r1v;
+                yq[q] = r1v * DI[S(DA)][q];
+                if (ownc[q] && own_a) {
+                    const unsigned g = (unsigned)ra * nt + gcol[q];
+                    rout[g] = r1v;
+                    acc_rr += r1v * r1v;
+                    if (INIT) {
+                        acc_ss += R[S(DA)][q] * R[S(DA)][q];
+                        if (!a.warm) pp[g] = 0.0;
+                    } else {
+                        __builtin_nontemporal_store(U[S(1)][q], &uout[g]);
+                        acc_uau += U[S(1)][q] * AU[S(0)][q];
+                        if (odd) pp[g] = PP[S(0)][q] + (a_prev * UP[S(1)][q] + alpha * U[S(1)][q]);
+                    }
                 }
             }
-            // ---- S2, S3: z_j of row s - M (Eq 3.5, 3.6 with M Neumann terms) --------------
-            double un[Q];                           // u_j of row s - M
-            if (INIT) {
+        }
+        // ---- S5, S6: z_{j+1} of row b ---------------------------------------------------
+        double zq[Q];
+        if (pk == 2) {
+            double t[Q], v[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) un[q] = rowz ? UP[0][q] : 0.0;   // p_0 (zero on a cold start)
-            } else if (pk == 2) {
-                // first sweep on row s: v = y + t_1 + ... + t_M, t_k = w D^-1 (west, south and
-                // east-wrap couplings of t_{k-1})
-                double t[Q], v[Q];
+            for (int q = 0; q < Q; ++q) t[q] = v[q] = yq[q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) t[q] = v[q] = y0[q];
+            for (int k = 1; k <= M; ++k) {
+                double tw[Q], te[Q];
+                west_of<Q>(t, tw);
+                if constexpr (WRAP) east_of<Q>(t, te);
 #pragma unroll
-                for (int k = 1; k <= M; ++k) {
-                    double tw[Q], te[Q];
-                    west_of<Q>(t, tw);
-                    east_of<Q>(t, te);
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        double nt_ = 0.0;
-                        if (row0) {
-                            double lo = 0.0;
-                            if (gcol[q] > 0) lo += kw0[q] * tw[q];
-                            if (gcol[q] == nt - 1) lo += KX[0][q] * te[q];
-                            if (s > 0) lo += F[1][q] * T[k - 1][q];
-                            nt_ = om * DI[0][q] * lo;
-                        }
-                        T[k - 1][q] = t[q];         // t_{k-1} of row s, the south neighbour next step
-                        t[q] = nt_;
-                        v[q] += nt_;
-                    }
+                for (int q = 0; q < Q; ++q) {
+                    double lo;
+                    if constexpr (WRAP)
+                        lo = (gcol[q] > 0 ? kwa[q] * tw[q] : 0.0) + (gcol[q] == nt - 1 ? KX[S(DA)][q] * te[q] : 0.0);
+                    else
+                        lo = kwa[q] * tw[q];
+                    lo += F[S(DA + 1)][q] * TQ[k - 1][q];
+                    const double nt_ = om * DI[S(DA)][q] * lo;
+                    TQ[k - 1][q] = t[q];
+                    t[q] = nt_;
+                    v[q] += nt_;
                 }
+            }
 #pragma unroll
-                for (int q = 0; q < Q; ++q) V[0][q] = row0 ? v[q] : 0.0;
-                // second sweep: w_k of row s - k from w_{k-1} of rows s - k + 1 (north) and
-                // s - k (east, west wrap); z = w(2-w)(v + w_1 + ... + w_M) on row s - M
-                double wl[Q];                       // w_M of row s - M
+            for (int q = 0; q < Q; ++q) VQ[S(0)][q] = v[q];
+            double wl[Q];
 #pragma unroll
-                for (int k = 1; k <= M; ++k) {
-                    double here[Q], he[Q], hw[Q], kwk[Q];
+            for (int k = 1; k <= M; ++k) {
+                const int d = DA + k;           // ring index of row a - k
+                double here[Q], he[Q], hw[Q], kwk[Q];
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) here[q] = k == 1 ? V[1][q] : W[k - 1][1][q];
-                    east_of<Q>(here, he);
+                for (int q = 0; q < Q; ++q) here[q] = k == 1 ? VQ[S(1)][q] : WQ[k - 1][S(1)][q];
+                east_of<Q>(here, he);
+                if constexpr (WRAP) {
                     west_of<Q>(here, hw);
-                    west_of<Q>(KX[k], kwk);
-                    const bool rowk = s - k >= 0 && s - k < nz;
+                    west_of<Q>(KX[S(d)], kwk);
+                }
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        double hi = F[k][q] * (k == 1 ? V[0][q] : W[k - 1][0][q]);
-                        if (gcol[q] < nt - 1) hi += KX[k][q] * he[q];
+                for (int q = 0; q < Q; ++q) {
+                    double hi = F[S(d)][q] * (k == 1 ? VQ[S(0)][q] : WQ[k - 1][S(0)][q]);
+                    if constexpr (WRAP) {
+                        if (gcol[q] < nt - 1) hi += KX[S(d)][q] * he[q];
                         if (gcol[q] == 0) hi += kwk[q] * hw[q];
-                        const double w = rowk ? om * DI[k][q] * hi : 0.0;
-                        if (k < M) W[k][0][q] = w;
-                        else wl[q] = w;
+                    } else {
+                        hi += KX[S(d)][q] * he[q];
                     }
-                }
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    double zs = V[M][q];
-#pragma unroll
-                    for (int k = 1; k < M; ++k) zs += W[k][M - k][q];
-                    zs += wl[q];
-                    const double zj = scale * zs;
-                    un[q] = rowz ? (has_prev ? zj + beta * UP[0][q] : zj) : 0.0;
-                }
-            } else {
-                // Jacobi (Eq 2.8) or ASSOR I: z_j = diag r_j of row s - 1 (M = 1)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const double zj = (pk == 0 ? DI[1][q] : MV1[q]) * R[1][q];
-                    un[q] = rowz ? (has_prev ? zj + beta * UP[0][q] : zj) : 0.0;
+                    const double w = om * DI[S(d)][q] * hi;
+                    if (k < M) WQ[k][S(0)][q] = w;
+                    else wl[q] = w;
                 }
             }
 #pragma unroll
-            for (int q = 0; q < Q; ++q) U[0][q] = un[q];
-            // ---- S4: A u_j, r_{j+1}, y' of row a ---------------------------------------
-            constexpr int DA = M + 1;               // ring index of row a
-            double yq[Q], kwa[Q];
-            west_of<Q>(KX[DA], kwa);
-            {
-                double ue[Q], uw[Q];
-                east_of<Q>(U[1], ue);
-                west_of<Q>(U[1], uw);
+            for (int q = 0; q < Q; ++q) {
+                double zs = VQ[S(M)][q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    yq[q] = RQ[0][q] = AU[0][q] = 0.0;
-                    if (!rowa) continue;
-                    double r1v = R[DA][q];
-                    if (spmv) {
-                        const double D = ((KX[DA][q] + kwa[q]) + F[DA + 1][q]) + F[DA][q];
-                        double v = D * U[1][q] - KX[DA][q] * ue[q] - kwa[q] * uw[q];
-                        if (ra > 0) v -= F[DA + 1][q] * U[2][q];
-                        if (ra < nz - 1) v -= F[DA][q] * U[0][q];
-                        AU[0][q] = v;
-                        r1v -= alpha * v;
-                    }
-                    RQ[0][q] = r1v;
-                    yq[q] = r1v * DI[DA][q];
-                    if (ownc[q] && ra >= j0 && ra < j1) {
-                        const unsigned g = (unsigned)ra * nt + gcol[q];
-                        rout[g] = r1v;
-                        acc_rr += r1v * r1v;
-                        if (INIT) {
-                            acc_ss += R[DA][q] * R[DA][q];
-                            if (!a.warm) pp[g] = 0.0;
-                        } else {
-                            __builtin_nontemporal_store(U[1][q], &uout[g]);
-                            acc_uau += U[1][q] * AU[0][q];
-                            if (odd) pp[g] = pp2[q] + (a_prev * UP[1][q] + alpha * U[1][q]);
-                        }
-                    }
+                for (int k = 1; k < M; ++k) zs += WQ[k][S(M - k)][q];
+                zs += wl[q];
+                zq[q] = scale * zs;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) zq[q] = (pk == 0 ? DI[S(LB)][q] : MV3[S(0)][q]) * RQ[S(M)][q];
+        }
+        // ---- S7: partials and faces of z'^T A z' on row b -------------------------------
+        {
+            double ze[Q];
+            east_of<Q>(zq, ze);
+            const bool rowb = rb >= 0 && rb < nz;
+            const bool ownb = rowb && rb >= j0 && rb < j1;
+            const bool own_below = rb - 1 >= j0 && rb - 1 < j1;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (!ownc[q] || !rowb) continue;
+                if (ownb) {
+                    acc_rz += RQ[S(M)][q] * zq[q];
+                    acc_zau += zq[q] * AU[S(M)][q];
+                    const double d = zq[q] - ze[q];
+                    acc_zaz += KX[S(LB)][q] * d * d;
+                    if (rb == nz - 1) acc_zaz += F[S(LB)][q] * zq[q] * zq[q];
+                }
+                if (rb == 0) {
+                    if (ownb) acc_zaz += F[S(LB + 1)][q] * zq[q] * zq[q];
+                } else if (own_below) {
+                    const double d = ZQ[q] - zq[q];
+                    acc_zaz += F[S(LB + 1)][q] * d * d;
                 }
             }
-            // ---- S5, S6: z_{j+1} of row b ---------------------------------------------
-            double zq[Q];
-            if (pk == 2) {
-                double t[Q], v[Q];
+        }
 #pragma unroll
-                for (int q = 0; q < Q; ++q) t[q] = v[q] = yq[q];
-#pragma unroll
-                for (int k = 1; k <= M; ++k) {
-                    double tw[Q], te[Q];
-                    west_of<Q>(t, tw);
-                    east_of<Q>(t, te);
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        double nt_ = 0.0;
-                        if (rowa) {
-                            double lo = 0.0;
-                            if (gcol[q] > 0) lo += kwa[q] * tw[q];
-                            if (gcol[q] == nt - 1) lo += KX[DA][q] * te[q];
-                            if (ra > 0) lo += F[DA + 1][q] * TQ[k - 1][q];
-                            nt_ = om * DI[DA][q] * lo;
-                        }
-                        TQ[k - 1][q] = t[q];
-                        t[q] = nt_;
-                        v[q] += nt_;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < Q; ++q) VQ[0][q] = rowa ? v[q] : 0.0;
-                double wl[Q];
-#pragma unroll
-                for (int k = 1; k <= M; ++k) {
-                    constexpr int D0 = M + 1;
-                    const int d = D0 + k;               // ring index of row a - k
-                    double here[Q], he[Q], hw[Q], kwk[Q];
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) here[q] = k == 1 ? VQ[1][q] : WQ[k - 1][1][q];
-                    east_of<Q>(here, he);
-                    west_of<Q>(here, hw);
-                    west_of<Q>(KX[d], kwk);
-                    const bool rowk = ra - k >= 0 && ra - k < nz;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        double hi = F[d][q] * (k == 1 ? VQ[0][q] : WQ[k - 1][0][q]);
-                        if (gcol[q] < nt - 1) hi += KX[d][q] * he[q];
-                        if (gcol[q] == 0) hi += kwk[q] * hw[q];
-                        const double w = rowk ? om * DI[d][q] * hi : 0.0;
-                        if (k < M) WQ[k][0][q] = w;
-                        else wl[q] = w;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    double zs = VQ[M][q];
-#pragma unroll
-                    for (int k = 1; k < M; ++k) zs += WQ[k][M - k][q];
-                    zs += wl[q];
-                    zq[q] = rowb ? scale * zs : 0.0;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < Q; ++q) zq[q] = rowb ? (pk == 0 ? DI[LB][q] : MV3[q]) * RQ[M][q] : 0.0;
+        for (int q = 0; q < Q; ++q) ZQ[q] = zq[q];
+        // ---- S1 of row s + 1 from its loads (already in registers) ----------------------
+        if constexpr (kAhead == 2) s1(s + 1, std::integral_constant<int, S(-1)>{});
+    };
+
+    if (has_strip) {
+        if constexpr (kAhead == 2) s1(s_begin, std::integral_constant<int, 0>{});
+        // the strip's columns lie inside [1, n_theta - 2]: no wrap coupling in it
+        const int w0 = oc0 - strip_halo(M);
+        const bool wrap = !(w0 >= 1 && w0 + 64 * Q - 1 <= nt - 2);
+        int s = s_begin;
+        auto march = [&](auto WRc) {
+            auto one = [&](int sv, auto PHc) { step(sv, PHc, WRc); };
+            while (strip_steps<0, P>(one, s, s_last)) {
             }
-            // ---- S7: partials and faces of z'^T A z' on row b ---------------------------
-            {
-                double ze[Q];
-                east_of<Q>(zq, ze);
-                const bool ownb = rowb && rb >= j0 && rb < j1;
-                const bool own_below = rb - 1 >= j0 && rb - 1 < j1;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    if (!ownc[q] || !rowb) continue;
-                    if (ownb) {
-                        acc_rz += RQ[M][q] * zq[q];
-                        acc_zau += zq[q] * AU[M][q];
-                        const double d = zq[q] - ze[q];
-                        acc_zaz += KX[LB][q] * d * d;
-                        if (rb == nz - 1) acc_zaz += F[LB][q] * zq[q] * zq[q];
-                    }
-                    if (rb == 0) {
-                        if (ownb) acc_zaz += F[LB + 1][q] * zq[q] * zq[q];
-                    } else if (own_below) {
-                        const double d = ZQ[q] - zq[q];
-                        acc_zaz += F[LB + 1][q] * d * d;
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < Q; ++q) ZQ[q] = zq[q];
-            // ---- S1 of row s + 1 from its loads (already in registers) -------------------
-            if constexpr (kAhead == 2) {
-                west_of<Q>(akx, kwn);
-                const bool rown = s + 1 < nz;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    din[q] = yn[q] = 0.0;
-                    if (rown) {
-                        const double D = ((akx[q] + kwn[q]) + F[0][q]) + af[q];
-                        din[q] = 1.0 / D;
-                        yn[q] = ar[q] * din[q];
-                    }
-                }
-            }
+        };
+        if constexpr (M == 1) {
+            if (!wrap) march(std::false_type{});
+            else march(std::true_type{});
+        } else {
+            march(std::true_type{});
         }
     }
     double v6[6] = {acc_rz, acc_rr, acc_zaz, acc_zau, acc_uau, acc_ss};

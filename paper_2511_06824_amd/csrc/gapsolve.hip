@@ -180,8 +180,10 @@ std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
 }
 
 // ---- strip kernel (gap_pcgw.hpp): shape = (kStripThreads, Q columns per lane) ----------
-constexpr int kStripMaxQ = 2;
-constexpr int kStripDefaultQ = 2;
+// One column per lane only: with two, the unrolled row march needs more than the 256 VGPRs a
+// lane has and spills (three times slower).
+constexpr int kStripMaxQ = 1;
+constexpr int kStripDefaultQ = 1;
 constexpr int kMinStripRows = 16;      // a row chunk recomputes 7 halo rows
 
 bool strip_q_known(int Q) { return Q >= 1 && Q <= kStripMaxQ; }
@@ -273,7 +275,6 @@ hipError_t strip_prepare(int Q, int M, int* occupancy)
 {
     switch (Q) {
     case 1: return strip_prepare_t<1>(M, occupancy);
-    case 2: return strip_prepare_t<2>(M, occupancy);
     default: return hipErrorInvalidValue;
     }
 }
@@ -286,7 +287,6 @@ hipError_t launch_strip(int Q, int pk, int M, bool init, const PcgDev* reqs, con
     const void* fn = nullptr;
     switch (Q) {
     case 1: fn = strip_fn<1>(init, pk, M); break;
-    case 2: fn = strip_fn<2>(init, pk, M); break;
     default: return hipErrorInvalidValue;
     }
     if (!fn) return hipErrorInvalidValue;
@@ -408,6 +408,8 @@ struct gap_grid_s {
     // device memory
     double *trig = nullptr;                                  // cos_c, sin_c, cos_e, sin_e
     double *tex = nullptr;                                   // centres, east faces, axial faces
+    double *dim_dev = nullptr, *dim_host = nullptr;          // dimple parameters for set_gap_dimples (host: pinned)
+    int dim_cap = 0;                                         // dimples they hold
     double *kx = nullptr, *kz = nullptr, *minv = nullptr;
     double *S = nullptr, *r0 = nullptr, *r1 = nullptr, *u0 = nullptr, *u1 = nullptr, *z = nullptr;
     double *z1 = nullptr;                                    // second z of the one-launch iteration
@@ -494,6 +496,8 @@ void release(gap_grid_t g)
     if (g->req_host) (void)hipHostFree(g->req_host);
     if (g->sc) (void)hipFree(g->sc);
     if (g->sc_host) (void)hipHostFree(g->sc_host);
+    if (g->dim_dev) (void)hipFree(g->dim_dev);
+    if (g->dim_host) (void)hipHostFree(g->dim_host);
     delete g;
 }
 
@@ -941,13 +945,10 @@ gap_status gap_default_opts(gap_solver_opts* o)
     return GAP_OK;
 }
 
-gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int32_t max_cond, gap_grid_t* out)
+namespace {
+
+gap_status check_dimples(const gap_geom* geom, const gap_dimples* dimples)
 {
-    if (!out) return fail(GAP_EINVAL, "out is NULL");
-    *out = nullptr;
-    gap_status st = validate_geom(geom);
-    if (st != GAP_OK) return st;
-    if (max_cond != 1 && max_cond != GAP_MAX_COND) return fail(GAP_EINVAL, "max_cond must be 1 or 9");
     const int count = dimples ? dimples->count : 0;
     if (count < 0) return fail(GAP_EINVAL, "dimple count < 0");
     if (count > 0) {
@@ -965,6 +966,20 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
                 return fail(GAP_EINVAL, "dimple %d: |theta| <= 1e3, -L <= z <= 2L, radius <= min(L, pi R)", k);
         }
     }
+    return GAP_OK;
+}
+
+}  // namespace
+
+gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int32_t max_cond, gap_grid_t* out)
+{
+    if (!out) return fail(GAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    gap_status st = validate_geom(geom);
+    if (st != GAP_OK) return st;
+    if (max_cond != 1 && max_cond != GAP_MAX_COND) return fail(GAP_EINVAL, "max_cond must be 1 or 9");
+    st = check_dimples(geom, dimples);
+    if (st != GAP_OK) return st;
 
     gap_grid_t g = new gap_grid_s;
     g->geom = *geom;
@@ -1055,32 +1070,27 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         trig[2 * nt + i] = std::cos(te);
         trig[3 * nt + i] = std::sin(te);
     }
-    hipError_t e = hipMemcpy(g->trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(g->tex, 0, (2 * n + (g->nz + 1) * nt) * sizeof(double));
-    if (e == hipSuccess) e = hipMemset(g->sc, 0, sizeof(PcgScalars));
-    if (e == hipSuccess) e = hipMemset(g->pcg_part, 0, 15 * g->pcg_part_stride * sizeof(double));
+    // initialisation on the handle's own stream: no device-wide synchronization, so a handle
+    // may be created beside the work and graph captures of other threads
+    hipError_t e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        g->cap_stream = nullptr;
+        release(g);
+        return fail(GAP_EDEVICE, "creating the handle's stream: %s", hipGetErrorString(e));
+    }
+    hipStream_t s0 = g->cap_stream;
+    e = hipMemcpyAsync(g->trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice, s0);
+    if (e == hipSuccess) e = hipMemsetAsync(g->sc, 0, sizeof(PcgScalars), s0);
+    if (e == hipSuccess) e = hipMemsetAsync(g->pcg_part, 0, 15 * g->pcg_part_stride * sizeof(double), s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(s0);
     if (e != hipSuccess) {
         release(g);
         return fail(GAP_EDEVICE, "initialising tables: %s", hipGetErrorString(e));
     }
-    if (count > 0) {
-        double* dm = nullptr;
-        if (dmalloc(&dm, 4 * (size_t)count) != GAP_OK) { release(g); return GAP_ENOMEM; }
-        const double* src[4] = {dimples->theta, dimples->z, dimples->radius, dimples->depth};
-        for (int k = 0; k < 4 && e == hipSuccess; ++k)
-            e = hipMemcpy(dm + k * count, src[k], count * sizeof(double), hipMemcpyHostToDevice);
-        if (e == hipSuccess) {
-            const TablesDev t = g->tables();
-            hipLaunchKernelGGL(k_texture, dim3(count, 3), dim3(GAP_BLOCK), 0, 0, d, count, dm, dm + count,
-                               dm + 2 * count, dm + 3 * count, (double*)t.tex_c, (double*)t.tex_e, (double*)t.tex_f);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        (void)hipFree(dm);
-        if (e != hipSuccess) {
-            release(g);
-            return fail(GAP_EDEVICE, "texture evaluation: %s", hipGetErrorString(e));
-        }
+    st = set_gap_dimples(g, dimples, s0);
+    if (st != GAP_OK) {
+        release(g);
+        return st;
     }
     *out = g;
     return GAP_OK;
@@ -1128,6 +1138,49 @@ gap_status destroy_gap_grid(gap_grid_t g)
     GAP_NOT_IN_BATCH(g, "destroy_gap_grid");
     (void)hipDeviceSynchronize();
     release(g);
+    return GAP_OK;
+}
+
+gap_status set_gap_dimples(gap_grid_t g, const gap_dimples* dimples, void* stream)
+{
+    if (!g) return fail(GAP_EINVAL, "grid is NULL");
+    GAP_NOT_IN_BATCH(g, "set_gap_dimples");
+    gap_status st = check_dimples(&g->geom, dimples);
+    if (st != GAP_OK) return st;
+    const int count = dimples ? dimples->count : 0;
+    hipStream_t s = (hipStream_t)stream;
+    // the parameter buffers grow to a multiple of 256 dimples (once, in the usual case)
+    if (count > g->dim_cap) {
+        HIPCHK(hipStreamSynchronize(s));
+        if (g->dim_dev) (void)hipFree(g->dim_dev);
+        if (g->dim_host) (void)hipHostFree(g->dim_host);
+        g->dim_dev = g->dim_host = nullptr;
+        g->dim_cap = 0;
+        const int cap = (count + 255) / 256 * 256;
+        if (hipMalloc((void**)&g->dim_dev, 4 * (size_t)cap * sizeof(double)) != hipSuccess) {
+            g->dim_dev = nullptr;
+            return fail(GAP_ENOMEM, "hipMalloc of the dimple parameters failed");
+        }
+        if (hipHostMalloc((void**)&g->dim_host, 4 * (size_t)cap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            g->dim_host = nullptr;
+            return fail(GAP_ENOMEM, "hipHostMalloc of the dimple parameters failed");
+        }
+        g->dim_cap = cap;
+    }
+    g->assembled = false;
+    const size_t nt = g->nt, n = g->n;
+    HIPCHK(hipMemsetAsync(g->tex, 0, (2 * n + (g->nz + 1) * nt) * sizeof(double), s));
+    if (count > 0) {
+        const double* src[4] = {dimples->theta, dimples->z, dimples->radius, dimples->depth};
+        for (int k = 0; k < 4; ++k) std::memcpy(g->dim_host + (size_t)k * count, src[k], count * sizeof(double));
+        double* dm = g->dim_dev;
+        HIPCHK(hipMemcpyAsync(dm, g->dim_host, 4 * (size_t)count * sizeof(double), hipMemcpyHostToDevice, s));
+        const TablesDev t = g->tables();
+        hipLaunchKernelGGL(k_texture, dim3(count, 3), dim3(GAP_BLOCK), 0, s, g->gd, count, dm, dm + count,
+                           dm + 2 * count, dm + 3 * count, (double*)t.tex_c, (double*)t.tex_e, (double*)t.tex_f);
+        HIPLAUNCHCHK("k_texture");
+    }
+    HIPCHK(hipStreamSynchronize(s));           // the pinned parameters may be overwritten after this
     return GAP_OK;
 }
 
@@ -2016,9 +2069,13 @@ void batch_release(gap_batch_t b)
     delete b;
 }
 
+// Grows a schedule table to hold `need` entries, at least doubling it, so that a batch whose
+// membership keeps changing reallocates (and synchronizes the device in hipFree) only a few
+// times.
 gap_status ensure_ints(int** p, size_t* cap, size_t need)
 {
     if (need <= *cap) return GAP_OK;
+    need = std::max(need, std::max<size_t>(2 * *cap, 4096));
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;

@@ -111,6 +111,7 @@ _SIGNATURES = {
                         ctypes.POINTER(_P)],
     "create_gap_grid_field": [ctypes.POINTER(gap_geom), _P, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)],
     "destroy_gap_grid": [_P],
+    "set_gap_dimples": [_P, ctypes.POINTER(gap_dimples), _P],
     "assemble_joint_system": [_P, _D8, _D8, _D8, ctypes.c_int32, _P],
     "solve_joint_pcg": [_P, ctypes.POINTER(gap_solver_opts), _P, ctypes.POINTER(gap_solve_info), _P],
     "integrate_force_moment": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P],
@@ -230,6 +231,10 @@ def create_gap_grid_field(geom, tex_c_ptr, tex_e_ptr, tex_f_ptr, max_cond):
 
 def destroy_gap_grid(handle):
     _check(load().destroy_gap_grid(handle))
+
+
+def set_gap_dimples(handle, dimples, stream=None):
+    _check(load().set_gap_dimples(handle, ctypes.byref(dimples) if dimples is not None else None, _stream(stream)))
 
 
 def assemble_joint_system(handle, e, edot, delta, n_cond, stream=None):

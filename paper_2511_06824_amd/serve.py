@@ -2,10 +2,13 @@
 
 Requests (one joint 9-condition solve each, any grid size) arrive over time.  A request is
 admitted as soon as its device footprint fits the HBM budget and a batch slot is free; it is
-then assembled and joins the running batch, whose every step advances all active requests
+then given a handle (a finished request's handle of the same grid and geometry, re-textured
+by set_gap_dimples, or a new one), assembled and joins the running batch, whose every step advances all active requests
 by a block of PCG iterations with one launch per kernel per iteration (gap_batch_* in the
-HIP library).  Finished requests are integrated (forces, FD Jacobian), their memory is
-released and the next queued requests are admitted.  Latency = completion - arrival.
+HIP library).  Finished requests are integrated (forces, FD Jacobian), their budget is
+released (their handle waits for the next request of its grid) and the next queued requests
+are admitted.  Reusing handles keeps device allocation, and the device-wide synchronization
+that freeing memory implies, out of the serving loop.  Latency = completion - arrival.
 
 Scheduling inside the batch: without a work cap every admitted request advances in every
 step (processor sharing).  With ``work_cap`` (condition-DOFs per step), each step advances
@@ -106,15 +109,55 @@ class WallClock:
             time.sleep(dt)
 
 
+class HandlePool:
+    """Idle JointGapSolver handles by grid and geometry, reused for later requests of the same
+    grid (re-textured with set_gap_dimples); at most `per_key` idle handles are kept per key."""
+
+    def __init__(self, device, per_key=4):
+        from .solver import JointGapSolver
+        self.Solver, self.device, self.per_key = JointGapSolver, device, int(per_key)
+        self.idle = {}
+        self.created = 0
+        self.reused = 0
+
+    def get(self, case):
+        key = self.Solver.geometry_key(case)
+        free = self.idle.get(key)
+        if free:
+            s = free.pop()
+            s.set_dimples(self.Solver.case_dimples(case))
+            self.reused += 1
+        else:
+            s = self.Solver.from_case(case, max_cond=9, device=self.device)
+            self.created += 1
+        s.pool_key = key
+        return s
+
+    def put(self, s):
+        free = self.idle.setdefault(s.pool_key, [])
+        if len(free) < self.per_key:
+            free.append(s)
+        else:
+            s.close()
+
+    def close(self):
+        for free in self.idle.values():
+            for s in free:
+                s.close()
+        self.idle.clear()
+
+
 class BatchBackend:
-    """Drives the HIP library: one JointGapSolver handle per request, one gap_batch.
+    """Drives the HIP library: one JointGapSolver handle per request (from a HandlePool), one
+    gap_batch.
 
     ``stream``: the stream every call of this backend runs on (default: the current stream of
     the thread that creates it); ``wg_per_cu``: the strip kernel's chunking target for the
-    requests of this batch (0: the kernel's occupancy)."""
+    requests of this batch (0: the kernel's occupancy); ``iteration``: the launch scheme of its
+    requests (default: the library's, strips)."""
 
     def __init__(self, device="cuda:0", iterations_per_step=32, use_graph=True, keep_pressure=False,
-                 stream=None, wg_per_cu=0):
+                 stream=None, wg_per_cu=0, iteration=None):
         import torch
         from . import gapsolve as G
         from .solver import JointGapSolver
@@ -124,6 +167,8 @@ class BatchBackend:
         self.iters = int(iterations_per_step)
         self.use_graph = use_graph
         self.keep_pressure = keep_pressure
+        self.kind = {} if iteration is None else {"iteration": int(iteration)}
+        self.pool = HandlePool(self.device)
         self.batch = G.gap_batch_create()
         G.gap_batch_set_target(self.batch, wg_per_cu)
         self.live = {}
@@ -151,9 +196,9 @@ class BatchBackend:
     def start(self, req):
         case = req.case
         with self.torch.cuda.stream(self.stream):
-            s = self.Solver.from_case(case, max_cond=9, device=self.device)
+            s = self.pool.get(case)
             s.assemble(case.e, case.edot, case.delta, 9)
-            opts = s.options(omega=case.omega, eps=case.eps)
+            opts = s.options(omega=case.omega, eps=case.eps, **self.kind)
             bid = self.G.gap_batch_add(self.batch, s.handle, opts, s.p.data_ptr(), self.stream.cuda_stream)
         self.live[bid] = (s, req, opts)
 
@@ -171,7 +216,7 @@ class BatchBackend:
                 req.J = s.jacobian_fd().cpu().numpy().copy()
                 if self.keep_pressure:
                     req.p = s.pressure().cpu().numpy().copy()
-                s.close()
+                self.pool.put(s)
                 out.append(req)
         return out
 
@@ -184,6 +229,7 @@ class BatchBackend:
         for s, _, _ in self.live.values():
             s.close()
         self.live.clear()
+        self.pool.close()
 
 
 class GapServer:
@@ -304,23 +350,27 @@ def latency_stats(done):
     return out
 
 
-def run_fifo(requests, device="cuda:0", clock=None):
-    """Baseline: the same requests solved one at a time in arrival order (plain handles,
-    no batching)."""
+def run_fifo(requests, device="cuda:0", clock=None, pool=None):
+    """Baseline: the same requests solved one at a time in arrival order, each a joint solve
+    of its own (no batching), on handles reused through a HandlePool as the batched server
+    reuses them (pass one to keep it across calls)."""
     import torch
-    from .solver import JointGapSolver
     clock = clock or WallClock()
+    own = pool is None
+    pool = pool or HandlePool(torch.device(device))
     done = []
     for r in sorted(requests, key=lambda q: q.arrival):
         clock.sleep_until(r.arrival)
         r.admitted = clock.now()
-        s = JointGapSolver.from_case(r.case, max_cond=9, device=torch.device(device))
+        s = pool.get(r.case)
         s.assemble(r.case.e, r.case.edot, r.case.delta, 9)
         _, info = s.solve(omega=r.case.omega, eps=r.case.eps)
         r.iterations = info.iterations
         r.F = s.integrate().cpu().numpy().copy()
         r.J = s.jacobian_fd().cpu().numpy().copy()
-        s.close()
+        pool.put(s)
         r.finished = clock.now()
         done.append(r)
+    if own:
+        pool.close()
     return done

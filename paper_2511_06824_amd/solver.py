@@ -67,6 +67,25 @@ class JointGapSolver:
         return cls(case.R, case.c, case.L, case.mu, case.U, case.V, case.p_in, case.p_out,
                    case.n_theta, case.n_axial, dimples=dimples, max_cond=max_cond, device=device)
 
+    @staticmethod
+    def geometry_key(case):
+        """What a handle is built for, apart from its texture: grid and geometry."""
+        return (case.n_theta, case.n_axial, case.R, case.c, case.L, case.mu, case.U, case.V, case.p_in, case.p_out)
+
+    def set_dimples(self, dimples=None):
+        """Replace the texture by a dimple list (theta, z, radius, depth), or make the gap smooth
+        (None): reuses this handle for another request of the same geometry without allocating
+        device memory.  The next solve needs a new assemble."""
+        dm = G.make_dimples(*dimples) if dimples is not None and len(dimples[0]) > 0 else None
+        G.set_gap_dimples(self.handle, dm, _stream(self.device))
+        self.n_cond = 0
+
+    @staticmethod
+    def case_dimples(case):
+        if not case.n_dimples:
+            return None
+        return (case.dimple_theta, case.dimple_z, case.dimple_radius, case.dimple_depth)
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             G.destroy_gap_grid(self.handle)

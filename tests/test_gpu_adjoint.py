@@ -90,6 +90,44 @@ def test_joint_base_and_adjoint_solve(case):
     s1.close()
 
 
+@pytest.mark.parametrize("iteration", [G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_STRIPS],
+                         ids=["one_launch", "strips"])
+def test_adjoint_tolerance_applies_to_the_adjoint_systems_only(iteration):
+    """eps_adjoint stops the adjoint systems at their own tolerance: the base system of the
+    joint solve keeps its recurrence bitwise (per-condition scalars), its residual meets eps,
+    every adjoint residual meets eps_adjoint, and the Jacobian stays within 1e-6 per block of
+    the exact complex-step derivative; jacobian_adjoint likewise."""
+    case = synth.textured_case(128, 64, 2)
+    log(f"case: {case.label}, adjoint tolerance 1e-7 against 1e-13, iteration kind {iteration}")
+    gap, tex = gap_of(case), texture_of(case)
+    ref = oracle.jacobian_complex_step(gap, case.e, case.edot, tex)
+    s = JointGapSolver.from_case(case, max_cond=9)
+    s.assemble(case.e, case.edot, None, 1)
+    with pytest.raises(G.GapError) as ei:
+        s.solve_with_adjoint(s.options(omega=case.omega, eps=1e-13, eps_adjoint=-1.0, iteration=iteration))
+    assert ei.value.status == G.GAP_EINVAL
+    tight = s.options(omega=case.omega, eps=1e-13, iteration=iteration)
+    loose = s.options(omega=case.omega, eps=1e-13, eps_adjoint=1e-7, iteration=iteration)
+    p_t, J_t, info_t = s.solve_with_adjoint(tight)
+    p_t = p_t.clone()
+    p_l, J_l, info_l = s.solve_with_adjoint(loose)
+    log(f"  iterations {info_t.iterations} -> {info_l.iterations}; adjoint residuals "
+        f"{[round(info_l.rel_residual_cond[k], 12) for k in range(1, 5)]}")
+    assert torch.equal(p_t, p_l)
+    assert info_l.rel_residual_cond[0] <= 1e-13
+    assert all(info_l.rel_residual_cond[k] <= 1e-7 for k in range(1, 5))
+    assert info_l.iterations <= info_t.iterations
+    assert block_err(J_l.cpu().numpy(), ref) <= 1e-6
+    s.assemble(case.e, case.edot, None, 1)
+    s.solve(tight)
+    J_a, info_a = s.jacobian_adjoint(loose)
+    _, info_at = s.jacobian_adjoint(tight)
+    assert all(info_a.rel_residual_cond[k] <= 1e-7 for k in range(4))
+    assert info_a.iterations < info_at.iterations
+    assert block_err(J_a.cpu().numpy(), ref) <= 1e-6
+    s.close()
+
+
 def test_vjp_equals_weighted_full_jacobian():
     case = synth.textured_case(96, 48, 4)
     log(f"case: {case.label}, vjp")

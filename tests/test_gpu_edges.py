@@ -127,7 +127,7 @@ def test_ring_wider_than_2048_cells_needs_strips_and_matches_the_exact_solution(
             s.solve(omega=1.6, eps=1e-10, iteration=it)
         assert ei.value.status == G.GAP_EINVAL and "STRIPS" in str(ei.value)
     cfg = s.pcg_config
-    assert cfg["strips_w"] == 20
+    assert cfg["cols_per_lane_w"] == 1 and cfg["strips_w"] == -(-2304 // (64 - 12))   # 52 owned columns each
     p, info = s.solve(omega=1.6, eps=1e-13, iteration=G.GAP_ITERATION_STRIPS)
     F = s.integrate().cpu().numpy()
     p = p.reshape(9, -1).cpu().numpy()
