@@ -56,7 +56,8 @@ def test_recorded_traffic_needs_the_current_kernel_sources(tmp_path, monkeypatch
 
 def test_committed_traffic_summary_matches_the_kernel_sources():
     # the committed counter summary was taken with the kernels in the tree
-    assert bench.recorded_traffic("k_pcg_f") is not None
+    for k in ("k_pcg_w", "k_pcg_f", "k_pcg_a", "k_pcg_b"):
+        assert bench.recorded_traffic(k) is not None, k
 
 
 @pytest.mark.parametrize("argv", [["--gpus", "2"], ["--timing-period", "0"]])
