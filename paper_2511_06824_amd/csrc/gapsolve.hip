@@ -947,6 +947,31 @@ gap_status gap_default_opts(gap_solver_opts* o)
 
 namespace {
 
+// One non-blocking stream per device for the initialisation copies of new handles (created
+// on first use, kept until the process ends): a handle gets no stream of its own until it
+// captures a graph, so that creating many handles does not multiply the streams that share
+// the hardware queues.
+std::mutex g_init_mu;
+hipStream_t g_init_stream[64] = {};
+
+hipError_t init_stream(hipStream_t* out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_init_mu);
+    if (!g_init_stream[dev]) {
+        e = hipStreamCreateWithFlags(&g_init_stream[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g_init_stream[dev] = nullptr;
+            return e;
+        }
+    }
+    *out = g_init_stream[dev];
+    return hipSuccess;
+}
+
 gap_status check_dimples(const gap_geom* geom, const gap_dimples* dimples)
 {
     const int count = dimples ? dimples->count : 0;
@@ -1070,15 +1095,16 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         trig[2 * nt + i] = std::cos(te);
         trig[3 * nt + i] = std::sin(te);
     }
-    // initialisation on the handle's own stream: no device-wide synchronization, so a handle
-    // may be created beside the work and graph captures of other threads
-    hipError_t e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+    // initialisation on a stream of its own (no device-wide synchronization, so a handle may
+    // be created beside the work and graph captures of other threads); concurrent creations
+    // share it, serialized
+    hipStream_t s0 = nullptr;
+    hipError_t e = init_stream(&s0);
     if (e != hipSuccess) {
-        g->cap_stream = nullptr;
         release(g);
-        return fail(GAP_EDEVICE, "creating the handle's stream: %s", hipGetErrorString(e));
+        return fail(GAP_EDEVICE, "creating the initialisation stream: %s", hipGetErrorString(e));
     }
-    hipStream_t s0 = g->cap_stream;
+    std::lock_guard<std::mutex> init_lock(g_init_mu);
     e = hipMemcpyAsync(g->trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice, s0);
     if (e == hipSuccess) e = hipMemsetAsync(g->sc, 0, sizeof(PcgScalars), s0);
     if (e == hipSuccess) e = hipMemsetAsync(g->pcg_part, 0, 15 * g->pcg_part_stride * sizeof(double), s0);

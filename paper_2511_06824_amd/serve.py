@@ -298,16 +298,18 @@ class LaneServer:
     (batch, stream) driven by its own thread.  Requests of work >= ``bulk_work`` (condition-
     DOFs per iteration) go to the bulk lane, which runs them in arrival order, advancing
     together only those that fit ``bulk_cap`` (default: bulk_work); the others go to the fast
-    lane, where every admitted request advances in every step."""
+    lane, where every admitted request advances in every step, or, with ``fast_cap``, the
+    smallest ones first while their work fits the cap."""
 
-    def __init__(self, bulk, fast, budget_bytes, bulk_work, clock=None, bulk_cap=None):
+    def __init__(self, bulk, fast, budget_bytes, bulk_work, clock=None, bulk_cap=None, fast_cap=None):
         self.admission = AdmissionController(budget_bytes)
         self.clock = clock or WallClock()
         self.bulk_work = int(bulk_work)
         self.lanes = {
             "bulk": GapServer(bulk, budget_bytes, clock=self.clock, work_cap=bulk_cap or self.bulk_work,
                               order="oldest", admission=self.admission),
-            "fast": GapServer(fast, budget_bytes, clock=self.clock, admission=self.admission),
+            "fast": GapServer(fast, budget_bytes, clock=self.clock, work_cap=fast_cap, order="smallest",
+                              admission=self.admission),
         }
 
     def lane_of(self, req):
