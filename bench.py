@@ -197,16 +197,19 @@ def _round(d):
 SERVE_COUNTS = {0.5: 48, 0.8: 96, 1.0: 96, 1.2: 48}   # requests per load
 SERVE_BULK = (2048, 1024)        # requests of this many cells or more run in the bulk lane
 SERVE_TARGETS = (2, 1)           # strip-kernel workgroups per CU: bulk lane, fast lane
+SERVE_FAST_CAP = 4 * 9 * 512 * 256   # fast lane: smallest first while the work fits four 512x256 systems
 
 
-def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=48, targets=SERVE_TARGETS):
+def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=48, targets=SERVE_TARGETS,
+                fast_cap=SERVE_FAST_CAP):
     """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
     128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server runs two
     lanes over one HBM budget: 2048x1024 requests in a bulk batch, one after another in arrival
     order (its launches chunked to `targets[0]` workgroups per CU), the smaller ones in a fast
-    batch whose every step advances all of them, on a second stream and host thread, beside
-    the bulk launches.  Its capacity is measured first, with `capacity_count` requests queued
-    at t = 0; then arrivals run at each load x that capacity (counts[load] requests), against
+    batch on a second stream and host thread, beside the bulk launches, smallest first while
+    their work fits `fast_cap` (a 1024x512 request waits while smaller ones are active).  Its
+    capacity is measured first, with `capacity_count` requests queued at t = 0; then arrivals
+    run at each load x that capacity (counts[load] requests), against
     the same requests solved one at a time in arrival order as joint solves, and (at load 0.8)
     as plain one-condition-at-a-time solves."""
     import numpy as np
@@ -230,7 +233,7 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     fifo_pool = HandlePool(dev)
 
     def batched(reqs):
-        return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work).run(reqs)
+        return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work, fast_cap=fast_cap).run(reqs)
 
     def fifo(reqs):
         return run_fifo(reqs, pool=fifo_pool)
@@ -278,7 +281,7 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     return {"capacity_requests": capacity_count, "capacity_batched_per_s": round(capacity, 3), "handles": handles,
             "capacity_one_at_a_time_joint_per_s": round(fifo_capacity, 3),
             "lanes": {"bulk_cells_min": list(SERVE_BULK), "wg_per_cu_bulk": targets[0], "wg_per_cu_fast": targets[1],
-                      "iterations_per_step": 32},
+                      "fast_cap_dofs": fast_cap, "iterations_per_step": 32},
             "hbm_budget_bytes": budget, "runs": runs}
 
 

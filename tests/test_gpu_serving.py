@@ -324,7 +324,7 @@ def test_a_grid_in_a_batch_is_lent_to_it():
     opts = s.options(omega=c.omega, eps=c.eps)
     bid = G.gap_batch_add(b, s.handle, opts, s.p.data_ptr(), stream)
     for call in (lambda: s.solve(opts), lambda: s.assemble(c.e, c.edot, c.delta, 9), lambda: s.tune(opts),
-                 lambda: s.set_pcg_config(), lambda: G.destroy_gap_grid(s.handle)):
+                 lambda: s.set_pcg_config(), lambda: G.destroy_gap_grid(s.handle), lambda: s.set_dimples(None)):
         with pytest.raises(G.GapError) as ei:
             call()
         assert ei.value.status == G.GAP_ESTATE
@@ -339,6 +339,40 @@ def test_a_grid_in_a_batch_is_lent_to_it():
     s.close()
     G.gap_batch_destroy(b)
     G.gap_batch_destroy(b2)
+
+
+def test_a_re_textured_handle_solves_as_a_new_one():
+    """set_gap_dimples: a handle re-textured to another dimple list (and back to smooth) gives
+    bitwise the pressure, forces and Jacobian of a handle created for that texture; bad
+    dimples are refused and leave the handle usable."""
+    dimpled = [synth.textured_case(192, 64, 31), synth.textured_case(192, 64, 32)]
+    smooth = synth.smooth_case(192, 64, 33)
+    log("case: 192x64 handle re-textured: dimples seed 31 -> 32 -> smooth -> 31")
+
+    def solve(s, c):
+        s.assemble(c.e, c.edot, c.delta, 9)
+        p, info = s.solve(omega=c.omega, eps=1e-12)
+        return p.cpu().numpy().copy(), s.integrate().cpu().numpy().copy(), s.jacobian_fd().cpu().numpy().copy()
+
+    def fresh(c):
+        s = JointGapSolver.from_case(c, max_cond=9)
+        out = solve(s, c)
+        s.close()
+        return out
+
+    s = JointGapSolver.from_case(dimpled[0], max_cond=9)
+    solve(s, dimpled[0])
+    for c in (dimpled[1], smooth, dimpled[0]):
+        s.set_dimples(JointGapSolver.case_dimples(c))
+        for a, b in zip(solve(s, c), fresh(c)):
+            assert np.array_equal(a, b), c.label
+    bad = (np.array([0.1]), np.array([0.02]), np.array([1e-3]), np.array([2e-3]))     # depth > radius
+    with pytest.raises(G.GapError) as ei:
+        s.set_dimples(bad)
+    assert ei.value.status == G.GAP_EINVAL
+    for a, b in zip(solve(s, dimpled[0]), fresh(dimpled[0])):
+        assert np.array_equal(a, b)
+    s.close()
 
 
 @ITERATIONS

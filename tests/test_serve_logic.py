@@ -227,3 +227,56 @@ def test_a_failing_lane_raises_in_the_caller():
     srv = LaneServer(bulk, fast, budget_bytes=50, bulk_work=4)
     with pytest.raises(ValueError):
         srv.run([req(0, 0.0, 60, 2, work=4), req(1, 0.0, 10, 2, work=1)])
+
+
+class FakeSolver:
+    """Stands in for JointGapSolver in the handle-pool test (no device)."""
+    made = 0
+
+    def __init__(self, case):
+        FakeSolver.made += 1
+        self.case, self.textures, self.closed = case, [case.fake_tex], False
+
+    @staticmethod
+    def geometry_key(case):
+        return (case.n_theta, case.n_axial)
+
+    @staticmethod
+    def case_dimples(case):
+        return case.fake_tex
+
+    @classmethod
+    def from_case(cls, case, max_cond=9, device=None):
+        return cls(case)
+
+    def set_dimples(self, dimples):
+        self.textures.append(dimples)
+
+    def close(self):
+        self.closed = True
+
+
+def test_handle_pool_reuses_handles_of_the_same_grid_and_bounds_the_idle_ones():
+    from paper_2511_06824_amd.serve import HandlePool
+    pool = HandlePool(device=None, per_key=2)
+    pool.Solver = FakeSolver
+    FakeSolver.made = 0
+
+    def case(nt, nz, tex):
+        return SimpleNamespace(n_theta=nt, n_axial=nz, fake_tex=tex)
+
+    a = pool.get(case(64, 32, "A"))
+    b = pool.get(case(64, 32, "B"))
+    c = pool.get(case(128, 64, "C"))
+    assert FakeSolver.made == 3 and pool.created == 3 and pool.reused == 0
+    pool.put(a)
+    d = pool.get(case(64, 32, "D"))               # the idle 64x32 handle, re-textured
+    assert d is a and a.textures == ["A", "D"] and pool.reused == 1
+    e = pool.get(case(128, 64, "E"))              # no idle 128x64 handle: a new one
+    assert e is not c and FakeSolver.made == 4
+    extra = [pool.get(case(64, 32, "F")) for _ in range(2)]
+    for s in [a, b] + extra:                      # 4 idle 64x32 handles offered, 2 kept
+        pool.put(s)
+    assert sum(s.closed for s in [a, b] + extra) == 2
+    pool.close()
+    assert all(s.closed for s in [a, b] + extra)
