@@ -71,6 +71,22 @@ __global__ __launch_bounds__(GAP_BLOCK) void k_texture(GeomDev g, int count, con
 // ---------------------------------------------------------------------------------------
 // Assembly (step I): one thread per (cell, condition).  Writes the source of every
 // condition and, for conditions that own an operator, its face conductances.
+// The faces each row owns, as pairs for the strip iteration: pair (r + 1, i) holds the east
+// face of cell (r, i) and the axial face above it, (kx(r, i), kz(r + 1, i)), for rows
+// r = -1 .. n_axial - 1 (row -1: (0, the inlet face kz(0, i))), per operator.  A row step then
+// reads its conductances with one 16-byte load per lane.
+__global__ __launch_bounds__(GAP_BLOCK) void k_pair_ops(int nt, int nz, const double* __restrict__ kx,
+                                                        const double* __restrict__ kz, double* __restrict__ kxz)
+{
+    const int op = blockIdx.y;
+    const size_t n = (size_t)nt * nz, nf = n + nt;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;     // pair (r + 1, i)
+    if (idx >= nf) return;
+    const double e = idx >= (size_t)nt ? kx[op * n + idx - nt] : 0.0;
+    kxz[op * 2 * nf + 2 * idx] = e;
+    kxz[op * 2 * nf + 2 * idx + 1] = kz[op * nf + idx];
+}
+
 __global__ __launch_bounds__(GAP_BLOCK) void k_assemble(GeomDev g, CondDev cd, TablesDev tb, double* __restrict__ kx,
                            double* __restrict__ kz, double* __restrict__ S)
 {

@@ -61,6 +61,7 @@ struct PcgDev {
     // operator (face conductances) and diagonal preconditioner, per distinct operator
     const double* kx;           // [n_op][n]
     const double* kz;           // [n_op][n + nt]
+    const double* kxz;          // [n_op][n + nt][2]: (kx of row r, kz of face r + 1) at pair r + 1
     const double* minv;         // [n_op][n]  (Jacobi / ASSOR I), or null
     // vectors, condition-major
     const double* S;            // [n_cond][n]

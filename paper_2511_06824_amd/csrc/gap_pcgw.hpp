@@ -187,13 +187,23 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     const int op = a.op[c];
     const GAP_AS1 double* kx = as_global(a.kx + (size_t)op * n);
     const GAP_AS1 double* kz = as_global(a.kz + (size_t)op * (n + nt));
+    const GAP_AS1 double* kxz = as_global(a.kxz + (size_t)op * 2 * (n + nt));   // pairs (order 1)
     const GAP_AS1 double* mv = as_global(pk == 1 ? a.minv + (size_t)op * n : a.kx);   // read by ASSOR I only
     const size_t co = (size_t)c * n;
-    // the vector that u_j is formed against: u_{j-1}, or p_0 for the initial residual
-    const GAP_AS1 double* uin = as_global((INIT ? a.p : a.u[(j + 1) & 1]) + co);
-    GAP_AS1 double* uout = as_global(a.u[(j & 1)] + co);
-    const GAP_AS1 double* rin = as_global((INIT ? a.S : a.r[j & 1]) + co);
+    // Order 1 keeps r and u as interleaved pairs: the block of parity k holds (r_k, u_{k-1})
+    // per cell, so a launch reads the pair it needs with one 16-byte load per lane and writes
+    // (r_{j+1}, u_j) with one store; the initial residual reads S and p_0 from their own
+    // arrays and writes (r_0, 0).  u_{j-1} of row s then waits M + 1 steps in registers, which
+    // higher orders cannot afford: they keep r and u in separate arrays (the halves of the
+    // same blocks) and read u_{j-1} of row s - M where it is needed.
+    constexpr bool kPairs = (M == 1);
+    constexpr int DU = kPairs ? M : 0;           // ring index of u_{j-1} of row s - M
+    const GAP_AS1 double* ruin = as_global(a.r[j & 1] + 2 * co);       // pair g at [2g], [2g + 1]
+    GAP_AS1 double* ruout = as_global(a.r[(j + 1) & 1] + 2 * co);
+    const GAP_AS1 double* rin = as_global((INIT ? a.S : a.r[j & 1]) + co);   // separate arrays
     GAP_AS1 double* rout = as_global(a.r[(j + 1) & 1] + co);
+    const GAP_AS1 double* uin = as_global((INIT ? a.p : a.u[(j + 1) & 1]) + co);
+    GAP_AS1 double* uout = as_global(a.u[j & 1] + co);
     GAP_AS1 double* pp = as_global(a.p + co);
 
     // Row pipeline with Neumann order M (the lags grow with M): S1, S2 on row s; the second
@@ -216,7 +226,7 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     double KX[P][Q];                            // east-face conductances
     double DI[P][Q];                            // 1/D
     double F[P][Q];                             // axial faces
-    double UP[P][Q];                            // loaded with step s: u_{j-1} (p_0 at the start) of row s - M
+    double UP[P][Q];                            // u_{j-1} (p_0 at the start) of row s - d (order 1), s - M - d
     double PP[P][Q];                            // loaded with step s: p of row s - M - 1 (odd iterations)
     double MV1[P][Q], MV3[P][Q];                // loaded with step s: ASSOR I diagonal of rows s - 1, s - 3
     double V[P][Q];                             // v of row s - d (z_j)
@@ -243,8 +253,8 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     }
     // u_{j-1} is read from the second iteration on (beta = 0 before), p_0 on a warm start
     const bool need_up = INIT ? a.warm != 0 : has_prev;
-    // loads of row step s into ring slot SL: r, kx of row s; face s + 1; u_prev of row s - M;
-    // p of row s - M - 1; the ASSOR I diagonal of rows s - 1 and s - 3
+    // loads of row step s into ring slot SL: r, u_prev (p_0), kx of row s; face s + 1; p of
+    // row s - M - 1; the ASSOR I diagonal of rows s - 1 and s - 3
     auto issue = [&](int s, auto SLc) {
         constexpr int sl = decltype(SLc)::value;
 #pragma unroll
@@ -253,12 +263,24 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
             const unsigned gc = (unsigned)gcol[q];
             if (s < nz) {
                 const unsigned g = (unsigned)s * nt + gc;
-                R[sl][q] = rin[g];
-                KX[sl][q] = kx[g];
+                if (INIT || !kPairs) {
+                    R[sl][q] = rin[g];
+                    if (kPairs && need_up) UP[sl][q] = uin[g];
+                } else {
+                    R[sl][q] = ruin[2 * g];         // u_{j-1} is 0 at j = 0 (written so by the initial residual)
+                    UP[sl][q] = ruin[2 * g + 1];
+                }
+                if (kPairs) {
+                    const unsigned h = g + (unsigned)nt;   // pair (s + 1, column): kx of row s, face s + 1
+                    KX[sl][q] = kxz[2 * h];
+                    F[sl][q] = kxz[2 * h + 1];
+                } else {
+                    KX[sl][q] = kx[g];
+                }
             }
-            if (s + 1 <= nz) F[sl][q] = kz[(unsigned)(s + 1) * nt + gc];
-            if (s - M >= 0 && s - M < nz && need_up)
+            if (!kPairs && s - M >= 0 && s - M < nz && need_up)
                 UP[sl][q] = __builtin_nontemporal_load(&uin[(unsigned)(s - M) * nt + gc]);
+            if (!kPairs && s + 1 <= nz) F[sl][q] = kz[(unsigned)(s + 1) * nt + gc];
             if (odd && ownc[q] && s - M - 1 >= j0 && s - M - 1 < j1)
                 PP[sl][q] = __builtin_nontemporal_load(&pp[(unsigned)(s - M - 1) * nt + gc]);
             if (pk == 1) {
@@ -272,7 +294,10 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     if (has_strip) {
         // face s_begin, the south face of the first row (d = 1 in phase 0)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) F[P - 1][q] = kz[(unsigned)s_begin * nt + gcol[q]];
+        for (int q = 0; q < Q; ++q) {
+            const unsigned h = (unsigned)s_begin * nt + gcol[q];
+            F[P - 1][q] = kPairs ? kxz[2 * h + 1] : kz[h];
+        }
         issue(s_begin, std::integral_constant<int, 0>{});
         if constexpr (kAhead == 2) issue(s_begin + 1, std::integral_constant<int, 1>{});
     }
@@ -368,7 +393,7 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
                     for (int q = 0; q < Q; ++q)
                         if (ownc[q]) {
                             const unsigned g = (unsigned)s * nt + gcol[q];
-                            pp[g] = pp[g] + a_prev * uin[g];
+                            pp[g] = pp[g] + a_prev * (kPairs ? ruin[2 * g + 1] : uin[g]);
                         }
                 }
             }
@@ -421,7 +446,7 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
         double un[Q];
         if constexpr (INIT) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) un[q] = UP[S(0)][q];   // p_0 (zero on a cold start)
+            for (int q = 0; q < Q; ++q) un[q] = UP[S(DU)][q];  // p_0 (zero on a cold start)
         } else if (pk == 2) {
             // first sweep on row s: v = y + t_1 + ... + t_M, t_k = w D^-1 (west, south and
             // east-wrap couplings of t_{k-1})
@@ -483,14 +508,14 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
                 for (int k = 1; k < M; ++k) zs += W[k][S(M - k)][q];
                 zs += wl[q];
                 const double zj = scale * zs;
-                un[q] = zj + beta * UP[S(0)][q];        // u_{j-1} reads 0 while beta = 0
+                un[q] = zj + beta * UP[S(DU)][q];       // u_{j-1} reads 0 while beta = 0
             }
         } else {
             // Jacobi (Eq 2.8) or ASSOR I: z_j = diag r_j of row s - 1 (M = 1)
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const double zj = (pk == 0 ? DI[S(1)][q] : MV1[S(0)][q]) * R[S(1)][q];
-                un[q] = zj + beta * UP[S(0)][q];
+                un[q] = zj + beta * UP[S(DU)][q];
             }
         }
 #pragma unroll
@@ -521,15 +546,20 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
                 yq[q] = r1v * DI[S(DA)][q];
                 if (ownc[q] && own_a) {
                     const unsigned g = (unsigned)ra * nt + gcol[q];
-                    rout[g] = r1v;
+                    if (kPairs) {
+                        ruout[2 * g] = r1v;
+                        ruout[2 * g + 1] = INIT ? 0.0 : U[S(1)][q];
+                    } else {
+                        rout[g] = r1v;
+                        if (!INIT) __builtin_nontemporal_store(U[S(1)][q], &uout[g]);
+                    }
                     acc_rr += r1v * r1v;
                     if (INIT) {
                         acc_ss += R[S(DA)][q] * R[S(DA)][q];
                         if (!a.warm) pp[g] = 0.0;
                     } else {
-                        __builtin_nontemporal_store(U[S(1)][q], &uout[g]);
                         acc_uau += U[S(1)][q] * AU[S(0)][q];
-                        if (odd) pp[g] = PP[S(0)][q] + (a_prev * UP[S(1)][q] + alpha * U[S(1)][q]);
+                        if (odd) pp[g] = PP[S(0)][q] + (a_prev * UP[S(DU + 1)][q] + alpha * U[S(1)][q]);
                     }
                 }
             }

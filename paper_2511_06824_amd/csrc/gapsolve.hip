@@ -411,6 +411,7 @@ struct gap_grid_s {
     double *dim_dev = nullptr, *dim_host = nullptr;          // dimple parameters for set_gap_dimples (host: pinned)
     int dim_cap = 0;                                         // dimples they hold
     double *kx = nullptr, *kz = nullptr, *minv = nullptr;
+    double *kxz = nullptr;                                   // kx and kz as the pairs of k_pair_ops
     double *S = nullptr, *r0 = nullptr, *r1 = nullptr, *u0 = nullptr, *u1 = nullptr, *z = nullptr;
     double *z1 = nullptr;                                    // second z of the one-launch iteration
     double *partial = nullptr;                               // force-integration partials
@@ -482,7 +483,7 @@ namespace {
 
 void release(gap_grid_t g)
 {
-    double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->minv, g->S, g->r0, g->r1, g->u0, g->u1, g->z, g->z1, g->partial,
+    double* bufs[] = {g->trig, g->tex, g->kx, g->kz, g->kxz, g->minv, g->S, g->r0, g->r1, g->z, g->z1, g->partial,
                       g->pcg_part, g->adj_rhs, g->adj_lam, g->adj_part, g->step_buf, g->hist};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
@@ -1029,6 +1030,7 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
     ALLOC(g->tex, 2 * n + (g->nz + 1) * nt);
     ALLOC(g->kx, g->max_op * n);
     ALLOC(g->kz, g->max_op * (n + nt));
+    ALLOC(g->kxz, g->max_op * 2 * (n + nt));
     {
         int dev = 0;
         (void)hipGetDevice(&dev);
@@ -1067,10 +1069,12 @@ gap_status create_gap_grid(const gap_geom* geom, const gap_dimples* dimples, int
         }
     }
     ALLOC(g->S, max_cond * n);
-    ALLOC(g->r0, max_cond * n);
-    ALLOC(g->r1, max_cond * n);
-    ALLOC(g->u0, max_cond * n);
-    ALLOC(g->u1, max_cond * n);
+    // r and u of one parity share a block: the ring kernels use its halves, the strip kernel
+    // reads it as interleaved (r, u) pairs (a solve uses one iteration kind)
+    ALLOC(g->r0, 2 * max_cond * n);
+    ALLOC(g->r1, 2 * max_cond * n);
+    g->u0 = g->r0 + max_cond * n;
+    g->u1 = g->r1 + max_cond * n;
     ALLOC(g->z, max_cond * n);
     ALLOC(g->z1, max_cond * n);
     ALLOC(g->partial, 10 * max_chunks);
@@ -1247,6 +1251,9 @@ gap_status assemble_joint_system(gap_grid_t g, const double e[4], const double e
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)((g->n + GAP_BLOCK - 1) / GAP_BLOCK), n_cond), dim3(GAP_BLOCK), 0, st,
                        g->gd, cd, t, g->kx, g->kz, g->S);
     HIPLAUNCHCHK("k_assemble");
+    hipLaunchKernelGGL(k_pair_ops, dim3((unsigned)((g->n + g->nt + GAP_BLOCK - 1) / GAP_BLOCK), cd.n_op),
+                       dim3(GAP_BLOCK), 0, st, g->nt, g->nz, (const double*)g->kx, (const double*)g->kz, g->kxz);
+    HIPLAUNCHCHK("k_pair_ops");
     g->cd = cd;
     g->n_cond = n_cond;
     g->n_op = cd.n_op;
@@ -1272,6 +1279,7 @@ gap_status solve_joint_pcg(gap_grid_t g, const gap_solver_opts* o, double* p, ga
 
     PcgDev a{};
     a.kx = g->kx;
+    a.kxz = g->kxz;
     a.kz = g->kz;
     a.minv = g->minv;
     a.S = g->S;
@@ -1352,6 +1360,7 @@ gap_status jacobian_adjoint(gap_grid_t g, const gap_solver_opts* o, const double
     oa.warm_start = 0;
     PcgDev a{};
     a.kx = g->kx;
+    a.kxz = g->kxz;
     a.kz = g->kz;
     a.minv = g->minv;
     a.S = g->adj_rhs;
@@ -1418,6 +1427,7 @@ gap_status solve_with_adjoint(gap_grid_t g, const gap_solver_opts* o, double* p0
     oa.warm_start = 0;
     PcgDev a{};
     a.kx = g->kx;
+    a.kxz = g->kxz;
     a.kz = g->kz;
     a.minv = g->minv;
     a.S = g->adj_rhs;
@@ -2128,6 +2138,7 @@ gap_status gap_grid_bytes(const gap_geom* geom, int32_t max_cond, int64_t* bytes
     const ChunkMap cm1 = make_chunks((int)nz, 1), cm9 = make_chunks((int)nz, GAP_MAX_COND);
     int64_t d = 4 * nt + 2 * n + (nz + 1) * nt;              // tables and texture samples
     d += max_op * n + max_op * (n + nt);                     // face conductances
+    d += max_op * 2 * (n + nt);                              // and as pairs
     d += 7 * (int64_t)max_cond * n;                          // S, r (2), u (2), z (2)
     d += 10 * (int64_t)std::max(cm1.total, cm9.total);       // force partials
     int strips1 = 1, groups1 = 1;
@@ -2216,6 +2227,7 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
 
     PcgDev a{};
     a.kx = g->kx;
+    a.kxz = g->kxz;
     a.kz = g->kz;
     a.minv = g->minv;
     a.S = g->S;
