@@ -20,9 +20,10 @@
 //   wave_shr:1 / wave_shl:1, with lane 0 / 63 filled from the next column block by
 //   readlane); axial neighbours are earlier rows held in registers.  No LDS rows, no data
 //   exchange in the row march, and any ring width: a ring is cut into as many strips as it
-//   needs.  At order 1 the wavefronts of a workgroup, which march neighbouring strips of the
-//   same rows, meet at a barrier once per unrolled period of the march, so that the columns
-//   two of them read are more often still in the caches when the second one reads them.
+//   needs.  On large systems at order 1 the wavefronts of a workgroup, which march
+//   neighbouring strips of the same rows, meet at a barrier once per unrolled period of the
+//   march, so that the columns two of them read are more often still in the caches when the
+//   second one reads them.
 // * Neumann order M (Eq 3.4 is M = 1): the inverses of (I + w D^-1 L) and (I + w D^-1 L^T)
 //   keep M terms of their series.  The first sweep adds t_k = -w D^-1 L t_{k-1} on the row
 //   being read (south and west couplings: earlier rows and lanes); the second adds
@@ -137,8 +138,9 @@ __device__ __forceinline__ bool strip_steps(Fn& fn, int& s, int s_last)
 
 // PK: the preconditioner fixed at compile time (0 Jacobi, 1 ASSOR I, 2 ASSOR II), or -1 to
 // read it from the request (a batch whose requests differ).  M: the Neumann order of ASSOR II
-// (1 is Eq 3.4; the diagonal preconditioners run with M = 1).
-template <int Q, int PK, int M, bool INIT>
+// (1 is Eq 3.4; the diagonal preconditioners run with M = 1).  SYNC (order 1 only): the
+// wavefronts of a workgroup meet at a barrier after each period of the row march.
+template <int Q, int PK, int M, bool INIT, bool SYNC = false>
 __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __restrict__ reqs,
                                                             const int* __restrict__ work, int launch_par)
 {
@@ -663,7 +665,8 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
         if constexpr (kAhead == 2) s1(s + 1, std::integral_constant<int, S(-1)>{});
     };
 
-    if constexpr (M == 1) {
+    if constexpr (SYNC) {
+        static_assert(M == 1, "the synchronized march is built for order 1");
         auto nowrap = [&](int sv, auto PHc) { step(sv, PHc, std::false_type{}); };
         auto withwrap = [&](int sv, auto PHc) { step(sv, PHc, std::true_type{}); };
         int s = s_begin;
@@ -671,12 +674,15 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
         const int w0 = oc0 - strip_halo(M);
         const bool wrap = !(w0 >= 1 && w0 + 64 * Q - 1 <= nt - 2);
         if (has_strip && kAhead == 2) s1(s_begin, std::integral_constant<int, 0>{});
-        // Order 1: the wavefronts of the workgroup meet at a barrier after each period of P
-        // row steps (periods - 1 full ones, then the last of 1 .. P steps).  The trip count
-        // is the same for all of them (one row chunk), and the barrier sits where every
-        // wavefront, with a strip or without, passes it once per trip.  Measured on the
-        // 2048-column rings: 3 % less time and 2 % less HBM traffic per launch; at orders 2
-        // and 3 the wait cost more than it saved.
+        // The wavefronts of the workgroup meet at a barrier after each period of P row steps
+        // (periods - 1 full ones, then the last of 1 .. P steps).  The trip count is the same
+        // for all of them (one row chunk), and the barrier sits where every wavefront, with a
+        // strip or without, passes it once per trip.  They exchange nothing there: held within
+        // a period of each other, the edge columns two of them read are more often still in
+        // the caches at the second read.  Measured on the 9-condition 2048 x 1024 system:
+        // 3 % less time and 2 % less HBM traffic per launch; on 1024 x 512, whose vectors and
+        // operators fit the last-level cache, this form of the march costs 3-5 %, so the host
+        // picks it for requests that stream more than that cache holds.
         const int periods = (s_last - s_begin + P) / P;
         for (int it = 0; it < periods; ++it) {
             if (has_strip) {
@@ -687,13 +693,21 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
         }
     } else if (has_strip) {
         if constexpr (kAhead == 2) s1(s_begin, std::integral_constant<int, 0>{});
+        // the strip's columns lie inside [1, n_theta - 2]: no wrap coupling in it
+        const int w0 = oc0 - strip_halo(M);
+        const bool wrap = !(w0 >= 1 && w0 + 64 * Q - 1 <= nt - 2);
         int s = s_begin;
         auto march = [&](auto WRc) {
             auto one = [&](int sv, auto PHc) { step(sv, PHc, WRc); };
             while (strip_steps<0, P>(one, s, s_last)) {
             }
         };
-        march(std::true_type{});
+        if constexpr (M == 1) {
+            if (!wrap) march(std::false_type{});
+            else march(std::true_type{});
+        } else {
+            march(std::true_type{});
+        }
     }
     double v6[6] = {acc_rz, acc_rr, acc_zaz, acc_zau, acc_uau, acc_ss};
     wg_sum<kStripThreads, 6>(v6);

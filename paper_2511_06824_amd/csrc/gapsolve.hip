@@ -78,6 +78,7 @@ struct PcgShape {
     int NT = 512, Q = 4;
     int pk = -1;    // strip kernel: the preconditioner compiled in (-1: read from each request)
     int M = 1;      // strip kernel: the Neumann order of ASSOR II
+    int sync = 0;   // strip kernel at order 1: the march with a workgroup barrier per period
 };
 
 // Every instantiated shape.
@@ -185,6 +186,25 @@ std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
 constexpr int kStripMaxQ = 1;
 constexpr int kStripDefaultQ = 1;
 constexpr int kMinStripRows = 16;      // a row chunk recomputes 7 halo rows
+// A request that streams at least this many bytes per iteration runs the order-1 strip
+// kernel whose wavefronts meet at a barrier once per period: 3 % faster on the 9-condition
+// 2048 x 1024 system (0.92 GB per iteration).  Where the vectors and operators fit the
+// 256 MB last-level cache the barrier only costs: 1024 x 512 (0.23 GB) runs 3-5 % faster
+// without it.  Both forms compute the same values in the same order.
+constexpr double kStripSyncBytes = 512.0 * 1024 * 1024;
+
+// Bytes the strip iteration streams for a request per launch: 40 B per condition-DOF on
+// average (r and u_prev read, u and r' written, p every other launch) and 16 B per
+// operator-DOF (the conductance pairs).
+inline double strip_request_bytes(const PcgDev& a)
+{
+    int n_op = 0;
+    for (int c = 0; c < a.n_cond; ++c) n_op = std::max(n_op, a.op[c] + 1);
+    return (double)a.nt * a.nz * (40.0 * a.n_cond + 16.0 * n_op);
+}
+
+// Whether a request of order M runs the synchronized march.
+inline bool strip_sync(int M, const PcgDev& a) { return M == 1 && strip_request_bytes(a) >= kStripSyncBytes; }
 
 bool strip_q_known(int Q) { return Q >= 1 && Q <= kStripMaxQ; }
 
@@ -225,10 +245,20 @@ void strip_chunks(int nz, int nt, int n_cond, int Q, int M, int slots, PcgDev& a
 // the request) for each Neumann order, and the iteration for each preconditioner, fixed or
 // read from the request; ASSOR II with Neumann orders 1 .. kStripMaxNeumann.
 template <int Q>
-const void* strip_fn(bool init, int pk, int M)
+const void* strip_fn(bool init, int pk, int M, bool sync = false)
 {
     // two columns per lane at order 3 would spill most of its registers: not instantiated
     if (Q >= 2 && M >= 3) return nullptr;
+    if (sync) {
+        if (M != 1) return nullptr;
+        if (init) return (const void*)k_pcg_w<Q, -1, 1, true, true>;
+        switch (pk) {
+        case 0: return (const void*)k_pcg_w<Q, 0, 1, false, true>;
+        case 1: return (const void*)k_pcg_w<Q, 1, 1, false, true>;
+        case 2: return (const void*)k_pcg_w<Q, 2, 1, false, true>;
+        default: return (const void*)k_pcg_w<Q, -1, 1, false, true>;
+        }
+    }
     if (init) {
         switch (M) {
         case 1: return (const void*)k_pcg_w<Q, -1, 1, true>;
@@ -256,16 +286,18 @@ const void* strip_fn(bool init, int pk, int M)
 template <int Q>
 hipError_t strip_prepare_t(int M, int* occupancy)
 {
-    // the occupancy of the ASSOR II iteration of order M and of its initial residual
+    // the occupancy of the ASSOR II iteration of order M and of its initial residual, in
+    // both forms of the march at order 1
     int occ = 1 << 20;
-    for (int init = 0; init < 2; ++init) {
-        int nb = 0;
-        const void* fn = strip_fn<Q>(init != 0, 2, M);
-        if (!fn) return hipErrorInvalidValue;
-        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStripThreads, 0);
-        if (e != hipSuccess) return e;
-        occ = std::min(occ, nb > 0 ? nb : 1);
-    }
+    for (int sync = 0; sync < (M == 1 ? 2 : 1); ++sync)
+        for (int init = 0; init < 2; ++init) {
+            int nb = 0;
+            const void* fn = strip_fn<Q>(init != 0, 2, M, sync != 0);
+            if (!fn) return hipErrorInvalidValue;
+            const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kStripThreads, 0);
+            if (e != hipSuccess) return e;
+            occ = std::min(occ, nb > 0 ? nb : 1);
+        }
     *occupancy = occ;
     return hipSuccess;
 }
@@ -280,13 +312,13 @@ hipError_t strip_prepare(int Q, int M, int* occupancy)
 }
 
 // pk: the preconditioner of every request in the launch (0, 1, 2), or -1 if they differ;
-// M: their Neumann order.
-hipError_t launch_strip(int Q, int pk, int M, bool init, const PcgDev* reqs, const int* work, int blocks,
+// M: their Neumann order; sync: the march with a barrier per period (order 1).
+hipError_t launch_strip(int Q, int pk, int M, bool sync, bool init, const PcgDev* reqs, const int* work, int blocks,
                         hipStream_t st, int par)
 {
     const void* fn = nullptr;
     switch (Q) {
-    case 1: fn = strip_fn<1>(init, pk, M); break;
+    case 1: fn = strip_fn<1>(init, pk, M, sync); break;
     default: return hipErrorInvalidValue;
     }
     if (!fn) return hipErrorInvalidValue;
@@ -355,7 +387,7 @@ hipError_t launch_pcg(PcgShape sh, int which, int lds_nt, const PcgDev* reqs, co
                       hipStream_t st, int par = 0)
 {
     if (which == kPcgStrip || which == kPcgStripInit)
-        return launch_strip(sh.Q, sh.pk, sh.M, which == kPcgStripInit, reqs, work, blocks, st, par);
+        return launch_strip(sh.Q, sh.pk, sh.M, sh.sync != 0, which == kPcgStripInit, reqs, work, blocks, st, par);
 #define GAP_SHAPE_CASE(nt_, q_) \
     if (sh.NT == nt_ && sh.Q == q_) return launch_pcg_t<nt_, q_>(which, lds_nt, reqs, work, blocks, st, par);
     GAP_PCG_SHAPES(GAP_SHAPE_CASE)
@@ -627,12 +659,13 @@ gap_status run_pcg(gap_grid_t g, PcgDev& a, const gap_solver_opts* o, hipStream_
         sh_b.pk = o->precond;
         sh_b.M = o->neumann;
         sh_b.Q = strip_q(sh_b.Q, sh_b.M);
+        sh_b.sync = strip_sync(sh_b.M, a) ? 1 : 0;
     }
 
     // schedule tables for this (iteration kind, kernel shapes, n_cond, chunk counts, operator
     // map); graphs are cached by table, so the shapes belong to the key
     std::vector<int> key = {o->iteration, one ? 0 : g->shape_a.NT, one ? 0 : g->shape_a.Q, sh_b.NT, sh_b.Q, sh_b.pk,
-                            sh_b.M, a.n_cond, a.chunks_a, a.chunks_b};
+                            sh_b.M, sh_b.sync, a.n_cond, a.chunks_a, a.chunks_b};
     for (int c = 0; c < a.n_cond; ++c) key.push_back(a.op[c]);
     gap_grid_s::Sched* sch = nullptr;
     for (auto& e : g->scheds)
@@ -2082,8 +2115,9 @@ struct gap_batch_s {
     long launches = 0;                                       // one-launch kernel launches so far
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
-    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0, exec_par0 = 0, exec_pk = -1;
+    int exec_iters = 0, exec_blocks_a = 0, exec_blocks_b = 0, exec_par0 = 0, exec_pk = -1, exec_sync = 0;
     int pk = -1;                                             // preconditioner common to the scheduled requests, or -1
+    int sync = 0;                                            // strips: every scheduled request streams enough bytes
     const int* exec_work = nullptr;
     int next_id = 1;
 };
@@ -2269,7 +2303,10 @@ gap_status gap_batch_add(gap_batch_t b, gap_grid_t g, const gap_solver_opts* o, 
     HIPCHK(hipMemcpyAsync(b->init_work, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, st));
     PcgShape sh_init = strip ? b->shape_w : b->shape;
     sh_init.M = o->neumann;
-    if (strip) sh_init.Q = strip_q(sh_init.Q, sh_init.M);
+    if (strip) {
+        sh_init.Q = strip_q(sh_init.Q, sh_init.M);
+        sh_init.sync = strip_sync(sh_init.M, a) ? 1 : 0;
+    }
     hipError_t le = launch_pcg(sh_init, strip ? kPcgStripInit : (one ? kPcgOneInit : kPcgInit), kBatchShape,
                                b->reqs_dev, b->init_work, (int)tb.size(), st);
     if (le != hipSuccess) return fail(GAP_EDEVICE, "launch of the initial residual kernel: %s", hipGetErrorString(le));
@@ -2299,11 +2336,13 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
     if (b->dirty) {
         std::vector<std::vector<int>> ga, gb;
         b->pk = -2;                                  // the preconditioner common to the scheduled requests
+        b->sync = 1;                                 // the synchronized march if every one qualifies
         for (auto& r : b->reqs) {
             r.scheduled = !(r.done || r.held);
             if (!r.scheduled) continue;
             PcgDev& a = b->reqs_host[r.slot];
             b->pk = (b->pk == -2 || b->pk == a.precond) ? a.precond : -1;
+            if (!strip_sync(b->neumann, a)) b->sync = 0;
             if (!one) pcg_groups(r.slot, a.chunks_a, a.n_cond, a.op, ga);
             pcg_groups(r.slot, a.chunks_b, a.n_cond, a.op, gb, strip ? a.strip_groups : 1);
             if (one) {
@@ -2332,6 +2371,7 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
         sh_one.pk = b->pk >= 0 ? b->pk : -1;
         sh_one.M = b->neumann;
         sh_one.Q = strip_q(sh_one.Q, sh_one.M);
+        sh_one.sync = b->sync;
     }
     if ((one ? b->blocks_b : b->blocks_a) > 0) {
         const int* wa = b->work;
@@ -2340,7 +2380,7 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
         if (use_graph) {
             if (!b->exec || b->exec_iters != iterations || b->exec_blocks_a != b->blocks_a ||
                 b->exec_blocks_b != b->blocks_b || b->exec_work != b->work || b->exec_par0 != par0 ||
-                b->exec_pk != sh_one.pk) {
+                b->exec_pk != sh_one.pk || b->exec_sync != sh_one.sync) {
                 if (b->exec) (void)hipGraphExecDestroy(b->exec);
                 b->exec = nullptr;
                 if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
@@ -2356,6 +2396,7 @@ gap_status gap_batch_step(gap_batch_t b, int32_t iterations, int32_t use_graph, 
                 b->exec_work = b->work;
                 b->exec_par0 = par0;
                 b->exec_pk = sh_one.pk;
+                b->exec_sync = sh_one.sync;
             }
             HIPCHK(hipGraphLaunch(b->exec, st));
         } else {

@@ -33,10 +33,13 @@ ITERATIONS = pytest.mark.parametrize("iteration", [G.GAP_ITERATION_TWO_LAUNCH, G
 
 
 def batch_solve(cases, eps_override=None, iters=8, use_graph=True, iteration=G.GAP_ITERATION_ONE_LAUNCH,
-                join_every=0, neumann=1):
+                join_every=0, neumann=1, target=0):
     """Solve the cases together in one batch; returns pressures, infos by case index.
-    join_every > 0: the cases join one at a time, one step of `iters` iterations apart."""
+    join_every > 0: the cases join one at a time, one step of `iters` iterations apart.
+    target > 0: the strip chunking aims at that many workgroups per CU."""
     b = G.gap_batch_create()
+    if target:
+        G.gap_batch_set_target(b, target)
     stream = torch.cuda.current_stream().cuda_stream
     solvers, ids = [], []
     pending = list(cases)
@@ -77,6 +80,21 @@ def test_results_alone_and_in_the_mix_are_bitwise_equal(iteration):
             assert alone[1] == other[1]
             assert np.array_equal(alone[0], other[0]), c.label
             assert np.array_equal(alone[2], other[2]), c.label
+
+
+def test_strip_march_with_and_without_barriers_is_bitwise_equal():
+    """At order 1 a strip request that streams more than 512 MiB per iteration runs the march
+    with a workgroup barrier per period when it is alone; in a batch with a small request the
+    launch runs the march without barriers for both.  The two forms compute the same values
+    in the same order, so the large request's results are bitwise equal.  2048 x 640 with 9
+    conditions on 5 operators streams 1310720 x (9 x 40 + 5 x 16) B = 577 MB."""
+    big = synth.textured_case(2048, 640, 11)
+    log(f"case: {big.label} alone (barriers) and with {CASES[0].label} (no barriers), strips")
+    alone = batch_solve([big], iteration=G.GAP_ITERATION_STRIPS)[0]
+    mixed = batch_solve([big, CASES[0]], iteration=G.GAP_ITERATION_STRIPS)[0]
+    assert alone[1] == mixed[1]
+    assert np.array_equal(alone[0], mixed[0])
+    assert np.array_equal(alone[2], mixed[2])
 
 
 @pytest.mark.parametrize("iteration", [G.GAP_ITERATION_ONE_LAUNCH, G.GAP_ITERATION_STRIPS],
