@@ -35,6 +35,16 @@ def _dispatches(path, counter):
     return {k: [v for _, v in sorted(x)] for k, x in out.items()}
 
 
+def _is_initial_residual(name):
+    """Whether a PCG kernel name is an initial-residual instantiation: the INIT template
+    argument is the fourth of k_pcg_w<Q, PK, M, INIT, SYNC> and the last of k_pcg_b / k_pcg_f
+    <NT, Q, INIT>."""
+    args = [x.strip() for x in name[name.index("<") + 1:name.index(">")].split(",")]
+    if name.startswith("void k_pcg_w"):
+        return args[3] == "true"
+    return len(args) == 3 and args[2] == "true"
+
+
 def summarize(fetch_csv, write_csv, copy_mib=1024):
     fetch, write = _dispatches(fetch_csv, "FETCH_SIZE"), _dispatches(write_csv, "WRITE_SIZE")
     copy_kib = copy_mib * 1024.0
@@ -50,7 +60,7 @@ def summarize(fetch_csv, write_csv, copy_mib=1024):
     print("|---|---|---|---|---|")
     mean = lambda x: sum(x) / len(x)
     for name in sorted(fetch):
-        if not name.startswith("void k_pcg_") or ", true>" in name:
+        if not name.startswith("void k_pcg_") or _is_initial_residual(name):
             continue
         f, w = fetch[name][1:-1], write.get(name, [])[1:-1]
         if not f or len(f) != len(w):

@@ -92,6 +92,15 @@ def test_counter_summary_takes_the_steady_state(tmp_path, capsys):
     for k, (fv, wv) in enumerate([(50, 10), (200, 100), (200, 100), (7, 0)]):
         fetch.append((30 + k, ka, fv))
         write.append((30 + k, ka, wv))
+    # the strip kernel: its initial residual (INIT, the fourth argument) is left out, the
+    # iteration of the synchronized march (SYNC, the fifth) is summarized
+    kwi = "void k_pcg_w<1, -1, 1, true, true>(PcgDev const*, int const*, int)"
+    kw = "void k_pcg_w<1, 2, 1, false, true>(PcgDev const*, int const*, int)"
+    fetch.append((40, kwi, 999))
+    write.append((40, kwi, 999))
+    for k, (fv, wv) in enumerate(f_vals):
+        fetch.append((50 + k, kw, fv))
+        write.append((50 + k, kw, wv))
     fcsv, wcsv = tmp_path / "fetch.csv", tmp_path / "write.csv"
     _counter_csv(fcsv, "FETCH_SIZE", fetch)
     _counter_csv(wcsv, "WRITE_SIZE", write)
@@ -104,3 +113,5 @@ def test_counter_summary_takes_the_steady_state(tmp_path, capsys):
     assert f"| k_pcg_f<1024,2,false>, even j | 2 | 300.0 | 450.0 | {even} |" in out
     assert f"| k_pcg_f<1024,2,false>, average | 4 | | | {(odd + even) // 2} |" in out
     assert f"| k_pcg_a<1024,2> | 2 | 200.0 | 100.0 | {200 * 1024 * 2 + 100 * 1024} |" in out
+    assert f"| k_pcg_w<1,2,1,false,true>, odd j | 2 | 400.0 | 500.0 | {odd} |" in out
+    assert "k_pcg_w<1,-1,1,true,true>" not in out
