@@ -125,6 +125,62 @@ __device__ __forceinline__ void east_of(const double (&x)[Q], double (&e)[Q])
     for (int q = 0; q < Q; ++q) e[q] = q < Q - 1 ? dpp_shift<0x130>(x[q], read_lane(x[q + 1], 0)) : dpp_shift0<0x130>(x[q]);
 }
 
+// Per-condition sums of NQ partial arrays of `chunks` slots each, in the order of cond_sums
+// (wave w takes conditions w, w + NW, ...; lane l adds slots l, l + 64, ... to a zero start;
+// then the same shuffle tree), so the sums are the same to the bit.  The loads of a round of
+// 64 slots go out for all of a wave's conditions and arrays together: one memory latency per
+// round instead of one per condition and array.  Threads 0 .. n_cond - 1 also copy gsrc[t]
+// to gout[t] on the way.  Results in out[q][c] and gout, valid after the trailing barrier.
+template <int NT, int NQ>
+__device__ __forceinline__ void strip_cond_sums(int n_cond, int chunks, const double* const (&src)[NQ],
+                                                double (*out)[GAP_MAXC], const double* gsrc, double* gout)
+{
+    constexpr int NW = NT / 64;
+    constexpr int R = (GAP_MAXC + NW - 1) / NW;     // conditions per wavefront at most
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool gcopy = (int)threadIdx.x < n_cond;
+    double g = 0.0;
+    if (gcopy) g = gsrc[threadIdx.x];
+    double v[R][NQ];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[r][q] = 0.0;
+    for (int k0 = 0; k0 < chunks; k0 += 64) {
+        const int k = k0 + lane;
+        double x[R][NQ];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool ok = w + r * NW < n_cond && k < chunks;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) x[r][q] = ok ? src[q][(w + r * NW) * chunks + k] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool ok = w + r * NW < n_cond && k < chunks;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (ok) v[r][q] += x[r][q];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[r][q] += __shfl_xor(v[r][q], off, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (w + r * NW < n_cond) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) out[q][w + r * NW] = v[r][q];
+            }
+    }
+    if (gcopy) gout[threadIdx.x] = g;
+    __syncthreads();
+}
+
 // Runs the row steps of phases PH .. P - 1 (fn(s, phase) each), advancing s; false once s has
 // passed s_last.  Unrolled at compile time, so each step sees its phase as a constant.
 template <int PH, int P, class Fn>
@@ -310,15 +366,17 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
     // ---- scalars (as in the ring kernel) ------------------------------------------------
     double alpha = 1.0, beta = 0.0, a_prev = 0.0;
     if (!INIT) {
+        // the device record's fields are read before the reduction's barrier, so that their
+        // latency overlaps that of the partial sums; r.z of the previous launch goes through LDS
         __shared__ double sums[kStripParts + 1][GAP_MAXC];
+        __shared__ double gprev[GAP_MAXC];
+        const unsigned was_active = (unsigned)a.sc->act_f[par];
+        const double alf_prev = odd ? a.sc->alf[par][c] : 0.0;
         {
             const double* rp = a.fpart[par];
             const double* src[kStripParts + 1] = {rp, rp + fs, rp + 2 * fs, rp + 3 * fs, rp + 4 * fs, a.part_ss};
-            const int cnt[kStripParts + 1] = {a.chunks_b, a.chunks_b, a.chunks_b, a.chunks_b, a.chunks_b, a.chunks_b};
-            cond_sums<kStripThreads, kStripParts + 1>(a.n_cond, cnt, src, sums);
+            strip_cond_sums<kStripThreads, kStripParts + 1>(a.n_cond, a.chunks_b, src, sums, a.sc->gam[par], gprev);
         }
-        const double* gprev = a.sc->gam[par];
-        const unsigned was_active = (unsigned)a.sc->act_f[par];
         unsigned active = 0;
         double rr = 0.0, ss = 0.0;
         for (int k = 0; k < a.n_cond; ++k) {
@@ -385,7 +443,7 @@ __global__ __launch_bounds__(kStripThreads, 2) void k_pcg_w(const PcgDev* __rest
                 a.hist[2 * j + 1] = beta;
             }
         }
-        a_prev = odd ? a.sc->alf[par][c] : 0.0;
+        a_prev = alf_prev;
         if (stop || !(active & (1u << c))) {
             if (!stop && t == 0)
                 for (int q = 0; q < kStripParts; ++q) wpart[q * fs + slot] = a.fpart[par][q * fs + slot];

@@ -154,10 +154,12 @@ void pcg_groups(int req, int chunks, int n_cond, const int* op, std::vector<std:
     }
 }
 
-// Schedule table of one PCG launch.  Workgroup b is dispatched to XCD b % 8; each group is
-// kept on one XCD (the conditions in it read the same operator, so the repeats hit that
-// XCD's L2), groups go largest first to the least loaded XCD, and idle entries (-1) pad the
-// XCD lists to equal length.
+// Schedule table of one PCG launch.  Workgroup b is dispatched to XCD b % 8.  Groups go
+// largest first to the least loaded XCD and stay on it (the conditions in a group read the
+// same operator, so the repeats hit that XCD's L2) as far as they fit: no XCD takes more than
+// its even share, ceil(entries / 8), so that a launch that fills the chip in one round does
+// so on every XCD; the part of a group beyond that share goes on to the next least loaded
+// XCD.  Idle entries (-1) pad the XCD lists to equal length.
 std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
 {
     constexpr int X = 8;
@@ -165,12 +167,20 @@ std::vector<int> pcg_schedule(std::vector<std::vector<int>> groups)
     std::vector<int> load(X, 0);
     std::stable_sort(groups.begin(), groups.end(),
                      [](const std::vector<int>& x, const std::vector<int>& y) { return x.size() > y.size(); });
+    size_t total = 0;
+    for (const auto& gcl : groups) total += gcl.size();
+    const int share = (int)((total + X - 1) / X);
     for (const auto& gcl : groups) {
-        int best = 0;
-        for (int x = 1; x < X; ++x)
-            if (load[x] < load[best]) best = x;
-        for (int w : gcl) lists[best].push_back(w);
-        load[best] += (int)gcl.size();
+        size_t i = 0;
+        while (i < gcl.size()) {
+            int best = 0;
+            for (int x = 1; x < X; ++x)
+                if (load[x] < load[best]) best = x;
+            const size_t take = std::min(gcl.size() - i, (size_t)std::max(1, share - load[best]));
+            for (size_t m = 0; m < take; ++m) lists[best].push_back(gcl[i + m]);
+            load[best] += (int)take;
+            i += take;
+        }
     }
     size_t len = 0;
     for (auto& l : lists) len = std::max(len, l.size());

@@ -86,9 +86,11 @@ def test_strip_march_with_and_without_barriers_is_bitwise_equal():
     """At order 1 a strip request that streams more than 512 MiB per iteration runs the march
     with a workgroup barrier per period when it is alone; in a batch with a small request the
     launch runs the march without barriers for both.  The two forms compute the same values
-    in the same order, so the large request's results are bitwise equal.  2048 x 640 with 9
-    conditions on 5 operators streams 1310720 x (9 x 40 + 5 x 16) B = 577 MB."""
-    big = synth.textured_case(2048, 640, 11)
+    in the same order, so the large request's results are bitwise equal.  2100 x 640 with 9
+    conditions on 5 operators streams 1344000 x (9 x 40 + 5 x 16) B = 591 MB; its rings are
+    cut into 41 strips, so the last workgroup of each row chunk has three wavefronts without
+    a strip, which meet the barriers all the same."""
+    big = synth.textured_case(2100, 640, 11)
     log(f"case: {big.label} alone (barriers) and with {CASES[0].label} (no barriers), strips")
     alone = batch_solve([big], iteration=G.GAP_ITERATION_STRIPS)[0]
     mixed = batch_solve([big, CASES[0]], iteration=G.GAP_ITERATION_STRIPS)[0]
