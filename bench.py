@@ -436,6 +436,9 @@ def main():
     ap.add_argument("--no-seeds", action="store_true", help="skip the two extra seeds of the workload")
     ap.add_argument("--no-strategies", action="store_true", help="skip the sync / async strategy comparison")
     ap.add_argument("--no-paper-meshes", action="store_true", help="skip the joint vs sequential runs at 400x360, 800x760")
+    ap.add_argument("--serve-targets", default=None,
+                    help="strip-kernel workgroups per CU of the serving lanes, 'bulk,fast' (default %d,%d)"
+                    % SERVE_TARGETS)
     ap.add_argument("--timing-period", type=int, default=TIMING_PERIOD,
                     help="time one iteration-kernel launch in this many inside the timed region (odd)")
     args = ap.parse_args()
@@ -713,7 +716,8 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = run_serving(torch, JointGapSolver, dev)
+        targets = tuple(int(x) for x in args.serve_targets.split(",")) if args.serve_targets else SERVE_TARGETS
+        serving = run_serving(torch, JointGapSolver, dev, targets=targets)
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint_vs_fd(torch, G, JointGapSolver, dev)
