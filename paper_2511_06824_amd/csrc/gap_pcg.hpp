@@ -113,21 +113,32 @@ __device__ __forceinline__ bool pcg_work(const int* work, int b, int& req, int& 
     return true;
 }
 
-// Per-condition sums of up to 4 partial arrays, in a fixed order: wave w handles
-// conditions w, w + NW, ...; lanes stride over the chunk slots, then a fixed shuffle tree.
-// Results land in out[q][c] (shared memory), valid after the trailing barrier.
+// Per-condition sums of up to NQ partial arrays, in a fixed order: wave w handles
+// conditions w, w + NW, ...; lane l adds slots l, l + 64, ... to a zero start, then a fixed
+// shuffle tree.  The loads of one round of 64 slots go out for all arrays together, so a
+// condition waits for one memory latency per round, not one per array.  Results land in
+// out[q][c] (shared memory), valid after the trailing barrier.
 template <int NT, int NQ>
 __device__ __forceinline__ void cond_sums(int n_cond, const int (&chunks)[NQ], const double* const (&src)[NQ],
                                           double (*out)[GAP_MAXC])
 {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int kmax = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) kmax = chunks[q] > kmax ? chunks[q] : kmax;
     for (int c = w; c < n_cond; c += NW) {
         double v[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            v[q] = 0.0;
-            for (int k = lane; k < chunks[q]; k += 64) v[q] += src[q][c * chunks[q] + k];
+        for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+        for (int k0 = 0; k0 < kmax; k0 += 64) {
+            const int k = k0 + lane;
+            double x[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) x[q] = k < chunks[q] ? src[q][c * chunks[q] + k] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (k < chunks[q]) v[q] += x[q];
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
