@@ -198,10 +198,11 @@ SERVE_COUNTS = {0.5: 48, 0.8: 96, 1.0: 96, 1.2: 48}   # requests per load
 SERVE_BULK = (2048, 1024)        # requests of this many cells or more run in the bulk lane
 SERVE_TARGETS = (2, 1)           # strip-kernel workgroups per CU: bulk lane, fast lane
 SERVE_FAST_CAP = 4 * 9 * 512 * 256   # fast lane: smallest first while the work fits four 512x256 systems
+SERVE_BULK_ITERS = 32            # PCG iterations per step of the bulk lane (the fast lane takes 32)
 
 
 def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=48, targets=SERVE_TARGETS,
-                fast_cap=SERVE_FAST_CAP):
+                fast_cap=SERVE_FAST_CAP, bulk_iters=SERVE_BULK_ITERS):
     """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
     128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server runs two
     lanes over one HBM budget: 2048x1024 requests in a bulk batch, one after another in arrival
@@ -228,7 +229,7 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     bulk_work = 9 * SERVE_BULK[0] * SERVE_BULK[1]
     streams = (torch.cuda.Stream(dev), torch.cuda.Stream(dev))
     # both servers keep their handles (and the batches their graphs) across the runs below
-    bulk = BatchBackend(iterations_per_step=32, stream=streams[0], wg_per_cu=targets[0])
+    bulk = BatchBackend(iterations_per_step=bulk_iters, stream=streams[0], wg_per_cu=targets[0])
     fast = BatchBackend(iterations_per_step=32, stream=streams[1], wg_per_cu=targets[1])
     fifo_pool = HandlePool(dev)
 
@@ -281,7 +282,8 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     return {"capacity_requests": capacity_count, "capacity_batched_per_s": round(capacity, 3), "handles": handles,
             "capacity_one_at_a_time_joint_per_s": round(fifo_capacity, 3),
             "lanes": {"bulk_cells_min": list(SERVE_BULK), "wg_per_cu_bulk": targets[0], "wg_per_cu_fast": targets[1],
-                      "fast_cap_dofs": fast_cap, "iterations_per_step": 32},
+                      "iterations_per_step_bulk": bulk_iters, "iterations_per_step_fast": 32,
+                      "fast_cap_dofs": fast_cap},
             "hbm_budget_bytes": budget, "runs": runs}
 
 
@@ -439,6 +441,8 @@ def main():
     ap.add_argument("--serve-targets", default=None,
                     help="strip-kernel workgroups per CU of the serving lanes, 'bulk,fast' (default %d,%d)"
                     % SERVE_TARGETS)
+    ap.add_argument("--serve-bulk-iters", type=int, default=SERVE_BULK_ITERS,
+                    help="PCG iterations per step of the serving bulk lane")
     ap.add_argument("--timing-period", type=int, default=TIMING_PERIOD,
                     help="time one iteration-kernel launch in this many inside the timed region (odd)")
     args = ap.parse_args()
@@ -717,7 +721,7 @@ def main():
     serving = None
     if not args.no_serving:
         targets = tuple(int(x) for x in args.serve_targets.split(",")) if args.serve_targets else SERVE_TARGETS
-        serving = run_serving(torch, JointGapSolver, dev, targets=targets)
+        serving = run_serving(torch, JointGapSolver, dev, targets=targets, bulk_iters=args.serve_bulk_iters)
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint_vs_fd(torch, G, JointGapSolver, dev)
