@@ -199,10 +199,13 @@ SERVE_BULK = (2048, 1024)        # requests of this many cells or more run in th
 SERVE_TARGETS = (2, 1)           # strip-kernel workgroups per CU: bulk lane, fast lane
 SERVE_FAST_CAP = 4 * 9 * 512 * 256   # fast lane: smallest first while the work fits four 512x256 systems
 SERVE_BULK_ITERS = 32            # PCG iterations per step of the bulk lane (the fast lane takes 32)
+SERVE_YIELD_WORK = None          # fast-lane requests of more work yield while bulk work runs (None: never)
+SERVE_MAX_YIELD_S = 1.0          # ... for at most this long after admission
 
 
 def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=48, targets=SERVE_TARGETS,
-                fast_cap=SERVE_FAST_CAP, bulk_iters=SERVE_BULK_ITERS):
+                fast_cap=SERVE_FAST_CAP, bulk_iters=SERVE_BULK_ITERS, yield_work=SERVE_YIELD_WORK,
+                max_yield_s=SERVE_MAX_YIELD_S):
     """The served stream: Poisson arrivals of joint solves on grids drawn uniformly from
     128x64 ... 2048x1024, smooth or with 0-200 random dimples.  The batched server runs two
     lanes over one HBM budget: 2048x1024 requests in a bulk batch, one after another in arrival
@@ -234,7 +237,8 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
     fifo_pool = HandlePool(dev)
 
     def batched(reqs):
-        return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work, fast_cap=fast_cap).run(reqs)
+        return LaneServer(bulk, fast, budget_bytes=budget, bulk_work=bulk_work, fast_cap=fast_cap,
+                          yield_work=yield_work, max_yield_s=max_yield_s).run(reqs)
 
     def fifo(reqs):
         return run_fifo(reqs, pool=fifo_pool)
@@ -283,6 +287,7 @@ def run_serving(torch, JointGapSolver, dev, seed=0, counts=None, capacity_count=
             "capacity_one_at_a_time_joint_per_s": round(fifo_capacity, 3),
             "lanes": {"bulk_cells_min": list(SERVE_BULK), "wg_per_cu_bulk": targets[0], "wg_per_cu_fast": targets[1],
                       "iterations_per_step_bulk": bulk_iters, "iterations_per_step_fast": 32,
+                      "yield_work": yield_work, "max_yield_s": max_yield_s if yield_work else None,
                       "fast_cap_dofs": fast_cap},
             "hbm_budget_bytes": budget, "runs": runs}
 
@@ -443,6 +448,8 @@ def main():
                     % SERVE_TARGETS)
     ap.add_argument("--serve-bulk-iters", type=int, default=SERVE_BULK_ITERS,
                     help="PCG iterations per step of the serving bulk lane")
+    ap.add_argument("--serve-yield-work", type=int, default=SERVE_YIELD_WORK,
+                    help="fast-lane requests of more condition-DOFs yield while bulk work runs")
     ap.add_argument("--timing-period", type=int, default=TIMING_PERIOD,
                     help="time one iteration-kernel launch in this many inside the timed region (odd)")
     args = ap.parse_args()
@@ -721,7 +728,8 @@ def main():
     serving = None
     if not args.no_serving:
         targets = tuple(int(x) for x in args.serve_targets.split(",")) if args.serve_targets else SERVE_TARGETS
-        serving = run_serving(torch, JointGapSolver, dev, targets=targets, bulk_iters=args.serve_bulk_iters)
+        serving = run_serving(torch, JointGapSolver, dev, targets=targets, bulk_iters=args.serve_bulk_iters,
+                              yield_work=args.serve_yield_work)
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint_vs_fd(torch, G, JointGapSolver, dev)

@@ -236,7 +236,7 @@ class GapServer:
     """Event loop: admit by arrival order and budget, step the batch, retire finished work."""
 
     def __init__(self, backend, budget_bytes, clock=None, work_cap=None, order="smallest", admission=None,
-                 poll_s=5e-4):
+                 poll_s=5e-4, hold_if=None, max_hold_s=float("inf")):
         if order not in ("smallest", "oldest"):
             raise ValueError(f"unknown order {order!r}")
         self.backend = backend
@@ -245,21 +245,29 @@ class GapServer:
         self.clock = clock or WallClock()
         self.work_cap = work_cap
         self.order = order
+        # hold_if(request): the request yields for now (it does not advance), but never for
+        # more than max_hold_s after its admission
+        self.hold_if = hold_if
+        self.max_hold_s = max_hold_s
 
     def _schedule(self):
-        """Requests in scheduling order while the summed work fits the cap; the first always
-        advances."""
+        """Requests in scheduling order while the summed work fits the cap (no cap: all); the
+        first always advances, except those that yield.  Returns whether any request advances."""
         if self.order == "smallest":
             key = lambda q: (self.backend.work(q.case), q.arrival, q.rid)
         else:
             key = lambda q: (q.arrival, q.rid)
+        now = self.clock.now()
         chosen, total = [], 0
         for r in sorted(self.backend.active(), key=key):
+            if self.hold_if is not None and now - r.admitted < self.max_hold_s and self.hold_if(r):
+                continue
             w = self.backend.work(r.case)
-            if not chosen or total + w <= self.work_cap:
+            if not chosen or self.work_cap is None or total + w <= self.work_cap:
                 chosen.append(r)
                 total += w
         self.backend.select(chosen)
+        return bool(chosen)
 
     def run(self, requests: List[Request]):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -284,8 +292,9 @@ class GapServer:
                 elif pending:
                     self.clock.sleep_until(pending[0].arrival)
                 continue
-            if self.work_cap is not None:
-                self._schedule()
+            if (self.work_cap is not None or self.hold_if is not None) and not self._schedule():
+                self.clock.sleep_until(self.clock.now() + self.poll_s)   # every active request yields
+                continue
             for r in self.backend.step():
                 r.finished = self.clock.now()
                 self.admission.release(r.nbytes)
@@ -299,17 +308,24 @@ class LaneServer:
     DOFs per iteration) go to the bulk lane, which runs them in arrival order, advancing
     together only those that fit ``bulk_cap`` (default: bulk_work); the others go to the fast
     lane, where every admitted request advances in every step, or, with ``fast_cap``, the
-    smallest ones first while their work fits the cap."""
+    smallest ones first while their work fits the cap.  With ``yield_work``, a fast-lane
+    request of more work than that does not advance while the bulk lane has work, for at most
+    ``max_yield_s`` after its admission: the bulk requests, which set the tail, then keep the
+    device's bandwidth to themselves, and the small requests still run beside them."""
 
-    def __init__(self, bulk, fast, budget_bytes, bulk_work, clock=None, bulk_cap=None, fast_cap=None):
+    def __init__(self, bulk, fast, budget_bytes, bulk_work, clock=None, bulk_cap=None, fast_cap=None,
+                 yield_work=None, max_yield_s=float("inf")):
         self.admission = AdmissionController(budget_bytes)
         self.clock = clock or WallClock()
         self.bulk_work = int(bulk_work)
+        hold_if = None
+        if yield_work is not None:
+            hold_if = lambda r: (not bulk.idle()) and fast.work(r.case) > yield_work
         self.lanes = {
             "bulk": GapServer(bulk, budget_bytes, clock=self.clock, work_cap=bulk_cap or self.bulk_work,
                               order="oldest", admission=self.admission),
             "fast": GapServer(fast, budget_bytes, clock=self.clock, work_cap=fast_cap, order="smallest",
-                              admission=self.admission),
+                              admission=self.admission, hold_if=hold_if, max_hold_s=max_yield_s),
         }
 
     def lane_of(self, req):

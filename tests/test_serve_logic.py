@@ -222,6 +222,24 @@ def test_lanes_share_one_budget_and_wait_for_each_other():
         assert a1 >= f0                            # never two on the device together
 
 
+def test_large_fast_requests_yield_to_bulk_work_within_a_bound():
+    bulk, fast = SleepBackend(0.003), SleepBackend(0.001)
+    srv = LaneServer(bulk, fast, budget_bytes=1000, bulk_work=4, fast_cap=10, yield_work=1)
+    # bulk request 0 runs about 0.09 s; fast request 1 (work 2) yields while it runs, the
+    # small request 2 (work 1) does not
+    rs = [req(0, 0.0, 100, 30, work=4), req(1, 0.005, 10, 3, work=2), req(2, 0.005, 10, 3, work=1)]
+    done = {r.rid: r for r in srv.run(rs)}
+    assert done[2].finished < done[0].finished
+    assert done[1].finished >= done[0].finished
+    # with a bound on the wait, the large request moves before the bulk work ends
+    bulk, fast = SleepBackend(0.003), SleepBackend(0.001)
+    srv = LaneServer(bulk, fast, budget_bytes=1000, bulk_work=4, fast_cap=10, yield_work=1, max_yield_s=0.02)
+    rs = [req(0, 0.0, 100, 30, work=4), req(1, 0.005, 10, 3, work=2)]
+    done = {r.rid: r for r in srv.run(rs)}
+    assert done[1].finished < done[0].finished
+    assert srv.admission.used == 0 and srv.admission.active == 0
+
+
 def test_a_failing_lane_raises_in_the_caller():
     bulk, fast = SleepBackend(0.001), SleepBackend(0.001)
     srv = LaneServer(bulk, fast, budget_bytes=50, bulk_work=4)
